@@ -1,0 +1,244 @@
+/*
+ * fg.h -- C ABI of the frontier graph library (libfg.so) for MI355X (gfx950).
+ *
+ * The library implements the single-GPU data-parallel path of frontier-
+ * centric graph traversal from "Multi-GPU Graph Analytics" (Pan, Wang, Wu,
+ * Yang, Owens): the advance and filter operators (Sec. II-B), breadth-first
+ * search built from them (Alg. 1), direction-optimizing BFS with the
+ * vertex-parallel early-exit pull step and the inexpensive direction rule
+ * (Sec. VI-A, Alg. 2), advance+filter kernel fusion (Sec. VI-C), integer
+ * single-source shortest paths (Table I), the per-iteration split/package
+ * step of the multi-GPU framework (Sec. III-B), and a 64-lane batched BFS.
+ *
+ * The calls follow the problem statement of the paper's framework: load a
+ * CSR graph, set the source, run the primitive, read depths / distances /
+ * predecessors.
+ *
+ * Conventions shared by every call
+ *  - All functions return fg_status: FG_OK (0) or a negative error code.
+ *    They never throw.  fg_last_error() returns a thread-local message that
+ *    describes the last error of the calling thread.
+ *  - Argument errors are detected synchronously, before any work is
+ *    enqueued; on error no output is written.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t, NULL = the
+ *    null stream).  Outputs are valid after the stream has been synchronised.
+ *    Device-side failures (e.g. FG_EOVERFLOW) are reported in the `status`
+ *    field of the device-resident fg_run_stats of that call.
+ *  - Pointers documented as "device" must be device memory of the current
+ *    HIP device (e.g. torch tensor data_ptr()).  Caller owns every buffer it
+ *    passes; the library never frees caller memory.
+ *  - Vertex ids are int32 in [0, n); edge offsets are int32 (m < 2^31).
+ *  - A workspace may not be used by two calls that overlap in time.
+ */
+#ifndef FG_H
+#define FG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fg_status;
+
+#define FG_OK 0
+#define FG_EINVAL (-1)       /* bad argument or malformed CSR               */
+#define FG_ENOMEM (-2)       /* workspace too small / allocation failed      */
+#define FG_EDEVICE (-3)      /* HIP runtime error or device-side time-out    */
+#define FG_EOVERFLOW (-4)    /* an output buffer's capacity was exceeded     */
+#define FG_EUNSUPPORTED (-5) /* valid request the graph cannot serve         */
+
+/* Thread-local description of the last error (never NULL). */
+const char* fg_last_error(void);
+
+/* Library version, "major.minor.patch". */
+const char* fg_version(void);
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct fg_graph fg_graph;
+
+#define FG_DEVICE_PTRS 1u /* the CSR arrays are device pointers              */
+#define FG_BORROW 2u      /* with FG_DEVICE_PTRS: use the arrays in place;
+                             the caller keeps them alive until destroy        */
+#define FG_VALIDATE 4u    /* check row_offsets[0]==0, monotone offsets,
+                             row_offsets[n]==m, 0<=col<n                       */
+#define FG_SYMMETRIC 8u   /* the CSR is undirected (every u->v has v->u with
+                             the same weight).  Required for the pull step.
+                             With FG_VALIDATE the claim is checked as well,
+                             which additionally requires strictly ascending
+                             rows.                                           */
+
+/*
+ * Load a CSR graph (Sec. III-B: the framework's graph initialisation; the
+ * paper's inputs are undirected, without self-loops or duplicate edges,
+ * Sec. VII-A).  row_offsets: int32[n+1]; col_idx: int32[m]; weights:
+ * uint32[m] aligned with col_idx, or NULL (required only by fg_sssp).
+ * Without FG_DEVICE_PTRS the arrays are host memory and are copied.
+ * Errors: FG_EINVAL (n < 1, m < 0, m >= 2^31, NULL arrays, failed
+ * validation), FG_ENOMEM, FG_EDEVICE.  On success *out owns a graph that
+ * is immutable and may be used from any stream of the same device.
+ */
+fg_status fg_graph_create_csr(int32_t n, int64_t m, const int32_t* row_offsets,
+                              const int32_t* col_idx, const uint32_t* weights,
+                              uint32_t flags, void* stream, fg_graph** out);
+
+/* Release a graph (waits for the device).  NULL is accepted. */
+fg_status fg_graph_destroy(fg_graph* g);
+
+typedef struct {
+  int32_t n;
+  int32_t has_weights;
+  int64_t m;
+  int32_t symmetric;
+  int32_t max_degree;
+  int32_t nonzero_degree; /* vertices with at least one edge              */
+  int32_t device;
+  int64_t resident_bytes; /* device bytes held by the graph object          */
+} fg_graph_info_t;
+
+fg_status fg_graph_info(const fg_graph* g, fg_graph_info_t* info);
+
+/* -------------------------------------------------------------- workspace */
+
+#define FG_PRIM_BFS 0          /* fg_bfs, modes FG_MODE_DO / FG_MODE_PUSH      */
+#define FG_PRIM_BFS_UNFUSED 1  /* fg_bfs, mode FG_MODE_PUSH_UNFUSED           */
+#define FG_PRIM_SSSP 2         /* fg_sssp                                      */
+#define FG_PRIM_MSBFS 3        /* fg_msbfs_* with `lanes` <= 64                */
+
+/*
+ * Bytes of device workspace a call needs (just-enough sizing, Sec. VI-B:
+ * frontier queues are bounded by |V_i|; the unfused advance additionally
+ * needs an edge frontier bounded by |E_i|).  Returns 0 for bad arguments.
+ */
+size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32_t lanes);
+
+/* --------------------------------------------------------------- run stats */
+
+#define FG_TRACE_MAX 64
+
+/*
+ * Device-resident record of one traversal, written by the library when the
+ * caller passes a device pointer to it.  The per-iteration arrays hold the
+ * first FG_TRACE_MAX iterations.
+ */
+typedef struct {
+  int32_t status;           /* FG_OK or a device-side error code             */
+  int32_t iterations;       /* iterations run (one per non-empty level)      */
+  int64_t reached;          /* vertices with a finite depth / distance       */
+  int64_t edges_inspected;  /* CSR entries read by advance / pull steps      */
+  int32_t direction_switches;
+  int32_t grid_blocks;      /* workgroups of the persistent launch           */
+  int8_t dir[FG_TRACE_MAX]; /* 0 = push (forward), 1 = pull (backward)       */
+  int64_t frontier[FG_TRACE_MAX];  /* input frontier size |Q| per iteration */
+  int64_t inspected[FG_TRACE_MAX]; /* CSR entries read per iteration         */
+} fg_run_stats;
+
+/* Copy a device-resident fg_run_stats into host memory (synchronises `stream`). */
+fg_status fg_stats_read(const fg_run_stats* dev_stats, fg_run_stats* host,
+                        void* stream);
+
+/* --------------------------------------------------------------------- BFS */
+
+#define FG_MODE_DO 0            /* direction-optimizing (Sec. VI-A)            */
+#define FG_MODE_PUSH 1          /* fused advance+filter only (Sec. VI-C)       */
+#define FG_MODE_PUSH_UNFUSED 2  /* separate advance and filter kernels (Alg. 1) */
+
+typedef struct {
+  int32_t mode;        /* FG_MODE_*                                          */
+  uint32_t do_a_num;   /* forward->backward when FV > (num/den) * BV         */
+  uint32_t do_a_den;   /*   (Sec. VI-A do_a; default 1/100)                   */
+  uint32_t do_b_num;   /* backward->forward when FV < (num/den) * BV         */
+  uint32_t do_b_den;   /*   (Sec. VI-A do_b; default 1/10)                    */
+  int32_t small_frontier; /* single-workgroup levels while |Q| <= this (0 = default) */
+  int32_t small_edges;    /* ... and sum of degrees <= this (0 = default)     */
+  int32_t big_degree;     /* push: vertices of at least this degree are
+                             expanded by the whole grid (0 = default)         */
+  int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
+} fg_bfs_opts;
+
+/* Fill *opts with the defaults (DO mode, do_a = 1/100, do_b = 1/10). */
+void fg_bfs_opts_default(fg_bfs_opts* opts);
+
+/*
+ * Breadth-first search from `src` (Alg. 1; Alg. 2 and Sec. VI-A in
+ * FG_MODE_DO).  depth: device int32[n], receives the hop distance from src
+ * or -1.  parent: device int32[n] or NULL; receives a BFS-tree predecessor
+ * (parent[src] = src, -1 if unreached); which of several valid parents is
+ * chosen may differ between runs.  ws: device workspace of at least
+ * fg_workspace_bytes(g, FG_PRIM_BFS or FG_PRIM_BFS_UNFUSED, 0) bytes.
+ * stats: device fg_run_stats* or NULL.  opts may be NULL (defaults).
+ * Errors: FG_EINVAL (src out of range, NULL depth/ws, bad opts),
+ * FG_ENOMEM (ws_bytes too small; the required size is in the message),
+ * FG_EUNSUPPORTED (FG_MODE_DO on a graph without FG_SYMMETRIC), FG_EDEVICE.
+ */
+fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
+                 void* ws, size_t ws_bytes, int32_t* depth, int32_t* parent,
+                 fg_run_stats* stats, void* stream);
+
+/* ----------------------------------------------------------- BFS operators */
+
+/*
+ * Advance (Sec. II-B): the edge frontier of `frontier` (device int32[len]).
+ * For frontier entry i = 0..len-1 and its CSR neighbours j in order, writes
+ * out_dst[k] = neighbour and out_src[k] = frontier[i] at k = sum of the
+ * degrees of entries 0..i-1 plus j (a deterministic layout).  The total is
+ * written to *out_len (device int64).  If it exceeds `capacity`, nothing
+ * beyond capacity is written and the call's stats status (if any) and
+ * *out_len report the needed size; the host-visible return is FG_OK (the
+ * size is only known on the device).  ws: device workspace of at least
+ * fg_workspace_bytes(g, FG_PRIM_BFS_UNFUSED, 0) bytes.
+ */
+fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int32_t len,
+                     int32_t* out_dst, int32_t* out_src, int64_t capacity,
+                     int64_t* out_len, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Filter (Sec. II-B, with the computation step fused): for each edge-
+ * frontier entry k (device arrays dst/src of length len), if vertex dst[k]
+ * is not yet set in `visited` (device uint32 bitmask of ceil(n/32) words,
+ * bit v%32 of word v/32) it is atomically marked, depth[dst] = iter + 1,
+ * parent[dst] = src[k] (parent may be NULL) and dst is appended to out_q
+ * (device int32, capacity n).  Each vertex is appended at most once; the
+ * order of out_q is unspecified.  *out_len (device int32) receives the count.
+ */
+fg_status fg_filter(const fg_graph* g, const int32_t* dst, const int32_t* src,
+                    int64_t len, uint32_t* visited, int32_t iter, int32_t* depth,
+                    int32_t* parent, int32_t* out_q, int32_t* out_len,
+                    void* stream);
+
+/*
+ * Backward (pull) step of one iteration (Sec. VI-A): every vertex v with
+ * degree > 0 whose `visited` bit is clear scans its CSR row in order and
+ * stops at the first neighbour u whose bit is set in `frontier_bits`
+ * (level `iter`).  Then depth[v] = iter+1, parent[v] = u (parent may be
+ * NULL), v's bit is set in `visited` and in `next_bits`, and v is appended
+ * to out_q.  Every word of next_bits is overwritten.  Bitmaps are device
+ * uint64 arrays of ceil(n/64) words (bit v%64 of word v/64).  *out_len
+ * (device int32) receives the number of new vertices and *inspected (device
+ * int64, may be NULL) the number of CSR entries read.
+ */
+fg_status fg_pull_step(const fg_graph* g, const uint64_t* frontier_bits,
+                       uint64_t* visited, uint64_t* next_bits, int32_t iter,
+                       int32_t* depth, int32_t* parent, int32_t* out_q,
+                       int32_t* out_len, int64_t* inspected, void* stream);
+
+/*
+ * Frontier conversions (Sec. VI-A: the newly discovered list gives a
+ * direction-independent view).  queue -> bitmap ORs the bits of
+ * queue[0..len) into `bits` (device uint64[ceil(n/64)], not cleared first).
+ * bitmap -> queue lists the set bits in ascending order into out_q and
+ * writes the count to *out_len (device int32).
+ */
+fg_status fg_queue_to_bitmap(const fg_graph* g, const int32_t* queue,
+                             int32_t len, uint64_t* bits, void* stream);
+fg_status fg_bitmap_to_queue(const fg_graph* g, const uint64_t* bits,
+                             int32_t* out_q, int32_t* out_len, void* ws,
+                             size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FG_H */

@@ -1,0 +1,268 @@
+"""MI355X frontier graph traversal: Python binding of libfg.so.
+
+Argument marshalling only: every step of the traversal runs in the HIP
+kernels of ``libfg.so`` (see ``include/fg.h`` for the C ABI).  PyTorch
+provides device memory and streams.  Importing this package never falls
+back to a CPU implementation: if the library is missing, calls raise.
+"""
+import ctypes
+import os
+
+import torch  # loaded first so libfg.so binds to the HIP runtime torch uses
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfg.so")
+
+FG_OK, FG_EINVAL, FG_ENOMEM, FG_EDEVICE, FG_EOVERFLOW, FG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FG_DEVICE_PTRS, FG_BORROW, FG_VALIDATE, FG_SYMMETRIC = 1, 2, 4, 8
+FG_PRIM_BFS, FG_PRIM_BFS_UNFUSED, FG_PRIM_SSSP, FG_PRIM_MSBFS = 0, 1, 2, 3
+FG_MODE_DO, FG_MODE_PUSH, FG_MODE_PUSH_UNFUSED = 0, 1, 2
+FG_TRACE_MAX = 64
+PUSH, PULL = 0, 1
+
+
+class FGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fg status {status}: {msg}")
+        self.status = status
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("reached", ctypes.c_int64),
+        ("edges_inspected", ctypes.c_int64),
+        ("direction_switches", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
+        ("dir", ctypes.c_int8 * FG_TRACE_MAX),
+        ("frontier", ctypes.c_int64 * FG_TRACE_MAX),
+        ("inspected", ctypes.c_int64 * FG_TRACE_MAX),
+    ]
+
+    def trace(self):
+        k = min(self.iterations, FG_TRACE_MAX)
+        return (list(self.dir[:k]), list(self.frontier[:k]), list(self.inspected[:k]))
+
+
+class BfsOpts(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32),
+        ("do_a_num", ctypes.c_uint32),
+        ("do_a_den", ctypes.c_uint32),
+        ("do_b_num", ctypes.c_uint32),
+        ("do_b_den", ctypes.c_uint32),
+        ("small_frontier", ctypes.c_int32),
+        ("small_edges", ctypes.c_int32),
+        ("big_degree", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+    ]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("has_weights", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("symmetric", ctypes.c_int32),
+        ("max_degree", ctypes.c_int32),
+        ("nonzero_degree", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("resident_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+# Every symbol declared in include/fg.h, with (restype, argtypes).
+_P = ctypes.c_void_p
+_I32, _I64, _U32, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+SIGNATURES = {
+    "fg_last_error": (ctypes.c_char_p, []),
+    "fg_version": (ctypes.c_char_p, []),
+    "fg_graph_create_csr": (_I32, [_I32, _I64, _P, _P, _P, _U32, _P, ctypes.POINTER(_P)]),
+    "fg_graph_destroy": (_I32, [_P]),
+    "fg_graph_info": (_I32, [_P, ctypes.POINTER(GraphInfo)]),
+    "fg_workspace_bytes": (_SZ, [_P, _I32, _I32]),
+    "fg_stats_read": (_I32, [_P, ctypes.POINTER(RunStats), _P]),
+    "fg_bfs_opts_default": (None, [ctypes.POINTER(BfsOpts)]),
+    "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
+    "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
+    "fg_queue_to_bitmap": (_I32, [_P, _P, _I32, _P, _P]),
+    "fg_bitmap_to_queue": (_I32, [_P, _P, _P, _P, _P, _SZ, _P]),
+}
+
+
+def lib():
+    """The loaded libfg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != FG_OK:
+        raise FGError(status, lib().fg_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def last_error():
+    return lib().fg_last_error().decode()
+
+
+def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, small_edges=0,
+             big_degree=0, blocks_per_cu=0):
+    o = BfsOpts()
+    lib().fg_bfs_opts_default(ctypes.byref(o))
+    o.mode = mode
+    o.do_a_num, o.do_a_den = do_a
+    o.do_b_num, o.do_b_den = do_b
+    o.small_frontier = small_frontier
+    o.small_edges = small_edges
+    o.big_degree = big_degree
+    o.blocks_per_cu = blocks_per_cu
+    return o
+
+
+class Graph:
+    """A CSR graph resident on the current GPU (fg_graph_create_csr)."""
+
+    def __init__(self, row_offsets, col_idx, weights=None, symmetric=True, validate=True,
+                 device="cuda"):
+        L = lib()
+        off = torch.as_tensor(row_offsets, dtype=torch.int32).to(device).contiguous()
+        col = torch.as_tensor(col_idx, dtype=torch.int32).to(device).contiguous()
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(weights).view(torch.int32) if isinstance(weights, torch.Tensor) \
+                else torch.from_numpy(weights.view("int32"))
+            w = w.to(device).contiguous()
+        self.n = off.numel() - 1
+        self.m = col.numel()
+        # the library keeps its own copies (no FG_BORROW)
+        flags = FG_DEVICE_PTRS | (FG_VALIDATE if validate else 0) | (FG_SYMMETRIC if symmetric else 0)
+        h = ctypes.c_void_p()
+        _check(L.fg_graph_create_csr(self.n, self.m, _ptr(off), _ptr(col) if self.m else _ptr(col),
+                                     _ptr(w), flags, _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.off = off
+        self.col = col
+        self.w = w
+        self._ws = {}
+
+    def info(self):
+        i = GraphInfo()
+        _check(lib().fg_graph_info(self.handle, ctypes.byref(i)))
+        return i
+
+    def workspace_bytes(self, prim=FG_PRIM_BFS, lanes=0):
+        return int(lib().fg_workspace_bytes(self.handle, prim, lanes))
+
+    def workspace(self, prim=FG_PRIM_BFS, lanes=0):
+        """A cached device workspace for `prim` (one per primitive)."""
+        key = (prim, lanes)
+        if key not in self._ws:
+            nb = self.workspace_bytes(prim, lanes)
+            self._ws[key] = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.off.device)
+        return self._ws[key]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fg_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def new_stats(device="cuda"):
+    return torch.zeros(ctypes.sizeof(RunStats), dtype=torch.uint8, device=device)
+
+
+def read_stats(stats_dev, stream=None):
+    s = RunStats()
+    _check(lib().fg_stats_read(_ptr(stats_dev), ctypes.byref(s), _stream(stream)))
+    return s
+
+
+def bfs_into(g, src, depth, parent=None, opts=None, ws=None, stats=None, stream=None):
+    """Enqueue fg_bfs on `stream`; outputs are caller-provided device tensors."""
+    prim = FG_PRIM_BFS_UNFUSED if (opts is not None and opts.mode == FG_MODE_PUSH_UNFUSED) \
+        else FG_PRIM_BFS
+    ws = ws if ws is not None else g.workspace(prim)
+    _check(lib().fg_bfs(g.handle, int(src), ctypes.byref(opts) if opts is not None else None,
+                        _ptr(ws), ws.numel(), _ptr(depth), _ptr(parent), _ptr(stats),
+                        _stream(stream)))
+
+
+def bfs(g, src, mode=FG_MODE_DO, parents=True, opts=None, **kw):
+    """Run one BFS and return (depth, parent or None, RunStats) after a sync."""
+    dev = g.off.device
+    depth = torch.empty(g.n, dtype=torch.int32, device=dev)
+    parent = torch.empty(g.n, dtype=torch.int32, device=dev) if parents else None
+    stats = new_stats(dev)
+    o = opts if opts is not None else bfs_opts(mode=mode, **kw)
+    bfs_into(g, src, depth, parent, o, stats=stats)
+    st = read_stats(stats)
+    return depth, parent, st
+
+
+def advance(g, frontier, capacity=None, ws=None):
+    """Edge frontier (dst, src, total) of `frontier` (fg_advance)."""
+    dev = g.off.device
+    cap = g.m if capacity is None else capacity
+    dst = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    out_len = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = ws if ws is not None else g.workspace(FG_PRIM_BFS_UNFUSED)
+    _check(lib().fg_advance(g.handle, _ptr(frontier), frontier.numel(), _ptr(dst), _ptr(src),
+                            cap, _ptr(out_len), _ptr(ws), ws.numel(), _stream()))
+    return dst, src, out_len
+
+
+def filter_(g, dst, src, length, visited, it, depth, parent, out_q, out_len):
+    _check(lib().fg_filter(g.handle, _ptr(dst), _ptr(src), int(length), _ptr(visited), int(it),
+                           _ptr(depth), _ptr(parent), _ptr(out_q), _ptr(out_len), _stream()))
+
+
+def pull_step(g, frontier_bits, visited, next_bits, it, depth, parent, out_q, out_len,
+              inspected=None):
+    _check(lib().fg_pull_step(g.handle, _ptr(frontier_bits), _ptr(visited), _ptr(next_bits),
+                              int(it), _ptr(depth), _ptr(parent), _ptr(out_q), _ptr(out_len),
+                              _ptr(inspected), _stream()))
+
+
+def queue_to_bitmap(g, queue, length, bits):
+    _check(lib().fg_queue_to_bitmap(g.handle, _ptr(queue), int(length), _ptr(bits), _stream()))
+
+
+def bitmap_to_queue(g, bits, out_q, out_len, ws=None):
+    ws = ws if ws is not None else g.workspace(FG_PRIM_BFS_UNFUSED)
+    _check(lib().fg_bitmap_to_queue(g.handle, _ptr(bits), _ptr(out_q), _ptr(out_len), _ptr(ws),
+                                    ws.numel(), _stream()))

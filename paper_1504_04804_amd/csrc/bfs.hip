@@ -1,0 +1,801 @@
+// Breadth-first search on one GPU: fused advance+filter push iterations
+// (Sec. II-B operators, Alg. 1, kernel fusion of Sec. VI-C) and the
+// direction-optimizing variant with the vertex-parallel early-exit pull
+// step and the inexpensive direction rule (Sec. VI-A, Alg. 2).
+//
+// The whole traversal runs in one cooperative (co-resident) launch: every
+// iteration's direction is decided on the device from counters the
+// iteration before produced, so the host is not involved between
+// iterations.  Levels whose frontier is small are run by workgroup 0 alone
+// (no grid barrier at all); larger levels use the whole grid and one grid
+// barrier per iteration (two when very high degree vertices are present).
+//
+// Data layout in HBM (all owned by the caller's workspace, 256-B aligned):
+//   visited   2 x uint64[ceil(n/64)]  current / next visited bitmap
+//   queue     2 x int32[n]            input / output vertex frontier
+//   big       int32[n]                push vertices of very high degree
+//   control   counters, barrier, hand-back state of the small-frontier mode
+#include <string.h>
+
+#include "fg_common.h"
+
+namespace {
+
+constexpr int PB = 1024;          // persistent workgroup size
+constexpr int PWAVES = PB / FG_WAVE;
+constexpr int BIG_BATCH = 2048;   // very-high-degree vertices per LDS batch
+constexpr int DIR_PUSH = 0, DIR_PULL = 1;
+
+constexpr int32_t DEF_SMALL_Q = 1024;
+constexpr int64_t DEF_SMALL_E = 2048;
+constexpr int32_t DEF_BIG_DEG = 1024;
+
+typedef unsigned __int128 u128;
+typedef unsigned long long ull;
+
+// One 256-byte line per counter so concurrent atomics do not share a line.
+struct alignas(256) Line64 {
+  ull v;
+  ull pad[31];
+};
+
+// Counters of one iteration parity.  Iteration k appends through slot k&1;
+// every workgroup reads the slot right after the iteration's last grid
+// barrier, before it can reach iteration k+2, the next user of the slot, so
+// monotone counters never need resetting.
+struct CtrSlot {
+  Line64 q;      // vertices discovered
+  Line64 big;    // entries appended to the big list
+  Line64 insp;   // CSR entries read
+  Line64 chunk;  // frontier chunks handed out (dynamic balance)
+};
+
+struct alignas(256) BfsCtl {
+  uint32_t arrive;          // grid barrier arrivals (monotone)
+  uint32_t pad0[63];
+  uint32_t abort_flag;      // set when a wait exceeded its bound
+  uint32_t pad1[63];
+  uint32_t sm_signal;       // small-frontier hand-backs (monotone)
+  uint32_t pad2[63];
+  Line64 aux;               // entries written by bitmap -> queue conversion
+  CtrSlot slot[2];
+  // state published by workgroup 0 when a small-frontier episode ends
+  int32_t pub_k, pub_dir, pub_prevdir, pub_switched, pub_qsel, pub_force;
+  int64_t pub_qlen, pub_p, pub_insp_sum;
+  int32_t pub_switches;
+};
+
+struct BfsParams {
+  const int32_t* __restrict__ off;
+  const int32_t* __restrict__ col;
+  const uint64_t* __restrict__ nz;
+  int32_t n;
+  int32_t nwords;
+  int64_t m;
+  int32_t src;
+  int32_t mode;
+  int32_t* depth;
+  int32_t* parent;
+  uint64_t* vis[2];
+  int32_t* q[2];
+  int32_t* big;
+  BfsCtl* ctl;
+  fg_run_stats* stats;
+  uint32_t a_num, a_den, b_num, b_den;
+  int32_t small_q;
+  int64_t small_e;
+  int32_t big_deg;
+};
+
+// Per-iteration state, identical in every workgroup.
+struct St {
+  int32_t k;         // iteration (= depth of the input frontier)
+  int32_t dir;       // direction of iteration k
+  int32_t prevdir;   // direction of iteration k-1
+  int32_t switched;  // a forward->backward switch has happened
+  int32_t qsel;      // queue holding the input frontier (push)
+  int32_t cur;       // visited bitmap holding levels <= k
+  int32_t switches;
+  int64_t qlen;      // |Q| of iteration k
+  int64_t p;         // |P|: vertices with a depth, Q included
+  int64_t insp_sum;  // CSR entries read so far
+  // last read value of slot[p].{q, big, insp, chunk}; kept as scalars so the
+  // parity select does not force the state into scratch memory
+  ull b0q, b0big, b0insp, b0chunk;
+  ull b1q, b1big, b1insp, b1chunk;
+  ull auxbase;
+};
+
+struct Bases {
+  ull q, big, insp, chunk;
+};
+
+__device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
+  // branch-free select on a wave-uniform parity
+  const ull m = 0ull - (ull)odd;
+  return (a1 & m) | (a0 & ~m);
+}
+
+__device__ __forceinline__ Bases get_bases(const St& S) {
+  const bool odd = S.k & 1;
+  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1big, S.b0big), sel(odd, S.b1insp, S.b0insp),
+               sel(odd, S.b1chunk, S.b0chunk)};
+}
+
+__device__ __forceinline__ void set_bases(St& S, const Bases& b) {
+  const bool odd = S.k & 1;
+  S.b1q = sel(odd, b.q, S.b1q);
+  S.b1big = sel(odd, b.big, S.b1big);
+  S.b1insp = sel(odd, b.insp, S.b1insp);
+  S.b1chunk = sel(odd, b.chunk, S.b1chunk);
+  S.b0q = sel(odd, S.b0q, b.q);
+  S.b0big = sel(odd, S.b0big, b.big);
+  S.b0insp = sel(odd, S.b0insp, b.insp);
+  S.b0chunk = sel(odd, S.b0chunk, b.chunk);
+}
+
+// Direction rule of Sec. VI-A for the iteration described by S (k >= 1):
+// FV = |Q| m / n, BV = |U| n / |P|, U = n - |P|; forward->backward when
+// FV > do_a BV (once), backward->forward when FV < do_b BV.  Exact in
+// 128-bit integers: FV > (a/b) BV  <=>  b |Q| m |P| > a |U| n n.
+__device__ __forceinline__ void decide(St& S, const BfsParams& P) {
+  S.prevdir = S.dir;
+  if (P.mode != FG_MODE_DO || S.k == 0) {
+    S.dir = DIR_PUSH;
+    return;
+  }
+  const u128 lhs = (u128)(ull)S.qlen * (ull)P.m * (ull)S.p;
+  const u128 rhs = (u128)(ull)((int64_t)P.n - S.p) * (ull)P.n * (ull)P.n;
+  if (S.dir == DIR_PUSH) {
+    if (!S.switched && lhs * P.a_den > rhs * P.a_num) {
+      S.dir = DIR_PULL;
+      S.switched = 1;
+      S.switches++;
+    }
+  } else if (lhs * P.b_den < rhs * P.b_num) {
+    S.dir = DIR_PUSH;
+    S.switches++;
+  }
+}
+
+__device__ __forceinline__ void trace_iter(const St& S, const BfsParams& P) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && S.k < FG_TRACE_MAX) {
+    P.stats->dir[S.k] = (int8_t)S.dir;
+    P.stats->frontier[S.k] = S.qlen;
+  }
+}
+
+__device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const BfsParams& P) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && k < FG_TRACE_MAX)
+    P.stats->inspected[k] = insp;
+}
+
+// Filter step fused into the advance: test-and-set of the visited bit.
+__device__ __forceinline__ bool try_visit(int32_t v, int32_t src, int32_t d,
+                                          uint32_t* vis32, const BfsParams& P) {
+  const uint32_t bit = 1u << (v & 31);
+  uint32_t* wp = vis32 + (v >> 5);
+  if (*wp & bit) return false;  // plain pre-check; a stale 0 only costs the atomic
+  const uint32_t old = atomicOr(wp, bit);
+  if (old & bit) return false;
+  P.depth[v] = d;
+  if (P.parent) P.parent[v] = src;
+  return true;
+}
+
+// Wave-aggregated append of the lanes in `mask` to `q` through the
+// monotone counter `total` (positions are relative to `base`).
+__device__ __forceinline__ void wave_append(uint64_t mask, int32_t v, ull* total, ull base,
+                                            int32_t* q) {
+  if (!mask) return;
+  ull pos = 0;
+  if (fg_lane() == 0) pos = atomicAdd(total, (ull)__popcll(mask));
+  pos = __shfl(pos, 0, FG_WAVE) - base;
+  if ((mask >> fg_lane()) & 1ull) q[pos + fg_mbcnt(mask)] = v;
+}
+
+struct Lds {
+  // per-wave scan-gather staging (push, full grid)
+  int32_t w_sc[PWAVES][FG_WAVE];
+  int32_t w_u[PWAVES][FG_WAVE];
+  int32_t w_b[PWAVES][FG_WAVE];
+  // block-level staging (small-frontier mode and the big-degree batches)
+  int32_t b_sc[BIG_BATCH + 1];
+  int32_t b_u[BIG_BATCH];
+  int32_t b_b[BIG_BATCH];
+  int64_t red[PWAVES + 1];
+  int32_t red32[PWAVES + 1];
+  int32_t newcnt;
+  int32_t flag;
+  int64_t bcast[16];
+};
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Largest j in [0, cnt) with sc[j] <= t (sc non-decreasing).
+__device__ __forceinline__ int32_t upper_idx(const int32_t* sc, int32_t cnt, int32_t t) {
+  int32_t lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (sc[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- push, full grid, phase A: waves take 64-entry chunks of the frontier
+// dynamically; vertices below big_deg are expanded by a wave-level scan-
+// gather (every lane handles one edge per round); the others are deferred
+// to the big list.
+__device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int32_t* Qin = P.q[S.qsel];
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
+  const int32_t d_new = S.k + 1;
+  int32_t* sc = L.w_sc[wid];
+  int32_t* su = L.w_u[wid];
+  int32_t* sb = L.w_b[wid];
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  const Bases B = get_bases(S);
+  int64_t insp = 0;
+  for (;;) {
+    ull c = 0;
+    if (lane == 0) c = atomicAdd(&C.chunk.v, 1ull);
+    c = __shfl(c, 0, FG_WAVE) - B.chunk;
+    const int64_t base = (int64_t)c * FG_WAVE;
+    if (base >= S.qlen) break;
+    const int64_t i = base + lane;
+    int32_t u = 0, b = 0, deg = 0;
+    if (i < S.qlen) {
+      u = Qin[i];
+      b = P.off[u];
+      deg = P.off[u + 1] - b;
+    }
+    insp += deg;
+    const bool big = deg >= P.big_deg;
+    const uint64_t bigmask = __ballot(big);
+    wave_append(bigmask, u, &C.big.v, B.big, P.big);
+    const int32_t d = big ? 0 : deg;
+    const int32_t inc = fg_wave_incl_scan(d);
+    const int32_t T = __shfl(inc, FG_WAVE - 1, FG_WAVE);
+    wave_lds_fence();
+    sc[lane] = inc - d;
+    su[lane] = u;
+    sb[lane] = b;
+    wave_lds_fence();
+    for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
+      const int32_t t = t0 + lane;
+      bool won = false;
+      int32_t v = 0;
+      if (t < T) {
+        const int32_t j = upper_idx(sc, FG_WAVE, t);
+        v = P.col[sb[j] + (t - sc[j])];
+        won = try_visit(v, su[j], d_new, vis32, P);
+      }
+      wave_append(__ballot(won), v, &C.q.v, B.q, Qout);
+    }
+  }
+  const int64_t tot = fg_block_sum<PB>(insp, L.red);
+  if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
+}
+
+// ---- push, full grid, phase B: the big list's edges are spread evenly over
+// every wave of the grid (each workgroup scans a batch's degrees in LDS).
+__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t nbig, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
+  const int32_t d_new = S.k + 1;
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  const Bases B = get_bases(S);
+  const int32_t* bigl = P.big;  // phase A wrote entries 0..nbig-1 of this iteration
+  for (int64_t b0 = 0; b0 < nbig; b0 += BIG_BATCH) {
+    const int32_t cnt = (int32_t)((nbig - b0) < BIG_BATCH ? (nbig - b0) : BIG_BATCH);
+    // two entries per thread, then a block scan of the pair sums
+    int32_t d0 = 0, d1 = 0;
+    const int32_t j0 = 2 * threadIdx.x, j1 = j0 + 1;
+    __syncthreads();
+    if (j0 < cnt) {
+      int32_t u = bigl[b0 + j0];
+      int32_t b = P.off[u];
+      d0 = P.off[u + 1] - b;
+      L.b_u[j0] = u;
+      L.b_b[j0] = b;
+    }
+    if (j1 < cnt) {
+      int32_t u = bigl[b0 + j1];
+      int32_t b = P.off[u];
+      d1 = P.off[u + 1] - b;
+      L.b_u[j1] = u;
+      L.b_b[j1] = b;
+    }
+    int32_t total = 0;
+    const int32_t ex = fg_block_excl_scan<PB>(d0 + d1, L.red32, &total);
+    if (j0 < cnt) L.b_sc[j0] = ex;
+    if (j1 < cnt) L.b_sc[j1] = ex + d0;
+    __syncthreads();
+    for (int64_t t0 = gw * FG_WAVE; t0 < total; t0 += W * FG_WAVE) {
+      const int32_t t = (int32_t)(t0 + lane);
+      bool won = false;
+      int32_t v = 0;
+      if (t < total) {
+        const int32_t j = upper_idx(L.b_sc, cnt, t);
+        v = P.col[L.b_b[j] + (t - L.b_sc[j])];
+        won = try_visit(v, L.b_u[j], d_new, vis32, P);
+      }
+      wave_append(__ballot(won), v, &C.q.v, B.q, Qout);
+    }
+  }
+}
+
+// ---- pull, full grid: each wave owns 64 consecutive vertices (one bitmap
+// word).  An unvisited vertex of nonzero degree scans its CSR row in order
+// and stops at the first visited neighbour: for an unvisited v every
+// visited neighbour has depth exactly k (depths differ by at most one across
+// an edge), so that neighbour is in the current frontier.  The next bitmap
+// word is written whole, so no atomics are needed.
+__device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  const uint64_t* Vin = P.vis[S.cur];
+  uint64_t* Vout = P.vis[S.cur ^ 1];
+  const int32_t d_new = S.k + 1;
+  int64_t insp = 0;
+  int32_t nnew = 0;
+  for (int64_t w = gw; w < P.nwords; w += W) {
+    const uint64_t vis = Vin[w];
+    const uint64_t act = P.nz[w] & ~vis;
+    uint64_t nb = 0;
+    if (act) {
+      const int32_t v = (int32_t)(w * 64 + lane);
+      bool found = false;
+      int32_t pu = -1;
+      if ((act >> lane) & 1ull) {
+        const int32_t e = P.off[v + 1];
+        for (int32_t i = P.off[v]; i < e; ++i) {
+          const int32_t u = P.col[i];
+          insp++;
+          if ((Vin[u >> 6] >> (u & 63)) & 1ull) {
+            found = true;
+            pu = u;
+            break;
+          }
+        }
+      }
+      nb = __ballot(found);
+      if (found) {
+        P.depth[v] = d_new;
+        if (P.parent) P.parent[v] = pu;
+      }
+      nnew += __popcll(nb);
+    }
+    if (lane == 0) Vout[w] = vis | nb;
+  }
+  if (lane != 0) nnew = 0;
+  const int64_t tot = fg_block_sum<PB>(insp, L.red);
+  const int32_t tn = fg_block_sum<PB>(nnew, L.red32);
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  if (threadIdx.x == 0) {
+    if (tot) atomicAdd(&C.insp.v, (ull)tot);
+    if (tn) atomicAdd(&C.q.v, (ull)tn);
+  }
+}
+
+// ---- backward -> forward switch: the new frontier is the set difference
+// of the current and the previous visited bitmap, listed into Q[qsel].
+__device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S) {
+  const int lane = fg_lane();
+  const uint64_t* Vnew = P.vis[S.cur];
+  const uint64_t* Vold = P.vis[S.cur ^ 1];
+  int32_t* Q = P.q[S.qsel];
+  const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * PB;
+  for (int64_t w0 = tid - lane; w0 < P.nwords; w0 += nth) {
+    const int64_t w = w0 + lane;
+    uint64_t diff = 0;
+    if (w < P.nwords) diff = Vnew[w] & ~Vold[w];
+    const int32_t c = __popcll(diff);
+    const int32_t inc = fg_wave_incl_scan(c);
+    const int32_t tot = __shfl(inc, FG_WAVE - 1, FG_WAVE);
+    ull base = 0;
+    if (lane == FG_WAVE - 1 && tot) base = atomicAdd(&P.ctl->aux.v, (ull)tot);
+    base = __shfl(base, FG_WAVE - 1, FG_WAVE) - S.auxbase;
+    int64_t pos = (int64_t)base + inc - c;
+    while (diff) {
+      const int bit = __builtin_ctzll(diff);
+      diff &= diff - 1;
+      Q[pos++] = (int32_t)(w * 64 + bit);
+    }
+  }
+}
+
+// ---- small-frontier mode, workgroup 0 only: push levels run back to back
+// with workgroup barriers while |Q| <= small_q and the frontier's degree sum
+// <= small_e.  Returns with S describing the next iteration; *force_full is
+// set when the degree sum was too large for iteration S.k.
+__device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
+  const int tid = threadIdx.x;
+  *force_full = 0;
+  for (;;) {
+    const int32_t* Qin = P.q[S.qsel];
+    int32_t* Qout = P.q[S.qsel ^ 1];
+    uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
+    int64_t s = 0;
+    for (int64_t i = tid; i < S.qlen; i += PB) {
+      const int32_t u = Qin[i];
+      s += P.off[u + 1] - P.off[u];
+    }
+    const int64_t sum = fg_block_sum<PB>(s, L.red);
+    if (sum > P.small_e) {
+      *force_full = 1;
+      return;
+    }
+    if (tid == 0) L.newcnt = 0;
+    const int32_t d_new = S.k + 1;
+    for (int64_t c0 = 0; c0 < S.qlen; c0 += PB) {
+      const int64_t i = c0 + tid;
+      int32_t u = 0, b = 0, d = 0;
+      if (i < S.qlen) {
+        u = Qin[i];
+        b = P.off[u];
+        d = P.off[u + 1] - b;
+      }
+      int32_t T = 0;
+      const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &T);
+      L.b_sc[tid] = ex;
+      L.b_u[tid] = u;
+      L.b_b[tid] = b;
+      __syncthreads();
+      const int32_t cnt = (int32_t)((S.qlen - c0) < PB ? (S.qlen - c0) : PB);
+      for (int32_t t0 = 0; t0 < T; t0 += PB) {
+        const int32_t t = t0 + tid;
+        bool won = false;
+        int32_t v = 0;
+        if (t < T) {
+          const int32_t j = upper_idx(L.b_sc, cnt, t);
+          v = P.col[L.b_b[j] + (t - L.b_sc[j])];
+          won = try_visit(v, L.b_u[j], d_new, vis32, P);
+        }
+        const uint64_t mask = __ballot(won);
+        if (mask) {
+          int32_t pos = 0;
+          if (fg_lane() == 0) pos = atomicAdd(&L.newcnt, __popcll(mask));
+          pos = __shfl(pos, 0, FG_WAVE);
+          if (won) Qout[pos + fg_mbcnt(mask)] = v;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t nq = L.newcnt;
+    trace_insp(S.k, sum, P);
+    S.insp_sum += sum;
+    S.k++;
+    S.qsel ^= 1;
+    S.qlen = nq;
+    S.p += nq;
+    decide(S, P);
+    trace_iter(S, P);
+    __syncthreads();
+    if (nq == 0 || S.dir != DIR_PUSH || nq > P.small_q) return;
+  }
+}
+
+__global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
+  __shared__ Lds L;
+  fg_grid_sync gs{&P.ctl->arrive, &P.ctl->abort_flag, gridDim.x, 0u};
+  St S = {};
+  S.dir = DIR_PUSH;
+  S.prevdir = DIR_PUSH;
+  S.qlen = 1;
+  S.p = 1;
+  uint32_t sm_seen = 0;
+  int force_full = 0;
+  bool ok = true;
+  trace_iter(S, P);
+  while (S.qlen > 0) {
+    // backward -> forward: list the last pull's discoveries first
+    if (S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
+      bitmap_diff_to_queue(P, S);
+      if (!(ok = gs.sync(&L.flag))) break;
+      S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
+      S.prevdir = DIR_PUSH;
+    }
+    if (S.dir == DIR_PUSH && !force_full && S.qlen <= P.small_q) {
+      sm_seen++;
+      if (blockIdx.x == 0) {
+        int ff = 0;
+        small_mode(P, S, L, &ff);
+        if (threadIdx.x == 0) {
+          BfsCtl* c = P.ctl;
+          c->pub_k = S.k;
+          c->pub_dir = S.dir;
+          c->pub_prevdir = S.prevdir;
+          c->pub_switched = S.switched;
+          c->pub_qsel = S.qsel;
+          c->pub_force = ff;
+          c->pub_qlen = S.qlen;
+          c->pub_p = S.p;
+          c->pub_insp_sum = S.insp_sum;
+          c->pub_switches = S.switches;
+          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        force_full = ff;
+        __syncthreads();
+      } else {
+        if (threadIdx.x == 0) {
+          uint32_t spins = 0;
+          int bad = 0;
+          for (;;) {
+            uint32_t now = __hip_atomic_load(&P.ctl->sm_signal, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            if ((int32_t)(now - sm_seen) >= 0) break;
+            if ((++spins & 31u) == 0 &&
+                __hip_atomic_load(&P.ctl->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              bad = 1;
+              break;
+            }
+            if (spins > FG_SPIN_LIMIT) {
+              __hip_atomic_store(&P.ctl->abort_flag, 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+              bad = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+          }
+          L.flag = bad;
+          if (!bad) {
+            const BfsCtl* c = P.ctl;
+            L.bcast[0] = c->pub_k;
+            L.bcast[1] = c->pub_dir;
+            L.bcast[2] = c->pub_prevdir;
+            L.bcast[3] = c->pub_switched;
+            L.bcast[4] = c->pub_qsel;
+            L.bcast[5] = c->pub_force;
+            L.bcast[6] = c->pub_qlen;
+            L.bcast[7] = c->pub_p;
+            L.bcast[8] = c->pub_insp_sum;
+            L.bcast[9] = c->pub_switches;
+          }
+        }
+        __syncthreads();
+        if (L.flag) {
+          ok = false;
+          break;
+        }
+        S.k = (int32_t)L.bcast[0];
+        S.dir = (int32_t)L.bcast[1];
+        S.prevdir = (int32_t)L.bcast[2];
+        S.switched = (int32_t)L.bcast[3];
+        S.qsel = (int32_t)L.bcast[4];
+        force_full = (int)L.bcast[5];
+        S.qlen = L.bcast[6];
+        S.p = L.bcast[7];
+        S.insp_sum = L.bcast[8];
+        S.switches = (int32_t)L.bcast[9];
+        __syncthreads();
+      }
+      continue;
+    }
+    force_full = 0;
+    CtrSlot& C = P.ctl->slot[S.k & 1];
+    Bases B = get_bases(S);
+    if (S.dir == DIR_PUSH) {
+      push_phase_a(P, S, L);
+      if (!(ok = gs.sync(&L.flag))) break;
+      const ull bt = fg_atomic_load_u64(&C.big.v);
+      const int64_t nbig = (int64_t)(bt - B.big);
+      if (nbig > 0) {
+        push_phase_b(P, S, nbig, L);
+        if (!(ok = gs.sync(&L.flag))) break;
+      }
+      B.big = bt;
+      B.chunk = fg_atomic_load_u64(&C.chunk.v);
+      S.qsel ^= 1;
+    } else {
+      pull_phase(P, S, L);
+      if (!(ok = gs.sync(&L.flag))) break;
+      S.cur ^= 1;
+    }
+    const ull qt = fg_atomic_load_u64(&C.q.v);
+    const ull it = fg_atomic_load_u64(&C.insp.v);
+    const int64_t nq = (int64_t)(qt - B.q);
+    const int64_t insp = (int64_t)(it - B.insp);
+    B.q = qt;
+    B.insp = it;
+    set_bases(S, B);
+    trace_insp(S.k, insp, P);
+    S.insp_sum += insp;
+    S.k++;
+    S.qlen = nq;
+    S.p += nq;
+    decide(S, P);
+    trace_iter(S, P);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
+    fg_run_stats* st = P.stats;
+    st->status = ok ? FG_OK : FG_EDEVICE;
+    st->iterations = S.k;
+    st->reached = S.p;
+    st->edges_inspected = S.insp_sum;
+    st->direction_switches = S.switches;
+    st->grid_blocks = (int32_t)gridDim.x;
+  }
+}
+
+// a1: depth = -1 / parent = -1 except at the source, visited = {src},
+// queue 0 = {src}, control block and stats cleared.
+__global__ void bfs_init_kernel(int32_t n, int32_t nwords, int32_t src, int32_t* depth,
+                                int32_t* parent, uint64_t* vis0, int32_t* q0, uint32_t* ctl,
+                                int32_t ctl_words, uint32_t* stats, int32_t stats_words) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  const bool vec = ((((uintptr_t)depth) | ((uintptr_t)(parent ? parent : depth))) & 15) == 0;
+  if (vec) {
+    const int64_t n4 = n / 4;
+    int4* d4 = (int4*)depth;
+    int4* p4 = (int4*)parent;
+    const int4 neg = make_int4(-1, -1, -1, -1);
+    for (int64_t i = tid; i < n4; i += nth) {
+      d4[i] = neg;
+      if (parent) p4[i] = neg;
+    }
+    for (int64_t i = n4 * 4 + tid; i < n; i += nth) {
+      depth[i] = -1;
+      if (parent) parent[i] = -1;
+    }
+  } else {
+    for (int64_t i = tid; i < n; i += nth) {
+      depth[i] = -1;
+      if (parent) parent[i] = -1;
+    }
+  }
+  for (int64_t w = tid; w < nwords; w += nth) vis0[w] = 0ull;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < ctl_words; i += blockDim.x) ctl[i] = 0u;
+    if (stats)
+      for (int i = threadIdx.x; i < stats_words; i += blockDim.x) stats[i] = 0u;
+  }
+}
+
+// Source entries, after the bulk fill (stream order).
+__global__ void bfs_seed_kernel(int32_t src, int32_t* depth, int32_t* parent, uint64_t* vis0,
+                                int32_t* q0) {
+  if (threadIdx.x == 0) {
+    depth[src] = 0;
+    if (parent) parent[src] = src;
+    vis0[src >> 6] = 1ull << (src & 63);
+    q0[0] = src;
+  }
+}
+
+struct BfsLayout {
+  BfsCtl* ctl;
+  uint64_t* vis[2];
+  int32_t* q[2];
+  int32_t* big;
+  size_t bytes;
+};
+
+BfsLayout bfs_layout(const fg_graph* g, void* ws) {
+  fg_carver c(ws);
+  BfsLayout L;
+  L.ctl = c.take<BfsCtl>(1);
+  L.vis[0] = c.take<uint64_t>(g->nwords);
+  L.vis[1] = c.take<uint64_t>(g->nwords);
+  L.q[0] = c.take<int32_t>(g->n);
+  L.q[1] = c.take<int32_t>(g->n);
+  L.big = c.take<int32_t>(g->n);
+  L.bytes = c.used;
+  return L;
+}
+
+int g_occupancy[64];
+
+int persistent_blocks_per_cu(int device) {
+  if (device < 0 || device >= 64) return 1;
+  if (g_occupancy[device] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_persistent, PB, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_occupancy[device] = nb;
+  }
+  return g_occupancy[device];
+}
+
+}  // namespace
+
+size_t fg_bfs_workspace_bytes(const fg_graph* g) { return bfs_layout(g, nullptr).bytes; }
+
+// a1 for every BFS variant: bulk fill, then the source entries.
+void fg_bfs_launch_init(const fg_graph* g, int32_t src, int32_t* depth, int32_t* parent,
+                        uint64_t* vis0, int32_t* q0, fg_run_stats* stats, hipStream_t s,
+                        void* ctl, int32_t ctl_bytes) {
+  int init_blocks = (int)((g->n + 4095) / 4096);
+  if (init_blocks > 2048) init_blocks = 2048;
+  if (init_blocks < 1) init_blocks = 1;
+  bfs_init_kernel<<<init_blocks, 256, 0, s>>>(g->n, g->nwords, src, depth, parent, vis0, q0,
+                                              (uint32_t*)ctl, ctl_bytes / 4, (uint32_t*)stats,
+                                              (int32_t)(sizeof(fg_run_stats) / 4));
+  bfs_seed_kernel<<<1, 64, 0, s>>>(src, depth, parent, vis0, q0);
+}
+
+extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts, void* ws,
+                            size_t ws_bytes, int32_t* depth, int32_t* parent,
+                            fg_run_stats* stats, void* stream) {
+  if (!g) return fg_set_error(FG_EINVAL, "fg_bfs: graph is NULL");
+  if (src < 0 || src >= g->n)
+    return fg_set_error(FG_EINVAL, "fg_bfs: src=%d outside [0, %d)", src, g->n);
+  if (!depth) return fg_set_error(FG_EINVAL, "fg_bfs: depth is NULL");
+  if (!ws) return fg_set_error(FG_EINVAL, "fg_bfs: workspace is NULL");
+  fg_bfs_opts o;
+  if (opts) o = *opts; else fg_bfs_opts_default(&o);
+  if (o.mode != FG_MODE_DO && o.mode != FG_MODE_PUSH && o.mode != FG_MODE_PUSH_UNFUSED)
+    return fg_set_error(FG_EINVAL, "fg_bfs: unknown mode %d", o.mode);
+  if (o.mode == FG_MODE_DO) {
+    if (!g->symmetric)
+      return fg_set_error(FG_EUNSUPPORTED,
+                          "fg_bfs: the pull step needs an undirected graph (FG_SYMMETRIC)");
+    if (o.do_a_den == 0 || o.do_b_den == 0)
+      return fg_set_error(FG_EINVAL, "fg_bfs: zero denominator in do_a / do_b");
+  }
+  if (o.mode == FG_MODE_PUSH_UNFUSED)
+    return fg_bfs_unfused(g, src, ws, ws_bytes, depth, parent, stats, (hipStream_t)stream);
+  BfsLayout lay = bfs_layout(g, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
+                        lay.bytes);
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  fg_device_props pr = fg_props(dev);
+  if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_bfs: device lacks cooperative launch");
+  int bpc = persistent_blocks_per_cu(dev);
+  if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
+  if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
+  const int grid = pr.cus * bpc;
+  hipStream_t s = (hipStream_t)stream;
+
+  BfsParams P;
+  memset(&P, 0, sizeof(P));
+  P.off = g->off;
+  P.col = g->col;
+  P.nz = g->nzmask;
+  P.n = g->n;
+  P.nwords = g->nwords;
+  P.m = g->m;
+  P.src = src;
+  P.mode = o.mode;
+  P.depth = depth;
+  P.parent = parent;
+  P.vis[0] = lay.vis[0];
+  P.vis[1] = lay.vis[1];
+  P.q[0] = lay.q[0];
+  P.q[1] = lay.q[1];
+  P.big = lay.big;
+  P.ctl = lay.ctl;
+  P.stats = stats;
+  P.a_num = o.do_a_num;
+  P.a_den = o.do_a_den;
+  P.b_num = o.do_b_num;
+  P.b_den = o.do_b_den;
+  P.small_q = o.small_frontier > 0 ? o.small_frontier : DEF_SMALL_Q;
+  if (P.small_q > PB) P.small_q = PB;
+  P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
+  P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
+
+  fg_bfs_launch_init(g, src, depth, parent, lay.vis[0], lay.q[0], stats, s, lay.ctl,
+                     (int32_t)sizeof(BfsCtl));
+  void* args[] = {&P};
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_persistent, dim3(grid), dim3(PB), args,
+                                        0, s));
+  return FG_OK;
+}

@@ -1,0 +1,188 @@
+// Shared host/device helpers of libfg (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/fg.h"
+
+// ---------------------------------------------------------------- host side
+
+// Records a thread-local error message and returns `code`.
+fg_status fg_set_error(fg_status code, const char* fmt, ...);
+
+#define FG_HIP_TRY(expr)                                                       \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return fg_set_error(FG_EDEVICE, "%s failed: %s (%s:%d)", #expr,          \
+                          hipGetErrorString(_e), __FILE__, __LINE__);          \
+  } while (0)
+
+struct fg_graph {
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t nwords = 0;       // ceil(n / 64)
+  const int32_t* off = nullptr;
+  const int32_t* col = nullptr;
+  const uint32_t* w = nullptr;
+  uint64_t* nzmask = nullptr;  // bit v set iff deg(v) > 0, nwords words
+  void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t symmetric = 0;
+  int32_t max_degree = 0;
+  int32_t nonzero_degree = 0;
+  int32_t device = 0;
+  int64_t resident_bytes = 0;
+};
+
+// Internal entry points shared between translation units.
+size_t fg_bfs_workspace_bytes(const fg_graph* g);
+size_t fg_ops_workspace_bytes(const fg_graph* g, bool with_bfs);
+size_t fg_sssp_workspace_bytes(const fg_graph* g);
+size_t fg_msbfs_workspace_bytes(const fg_graph* g, int32_t lanes);
+void fg_bfs_launch_init(const fg_graph* g, int32_t src, int32_t* depth, int32_t* parent,
+                        uint64_t* vis0, int32_t* q0, fg_run_stats* stats, hipStream_t s,
+                        void* ctl, int32_t ctl_bytes);
+fg_status fg_bfs_unfused(const fg_graph* g, int32_t src, void* ws, size_t ws_bytes,
+                         int32_t* depth, int32_t* parent, fg_run_stats* stats, hipStream_t s);
+
+// Device properties used for persistent launches (cached per device).
+struct fg_device_props {
+  int cus;
+  int coop;
+};
+fg_device_props fg_props(int device);
+
+static inline size_t fg_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves a caller workspace into 256-byte aligned pieces.
+struct fg_carver {
+  char* base;
+  size_t used = 0;
+  explicit fg_carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? (T*)(base + used) : nullptr;
+    used += fg_align(count * sizeof(T));
+    return p;
+  }
+};
+
+// ------------------------------------------------------------- device side
+
+#define FG_WAVE 64
+
+__device__ __forceinline__ int fg_lane() { return (int)__lane_id(); }
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ int fg_mbcnt(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <class T>
+__device__ __forceinline__ T fg_wave_incl_scan(T x) {
+  const int lane = fg_lane();
+#pragma unroll
+  for (int d = 1; d < FG_WAVE; d <<= 1) {
+    T y = __shfl_up(x, d, FG_WAVE);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+template <class T>
+__device__ __forceinline__ T fg_wave_sum(T x) {
+#pragma unroll
+  for (int d = FG_WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, FG_WAVE);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t fg_atomic_load_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long fg_atomic_load_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-wide barrier for cooperative (co-resident) launches.  `arrive` is a
+// monotonically increasing arrival counter that starts at zero for the
+// launch; `abort_flag` lets any workgroup stop the whole grid.  The wait is
+// bounded: after `FG_SPIN_LIMIT` polls the grid is aborted, so every
+// workgroup leaves the kernel even if co-residency were ever violated.
+#define FG_SPIN_LIMIT (1u << 24)
+
+struct fg_grid_sync {
+  uint32_t* arrive;
+  uint32_t* abort_flag;
+  uint32_t nblocks;
+  uint32_t count;  // barriers passed by this workgroup
+
+  // Returns false if the grid was aborted.  Must be called by every thread
+  // of every workgroup the same number of times.
+  __device__ bool sync(int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      const uint32_t target = count * nblocks;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t spins = 0;
+      int bad = 0;
+      for (;;) {
+        uint32_t now = __hip_atomic_load(arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(now - target) >= 0) break;
+        if ((++spins & 31u) == 0 &&
+            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          bad = 1;
+          break;
+        }
+        if (spins > FG_SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      *s_flag = bad;
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+};
+
+// Block-wide sum for blocks of BT threads (BT multiple of 64); `scratch`
+// needs BT/64 elements of LDS.  Every thread of the block must call it.
+template <int BT, class T>
+__device__ __forceinline__ T fg_block_sum(T x, T* scratch) {
+  x = fg_wave_sum(x);
+  const int wid = threadIdx.x / FG_WAVE;
+  __syncthreads();
+  if (fg_lane() == 0) scratch[wid] = x;
+  __syncthreads();
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < BT / FG_WAVE; ++i) s += scratch[i];
+  return s;
+}
+
+// Block-wide exclusive scan (BT threads); returns the exclusive prefix and
+// the block total in *total.  `scratch` needs BT/64 + 1 elements of LDS.
+template <int BT, class T>
+__device__ __forceinline__ T fg_block_excl_scan(T x, T* scratch, T* total) {
+  const int wid = threadIdx.x / FG_WAVE;
+  T inc = fg_wave_incl_scan(x);
+  __syncthreads();
+  if (fg_lane() == FG_WAVE - 1) scratch[wid] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < BT / FG_WAVE; ++i) {
+    T v = scratch[i];
+    before += (i < wid) ? v : (T)0;
+    all += v;
+  }
+  *total = all;
+  return before + inc - x;
+}
