@@ -111,6 +111,8 @@ fg_status fg_graph_info(const fg_graph* g, fg_graph_info_t* info);
  * Bytes of device workspace a call needs (just-enough sizing, Sec. VI-B:
  * frontier queues are bounded by |V_i|; the unfused advance additionally
  * needs an edge frontier bounded by |E_i|).  Returns 0 for bad arguments.
+ * A workspace must be zero-filled once before its first use; every call
+ * leaves it ready for the next one.
  */
 size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32_t lanes);
 
@@ -130,9 +132,13 @@ typedef struct {
   int64_t edges_inspected;  /* CSR entries read by advance / pull steps      */
   int32_t direction_switches;
   int32_t grid_blocks;      /* workgroups of the persistent launch           */
+  int32_t clock_khz;        /* rate of the device wall clock below           */
+  int32_t reserved;
+  int64_t t_start;          /* device wall clock when the traversal started  */
   int8_t dir[FG_TRACE_MAX]; /* 0 = push (forward), 1 = pull (backward)       */
   int64_t frontier[FG_TRACE_MAX];  /* input frontier size |Q| per iteration */
   int64_t inspected[FG_TRACE_MAX]; /* CSR entries read per iteration         */
+  int64_t t_end[FG_TRACE_MAX];     /* device wall clock when iteration ended */
 } fg_run_stats;
 
 /* Copy a device-resident fg_run_stats into host memory (synchronises `stream`). */

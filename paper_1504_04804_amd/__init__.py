@@ -35,10 +35,22 @@ class RunStats(ctypes.Structure):
         ("edges_inspected", ctypes.c_int64),
         ("direction_switches", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("clock_khz", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("t_start", ctypes.c_int64),
         ("dir", ctypes.c_int8 * FG_TRACE_MAX),
         ("frontier", ctypes.c_int64 * FG_TRACE_MAX),
         ("inspected", ctypes.c_int64 * FG_TRACE_MAX),
+        ("t_end", ctypes.c_int64 * FG_TRACE_MAX),
     ]
+
+    def iteration_us(self):
+        """Device time per iteration (first FG_TRACE_MAX), in microseconds."""
+        if self.clock_khz <= 0:
+            return []
+        k = min(self.iterations, FG_TRACE_MAX)
+        t = [self.t_start] + list(self.t_end[:k])
+        return [(t[i + 1] - t[i]) * 1000.0 / self.clock_khz for i in range(k)]
 
     def trace(self):
         k = min(self.iterations, FG_TRACE_MAX)
@@ -186,7 +198,8 @@ class Graph:
         key = (prim, lanes)
         if key not in self._ws:
             nb = self.workspace_bytes(prim, lanes)
-            self._ws[key] = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.off.device)
+            # zero-filled once; the library keeps it ready between calls
+            self._ws[key] = torch.zeros(max(nb, 256), dtype=torch.uint8, device=self.off.device)
         return self._ws[key]
 
     def close(self):

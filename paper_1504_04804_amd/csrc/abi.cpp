@@ -26,11 +26,12 @@ fg_device_props fg_props(int device) {
   static fg_device_props cache[64];
   static bool have[64] = {false};
   std::lock_guard<std::mutex> lock(mu);
-  if (device < 0 || device >= 64) return fg_device_props{0, 0};
+  if (device < 0 || device >= 64) return fg_device_props{0, 0, 0};
   if (!have[device]) {
-    fg_device_props p{0, 0};
+    fg_device_props p{0, 0, 0};
     hipDeviceGetAttribute(&p.cus, hipDeviceAttributeMultiprocessorCount, device);
     hipDeviceGetAttribute(&p.coop, hipDeviceAttributeCooperativeLaunch, device);
+    hipDeviceGetAttribute(&p.clock_khz, hipDeviceAttributeWallClockRate, device);
     cache[device] = p;
     have[device] = true;
   }

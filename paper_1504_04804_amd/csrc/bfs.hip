@@ -8,13 +8,19 @@
 // iteration before produced, so the host is not involved between
 // iterations.  Levels whose frontier is small are run by workgroup 0 alone
 // (no grid barrier at all); larger levels use the whole grid and one grid
-// barrier per iteration (two when very high degree vertices are present).
+// barrier per iteration (two when high-degree vertices are present).
+//
+// Push load balance: a vertex of degree below `big_degree` is expanded by a
+// wave-level scan-gather (each lane takes one edge per round); a vertex of
+// higher degree is cut into descriptors of CH consecutive edges that every
+// wave of the grid then takes in turn, so no wave walks a hub alone and no
+// per-edge search is needed.
 //
 // Data layout in HBM (all owned by the caller's workspace, 256-B aligned):
 //   visited   2 x uint64[ceil(n/64)]  current / next visited bitmap
 //   queue     2 x int32[n]            input / output vertex frontier
-//   big       int32[n]                push vertices of very high degree
-//   control   counters, barrier, hand-back state of the small-frontier mode
+//   desc      int2[m/CH + n + 64]     edge-chunk descriptors {vertex, first edge}
+//   control   barrier, counters, hand-back state of the small-frontier mode
 #include <string.h>
 
 #include "fg_common.h"
@@ -23,12 +29,12 @@ namespace {
 
 constexpr int PB = 1024;          // persistent workgroup size
 constexpr int PWAVES = PB / FG_WAVE;
-constexpr int BIG_BATCH = 2048;   // very-high-degree vertices per LDS batch
+constexpr int CH = 256;           // edges per descriptor
 constexpr int DIR_PUSH = 0, DIR_PULL = 1;
 
 constexpr int32_t DEF_SMALL_Q = 1024;
-constexpr int64_t DEF_SMALL_E = 2048;
-constexpr int32_t DEF_BIG_DEG = 1024;
+constexpr int64_t DEF_SMALL_E = 4096;
+constexpr int32_t DEF_BIG_DEG = 64;
 
 typedef unsigned __int128 u128;
 typedef unsigned long long ull;
@@ -45,19 +51,20 @@ struct alignas(256) Line64 {
 // monotone counters never need resetting.
 struct CtrSlot {
   Line64 q;      // vertices discovered
-  Line64 big;    // entries appended to the big list
+  Line64 desc;   // edge-chunk descriptors written
   Line64 insp;   // CSR entries read
-  Line64 chunk;  // frontier chunks handed out (dynamic balance)
 };
 
+// The control block is zero when a launch starts: a fresh workspace is
+// zero-filled by the caller, and the last workgroup to leave a launch clears
+// it again for the next one.
 struct alignas(256) BfsCtl {
-  uint32_t arrive;          // grid barrier arrivals (monotone)
-  uint32_t pad0[63];
-  uint32_t abort_flag;      // set when a wait exceeded its bound
-  uint32_t pad1[63];
-  uint32_t sm_signal;       // small-frontier hand-backs (monotone)
+  uint32_t bar[FG_BAR_WORDS];  // grid barrier (its second line is the abort flag)
+  uint32_t sm_signal;          // small-frontier hand-backs (monotone)
   uint32_t pad2[63];
-  Line64 aux;               // entries written by bitmap -> queue conversion
+  uint32_t exit_count;         // workgroups that left the launch
+  uint32_t pad3[63];
+  Line64 aux;                  // entries written by bitmap -> queue conversion
   CtrSlot slot[2];
   // state published by workgroup 0 when a small-frontier episode ends
   int32_t pub_k, pub_dir, pub_prevdir, pub_switched, pub_qsel, pub_force;
@@ -78,13 +85,14 @@ struct BfsParams {
   int32_t* parent;
   uint64_t* vis[2];
   int32_t* q[2];
-  int32_t* big;
+  int2* desc;
   BfsCtl* ctl;
   fg_run_stats* stats;
   uint32_t a_num, a_den, b_num, b_den;
   int32_t small_q;
   int64_t small_e;
   int32_t big_deg;
+  int32_t clock_khz;
 };
 
 // Per-iteration state, identical in every workgroup.
@@ -99,15 +107,15 @@ struct St {
   int64_t qlen;      // |Q| of iteration k
   int64_t p;         // |P|: vertices with a depth, Q included
   int64_t insp_sum;  // CSR entries read so far
-  // last read value of slot[p].{q, big, insp, chunk}; kept as scalars so the
+  // last read value of slot[p].{q, desc, insp}; kept as scalars so the
   // parity select does not force the state into scratch memory
-  ull b0q, b0big, b0insp, b0chunk;
-  ull b1q, b1big, b1insp, b1chunk;
+  ull b0q, b0desc, b0insp;
+  ull b1q, b1desc, b1insp;
   ull auxbase;
 };
 
 struct Bases {
-  ull q, big, insp, chunk;
+  ull q, desc, insp;
 };
 
 __device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
@@ -118,29 +126,27 @@ __device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
 
 __device__ __forceinline__ Bases get_bases(const St& S) {
   const bool odd = S.k & 1;
-  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1big, S.b0big), sel(odd, S.b1insp, S.b0insp),
-               sel(odd, S.b1chunk, S.b0chunk)};
+  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1desc, S.b0desc), sel(odd, S.b1insp, S.b0insp)};
 }
 
 __device__ __forceinline__ void set_bases(St& S, const Bases& b) {
   const bool odd = S.k & 1;
   S.b1q = sel(odd, b.q, S.b1q);
-  S.b1big = sel(odd, b.big, S.b1big);
+  S.b1desc = sel(odd, b.desc, S.b1desc);
   S.b1insp = sel(odd, b.insp, S.b1insp);
-  S.b1chunk = sel(odd, b.chunk, S.b1chunk);
   S.b0q = sel(odd, S.b0q, b.q);
-  S.b0big = sel(odd, S.b0big, b.big);
+  S.b0desc = sel(odd, S.b0desc, b.desc);
   S.b0insp = sel(odd, S.b0insp, b.insp);
-  S.b0chunk = sel(odd, S.b0chunk, b.chunk);
 }
 
 // Direction rule of Sec. VI-A for the iteration described by S (k >= 1):
 // FV = |Q| m / n, BV = |U| n / |P|, U = n - |P|; forward->backward when
 // FV > do_a BV (once), backward->forward when FV < do_b BV.  Exact in
 // 128-bit integers: FV > (a/b) BV  <=>  b |Q| m |P| > a |U| n n.
+template <int MODE>
 __device__ __forceinline__ void decide(St& S, const BfsParams& P) {
   S.prevdir = S.dir;
-  if (P.mode != FG_MODE_DO || S.k == 0) {
+  if (MODE != FG_MODE_DO || S.k == 0) {
     S.dir = DIR_PUSH;
     return;
   }
@@ -166,8 +172,10 @@ __device__ __forceinline__ void trace_iter(const St& S, const BfsParams& P) {
 }
 
 __device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const BfsParams& P) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && k < FG_TRACE_MAX)
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && k < FG_TRACE_MAX) {
     P.stats->inspected[k] = insp;
+    P.stats->t_end[k] = (int64_t)wall_clock64();
+  }
 }
 
 // Filter step fused into the advance: test-and-set of the visited bit.
@@ -183,26 +191,50 @@ __device__ __forceinline__ bool try_visit(int32_t v, int32_t src, int32_t d,
   return true;
 }
 
-// Wave-aggregated append of the lanes in `mask` to `q` through the
-// monotone counter `total` (positions are relative to `base`).
-__device__ __forceinline__ void wave_append(uint64_t mask, int32_t v, ull* total, ull base,
-                                            int32_t* q) {
-  if (!mask) return;
-  ull pos = 0;
-  if (fg_lane() == 0) pos = atomicAdd(total, (ull)__popcll(mask));
-  pos = __shfl(pos, 0, FG_WAVE) - base;
-  if ((mask >> fg_lane()) & 1ull) q[pos + fg_mbcnt(mask)] = v;
-}
+constexpr int STAGE = 512;   // per-wave LDS staging of discovered vertices
+constexpr int DSTAGE = 128;  // per-wave LDS staging of descriptors
+
+// Entries are staged per wave in LDS and written out with one global atomic
+// per batch, so concurrent waves do not serialise on the shared counter.
+template <class T, int CAP>
+struct WaveStage {
+  T* buf;
+  int32_t cnt;
+
+  __device__ __forceinline__ void flush(ull* total, ull base, T* out) {
+    if (cnt == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    ull pos = 0;
+    if (fg_lane() == 0) pos = atomicAdd(total, (ull)cnt);
+    pos = __shfl(pos, 0, FG_WAVE) - base;
+    for (int i = fg_lane(); i < cnt; i += FG_WAVE) out[pos + i] = buf[i];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    cnt = 0;
+  }
+
+  __device__ __forceinline__ void push(bool keep, const T& x, ull* total, ull base, T* out) {
+    const uint64_t mask = __ballot(keep);
+    if (!mask) return;
+    const int32_t c = __popcll(mask);
+    if (cnt + c > CAP) flush(total, base, out);
+    if (keep) buf[cnt + fg_mbcnt(mask)] = x;
+    cnt += c;
+  }
+};
 
 struct Lds {
+  int32_t stage[PWAVES][STAGE];
+  int2 dstage[PWAVES][DSTAGE];
   // per-wave scan-gather staging (push, full grid)
   int32_t w_sc[PWAVES][FG_WAVE];
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
-  // block-level staging (small-frontier mode and the big-degree batches)
-  int32_t b_sc[BIG_BATCH + 1];
-  int32_t b_u[BIG_BATCH];
-  int32_t b_b[BIG_BATCH];
+  // block-level staging (small-frontier mode)
+  int32_t b_sc[PB];
+  int32_t b_u[PB];
+  int32_t b_b[PB];
   int64_t red[PWAVES + 1];
   int32_t red32[PWAVES + 1];
   int32_t newcnt;
@@ -225,10 +257,9 @@ __device__ __forceinline__ int32_t upper_idx(const int32_t* sc, int32_t cnt, int
   return lo;
 }
 
-// ---- push, full grid, phase A: waves take 64-entry chunks of the frontier
-// dynamically; vertices below big_deg are expanded by a wave-level scan-
-// gather (every lane handles one edge per round); the others are deferred
-// to the big list.
+// ---- push, full grid, phase A: each wave takes 64-entry chunks of the
+// frontier (static stride).  Vertices below big_deg are expanded by a
+// wave-level scan-gather; the others become CH-edge descriptors.
 __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
@@ -241,13 +272,12 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
   int32_t* sb = L.w_b[wid];
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
   int64_t insp = 0;
-  for (;;) {
-    ull c = 0;
-    if (lane == 0) c = atomicAdd(&C.chunk.v, 1ull);
-    c = __shfl(c, 0, FG_WAVE) - B.chunk;
-    const int64_t base = (int64_t)c * FG_WAVE;
-    if (base >= S.qlen) break;
+  for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
     int32_t u = 0, b = 0, deg = 0;
     if (i < S.qlen) {
@@ -257,11 +287,31 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
     }
     insp += deg;
     const bool big = deg >= P.big_deg;
-    const uint64_t bigmask = __ballot(big);
-    wave_append(bigmask, u, &C.big.v, B.big, P.big);
+    // descriptors of the high-degree lanes, written cooperatively
+    const int32_t nd = big ? (deg + CH - 1) / CH : 0;
+    const int32_t ndi = fg_wave_incl_scan(nd);
+    const int32_t ND = __shfl(ndi, FG_WAVE - 1, FG_WAVE);
+    if (ND > 0) {
+      wave_lds_fence();
+      sc[lane] = ndi - nd;
+      su[lane] = u;
+      sb[lane] = b;
+      wave_lds_fence();
+      for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
+        const int32_t t = t0 + lane;
+        int2 dsc = make_int2(0, 0);
+        if (t < ND) {
+          const int32_t j = upper_idx(sc, FG_WAVE, t);
+          dsc = make_int2(su[j], sb[j] + (t - sc[j]) * CH);
+        }
+        dst.push(t < ND, dsc, &C.desc.v, B.desc, P.desc);
+      }
+    }
+    // scan-gather of the low-degree lanes
     const int32_t d = big ? 0 : deg;
     const int32_t inc = fg_wave_incl_scan(d);
     const int32_t T = __shfl(inc, FG_WAVE - 1, FG_WAVE);
+    if (T == 0) continue;
     wave_lds_fence();
     sc[lane] = inc - d;
     su[lane] = u;
@@ -276,16 +326,19 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
         v = P.col[sb[j] + (t - sc[j])];
         won = try_visit(v, su[j], d_new, vis32, P);
       }
-      wave_append(__ballot(won), v, &C.q.v, B.q, Qout);
+      st.push(won, v, &C.q.v, B.q, Qout);
     }
   }
+  st.flush(&C.q.v, B.q, Qout);
+  dst.flush(&C.desc.v, B.desc, P.desc);
   const int64_t tot = fg_block_sum<PB>(insp, L.red);
   if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
 }
 
-// ---- push, full grid, phase B: the big list's edges are spread evenly over
-// every wave of the grid (each workgroup scans a batch's degrees in LDS).
-__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t nbig, Lds& L) {
+// ---- push, full grid, phase B: waves take descriptors in turn; the CH
+// edges of a descriptor are contiguous, so each round is one coalesced read
+// of 64 column indices and no search is needed.
+__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
@@ -295,44 +348,27 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t nbig, Lds&
   const int32_t d_new = S.k + 1;
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
-  const int32_t* bigl = P.big;  // phase A wrote entries 0..nbig-1 of this iteration
-  for (int64_t b0 = 0; b0 < nbig; b0 += BIG_BATCH) {
-    const int32_t cnt = (int32_t)((nbig - b0) < BIG_BATCH ? (nbig - b0) : BIG_BATCH);
-    // two entries per thread, then a block scan of the pair sums
-    int32_t d0 = 0, d1 = 0;
-    const int32_t j0 = 2 * threadIdx.x, j1 = j0 + 1;
-    __syncthreads();
-    if (j0 < cnt) {
-      int32_t u = bigl[b0 + j0];
-      int32_t b = P.off[u];
-      d0 = P.off[u + 1] - b;
-      L.b_u[j0] = u;
-      L.b_b[j0] = b;
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  for (int64_t i = gw; i < ndesc; i += W) {
+    const int2 dsc = P.desc[i];
+    const int32_t u = dsc.x;
+    const int32_t e_end = P.off[u + 1];
+    const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
+    // CH / 64 rounds, loads first so the rounds' reads overlap
+    int32_t vv[CH / FG_WAVE];
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t e = dsc.y + r * FG_WAVE + lane;
+      vv[r] = e < e1 ? P.col[e] : -1;
     }
-    if (j1 < cnt) {
-      int32_t u = bigl[b0 + j1];
-      int32_t b = P.off[u];
-      d1 = P.off[u + 1] - b;
-      L.b_u[j1] = u;
-      L.b_b[j1] = b;
-    }
-    int32_t total = 0;
-    const int32_t ex = fg_block_excl_scan<PB>(d0 + d1, L.red32, &total);
-    if (j0 < cnt) L.b_sc[j0] = ex;
-    if (j1 < cnt) L.b_sc[j1] = ex + d0;
-    __syncthreads();
-    for (int64_t t0 = gw * FG_WAVE; t0 < total; t0 += W * FG_WAVE) {
-      const int32_t t = (int32_t)(t0 + lane);
-      bool won = false;
-      int32_t v = 0;
-      if (t < total) {
-        const int32_t j = upper_idx(L.b_sc, cnt, t);
-        v = P.col[L.b_b[j] + (t - L.b_sc[j])];
-        won = try_visit(v, L.b_u[j], d_new, vis32, P);
-      }
-      wave_append(__ballot(won), v, &C.q.v, B.q, Qout);
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t v = vv[r];
+      const bool won = v >= 0 && try_visit(v, u, d_new, vis32, P);
+      st.push(won, v, &C.q.v, B.q, Qout);
     }
   }
+  st.flush(&C.q.v, B.q, Qout);
 }
 
 // ---- pull, full grid: each wave owns 64 consecutive vertices (one bitmap
@@ -422,6 +458,7 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S) {
 // with workgroup barriers while |Q| <= small_q and the frontier's degree sum
 // <= small_e.  Returns with S describing the next iteration; *force_full is
 // set when the degree sum was too large for iteration S.k.
+template <int MODE>
 __device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
   const int tid = threadIdx.x;
   *force_full = 0;
@@ -482,16 +519,18 @@ __device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
     S.qsel ^= 1;
     S.qlen = nq;
     S.p += nq;
-    decide(S, P);
+    decide<MODE>(S, P);
     trace_iter(S, P);
     __syncthreads();
     if (nq == 0 || S.dir != DIR_PUSH || nq > P.small_q) return;
   }
 }
 
+// MODE is FG_MODE_DO or FG_MODE_PUSH (one kernel per mode).
+template <int MODE>
 __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   __shared__ Lds L;
-  fg_grid_sync gs{&P.ctl->arrive, &P.ctl->abort_flag, gridDim.x, 0u};
+  fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
   St S = {};
   S.dir = DIR_PUSH;
   S.prevdir = DIR_PUSH;
@@ -500,10 +539,54 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   uint32_t sm_seen = 0;
   int force_full = 0;
   bool ok = true;
+  // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
+  {
+    const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * PB;
+    const int32_t src = P.src;
+    if (blockIdx.x == 0 && P.stats) {
+      uint32_t* sw = (uint32_t*)P.stats;
+      for (int i = threadIdx.x; i < (int)(sizeof(fg_run_stats) / 4); i += PB) sw[i] = 0u;
+    }
+    const bool vec = ((((uintptr_t)P.depth) | ((uintptr_t)(P.parent ? P.parent : P.depth))) & 15) == 0;
+    if (vec) {
+      const int64_t n4 = P.n / 4;
+      int4* d4 = (int4*)P.depth;
+      int4* p4 = (int4*)P.parent;
+      for (int64_t i = tid; i < n4; i += nth) {
+        const bool hit = (src >> 2) == i;
+        const int r = src & 3;
+        const int4 d = make_int4(hit && r == 0 ? 0 : -1, hit && r == 1 ? 0 : -1,
+                                 hit && r == 2 ? 0 : -1, hit && r == 3 ? 0 : -1);
+        const int4 pp = make_int4(hit && r == 0 ? src : -1, hit && r == 1 ? src : -1,
+                                  hit && r == 2 ? src : -1, hit && r == 3 ? src : -1);
+        d4[i] = d;
+        if (P.parent) p4[i] = pp;
+      }
+      for (int64_t i = n4 * 4 + tid; i < P.n; i += nth) {
+        P.depth[i] = i == src ? 0 : -1;
+        if (P.parent) P.parent[i] = i == src ? src : -1;
+      }
+    } else {
+      for (int64_t i = tid; i < P.n; i += nth) {
+        P.depth[i] = i == src ? 0 : -1;
+        if (P.parent) P.parent[i] = i == src ? src : -1;
+      }
+    }
+    uint64_t* v0 = P.vis[0];
+    for (int64_t w = tid; w < P.nwords; w += nth)
+      v0[w] = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
+    if (tid == 0) P.q[0][0] = src;
+    if (!gs.sync(&L.flag)) ok = false;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
+    P.stats->t_start = (int64_t)wall_clock64();
+    P.stats->clock_khz = P.clock_khz;
+  }
   trace_iter(S, P);
-  while (S.qlen > 0) {
+  while (ok && S.qlen > 0) {
     // backward -> forward: list the last pull's discoveries first
-    if (S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
+    if (MODE == FG_MODE_DO && S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
       bitmap_diff_to_queue(P, S);
       if (!(ok = gs.sync(&L.flag))) break;
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
@@ -513,7 +596,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       sm_seen++;
       if (blockIdx.x == 0) {
         int ff = 0;
-        small_mode(P, S, L, &ff);
+        small_mode<MODE>(P, S, L, &ff);
         if (threadIdx.x == 0) {
           BfsCtl* c = P.ctl;
           c->pub_k = S.k;
@@ -532,25 +615,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         __syncthreads();
       } else {
         if (threadIdx.x == 0) {
-          uint32_t spins = 0;
-          int bad = 0;
-          for (;;) {
-            uint32_t now = __hip_atomic_load(&P.ctl->sm_signal, __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            if ((int32_t)(now - sm_seen) >= 0) break;
-            if ((++spins & 31u) == 0 &&
-                __hip_atomic_load(&P.ctl->abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-              bad = 1;
-              break;
-            }
-            if (spins > FG_SPIN_LIMIT) {
-              __hip_atomic_store(&P.ctl->abort_flag, 1u, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-              bad = 1;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(4);
-          }
+          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 64);
           L.flag = bad;
           if (!bad) {
             const BfsCtl* c = P.ctl;
@@ -588,17 +653,16 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     force_full = 0;
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
-    if (S.dir == DIR_PUSH) {
+    if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
       push_phase_a(P, S, L);
       if (!(ok = gs.sync(&L.flag))) break;
-      const ull bt = fg_atomic_load_u64(&C.big.v);
-      const int64_t nbig = (int64_t)(bt - B.big);
-      if (nbig > 0) {
-        push_phase_b(P, S, nbig, L);
+      const ull dt = fg_atomic_load_u64(&C.desc.v);
+      const int64_t ndesc = (int64_t)(dt - B.desc);
+      if (ndesc > 0) {
+        push_phase_b(P, S, ndesc, L);
         if (!(ok = gs.sync(&L.flag))) break;
       }
-      B.big = bt;
-      B.chunk = fg_atomic_load_u64(&C.chunk.v);
+      B.desc = dt;
       S.qsel ^= 1;
     } else {
       pull_phase(P, S, L);
@@ -617,7 +681,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     S.k++;
     S.qlen = nq;
     S.p += nq;
-    decide(S, P);
+    decide<MODE>(S, P);
     trace_iter(S, P);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
@@ -628,6 +692,18 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     st->edges_inspected = S.insp_sum;
     st->direction_switches = S.switches;
     st->grid_blocks = (int32_t)gridDim.x;
+  }
+  // the last workgroup out clears the control block for the next launch
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(&P.ctl->exit_count, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    L.flag = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (L.flag) {
+    uint32_t* w = (uint32_t*)P.ctl;
+    for (int i = threadIdx.x; i < (int)(sizeof(BfsCtl) / 4); i += PB) w[i] = 0u;
   }
 }
 
@@ -681,7 +757,7 @@ struct BfsLayout {
   BfsCtl* ctl;
   uint64_t* vis[2];
   int32_t* q[2];
-  int32_t* big;
+  int2* desc;
   size_t bytes;
 };
 
@@ -693,23 +769,26 @@ BfsLayout bfs_layout(const fg_graph* g, void* ws) {
   L.vis[1] = c.take<uint64_t>(g->nwords);
   L.q[0] = c.take<int32_t>(g->n);
   L.q[1] = c.take<int32_t>(g->n);
-  L.big = c.take<int32_t>(g->n);
+  L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
   L.bytes = c.used;
   return L;
 }
 
-int g_occupancy[64];
+int g_occupancy[2][64];
 
+template <int MODE>
 int persistent_blocks_per_cu(int device) {
   if (device < 0 || device >= 64) return 1;
-  if (g_occupancy[device] == 0) {
+  int& occ = g_occupancy[MODE == FG_MODE_DO ? 0 : 1][device];
+  if (occ == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_persistent, PB, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_persistent<MODE>, PB, 0) !=
+            hipSuccess ||
         nb < 1)
       nb = 1;
-    g_occupancy[device] = nb;
+    occ = nb;
   }
-  return g_occupancy[device];
+  return occ;
 }
 
 }  // namespace
@@ -758,7 +837,8 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   FG_HIP_TRY(hipGetDevice(&dev));
   fg_device_props pr = fg_props(dev);
   if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_bfs: device lacks cooperative launch");
-  int bpc = persistent_blocks_per_cu(dev);
+  int bpc = o.mode == FG_MODE_DO ? persistent_blocks_per_cu<FG_MODE_DO>(dev)
+                                 : persistent_blocks_per_cu<FG_MODE_PUSH>(dev);
   if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
   if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
   const int grid = pr.cus * bpc;
@@ -780,7 +860,7 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   P.vis[1] = lay.vis[1];
   P.q[0] = lay.q[0];
   P.q[1] = lay.q[1];
-  P.big = lay.big;
+  P.desc = lay.desc;
   P.ctl = lay.ctl;
   P.stats = stats;
   P.a_num = o.do_a_num;
@@ -791,11 +871,11 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   if (P.small_q > PB) P.small_q = PB;
   P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
+  P.clock_khz = pr.clock_khz;
 
-  fg_bfs_launch_init(g, src, depth, parent, lay.vis[0], lay.q[0], stats, s, lay.ctl,
-                     (int32_t)sizeof(BfsCtl));
   void* args[] = {&P};
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_persistent, dim3(grid), dim3(PB), args,
-                                        0, s));
+  const void* fn = o.mode == FG_MODE_DO ? (const void*)bfs_persistent<FG_MODE_DO>
+                                        : (const void*)bfs_persistent<FG_MODE_PUSH>;
+  FG_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PB), args, 0, s));
   return FG_OK;
 }

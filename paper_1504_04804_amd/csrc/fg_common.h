@@ -51,6 +51,7 @@ fg_status fg_bfs_unfused(const fg_graph* g, int32_t src, void* ws, size_t ws_byt
 struct fg_device_props {
   int cus;
   int coop;
+  int clock_khz;  // device wall clock (wall_clock64) rate
 };
 fg_device_props fg_props(int device);
 
@@ -107,45 +108,77 @@ __device__ __forceinline__ unsigned long long fg_atomic_load_u64(const unsigned 
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Device-wide barrier for cooperative (co-resident) launches.  `arrive` is a
-// monotonically increasing arrival counter that starts at zero for the
-// launch; `abort_flag` lets any workgroup stop the whole grid.  The wait is
-// bounded: after `FG_SPIN_LIMIT` polls the grid is aborted, so every
-// workgroup leaves the kernel even if co-residency were ever violated.
+// Bounded wait: poll `*p` (relaxed, no cache invalidation per poll) until
+// (int32)(*p - target) >= 0, then one agent-scope acquire fence.  Gives up
+// when `abort_flag` is set or after FG_SPIN_LIMIT polls (then sets it), so
+// every workgroup leaves the kernel even if a peer never arrives.
 #define FG_SPIN_LIMIT (1u << 24)
 
-struct fg_grid_sync {
-  uint32_t* arrive;
-  uint32_t* abort_flag;
-  uint32_t nblocks;
-  uint32_t count;  // barriers passed by this workgroup
+__device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
+                                            uint32_t* abort_flag, int sleep_cycles) {
+  uint32_t spins = 0;
+  for (;;) {
+    uint32_t now = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int32_t)(now - target) >= 0) break;
+    if ((++spins & 31u) == 0 &&
+        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
+    if (spins > FG_SPIN_LIMIT) {
+      __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if (sleep_cycles > 8) __builtin_amdgcn_s_sleep(8);
+    else __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
 
-  // Returns false if the grid was aborted.  Must be called by every thread
-  // of every workgroup the same number of times.
+// Device-wide barrier for cooperative (co-resident) launches, two levels:
+// workgroups arrive at their group's counter (groups of FG_BAR_GROUP
+// consecutive workgroups); the last arrival of a group arrives at the global
+// counter, waits for every group, then releases its group through the
+// group's flag.  All counters are monotone (barrier c completes when they
+// reach c times the number of arrivals) and start at zero for the launch.
+// `ctl` must hold FG_BAR_WORDS 32-bit words, one 256-byte line per counter.
+#define FG_BAR_GROUP 32
+#define FG_BAR_STRIDE 64  // words between counters (256 bytes)
+#define FG_BAR_MAXG 32
+#define FG_BAR_WORDS (FG_BAR_STRIDE * (2 * FG_BAR_MAXG + 2))
+
+struct fg_grid_sync {
+  uint32_t* ctl;       // [0] global arrivals, [1] abort, then per-group pairs
+  uint32_t nblocks;
+  uint32_t count;      // barriers passed by this workgroup
+
+  __device__ uint32_t* abort_flag() const { return ctl + FG_BAR_STRIDE; }
+  __device__ uint32_t* group_arrive(uint32_t g) const { return ctl + FG_BAR_STRIDE * (2 + 2 * g); }
+  __device__ uint32_t* group_release(uint32_t g) const {
+    return ctl + FG_BAR_STRIDE * (3 + 2 * g);
+  }
+
+  // Returns false if the grid was aborted.  Every thread of every workgroup
+  // must call it the same number of times.
   __device__ bool sync(int* s_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
       count++;
-      const uint32_t target = count * nblocks;
-      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t spins = 0;
-      int bad = 0;
-      for (;;) {
-        uint32_t now = __hip_atomic_load(arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if ((int32_t)(now - target) >= 0) break;
-        if ((++spins & 31u) == 0 &&
-            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          bad = 1;
-          break;
-        }
-        if (spins > FG_SPIN_LIMIT) {
-          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          bad = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+      const uint32_t g = blockIdx.x / FG_BAR_GROUP;
+      const uint32_t ngroups = (nblocks + FG_BAR_GROUP - 1) / FG_BAR_GROUP;
+      const uint32_t gsize = (g + 1 < ngroups) ? FG_BAR_GROUP : nblocks - g * FG_BAR_GROUP;
+      int ok = 1;
+      const uint32_t old = __hip_atomic_fetch_add(group_arrive(g), 1u, __ATOMIC_RELEASE,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if (old == count * gsize - 1) {
+        // last of its group: global level
+        __hip_atomic_fetch_add(ctl, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ok = fg_wait_geq(ctl, count * ngroups, abort_flag(), 1);
+        if (ok)
+          __hip_atomic_store(group_release(g), count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = fg_wait_geq(group_release(g), count, abort_flag(), 1);
       }
-      *s_flag = bad;
+      *s_flag = !ok;
     }
     __syncthreads();
     return *s_flag == 0;
