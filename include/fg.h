@@ -183,6 +183,35 @@ fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
                  void* ws, size_t ws_bytes, int32_t* depth, int32_t* parent,
                  fg_run_stats* stats, void* stream);
 
+/* -------------------------------------------------------------------- SSSP */
+
+typedef struct {
+  int32_t small_frontier; /* single-workgroup iterations while |F| <= this (0 = default) */
+  int32_t small_edges;    /* ... and sum of degrees <= this (0 = default)     */
+  int32_t big_degree;     /* vertices of at least this degree are relaxed by
+                             the whole grid (0 = default)                     */
+  int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
+} fg_sssp_opts;
+
+void fg_sssp_opts_default(fg_sssp_opts* opts);
+
+/*
+ * Single-source shortest paths with the graph's uint32 weights (Table I's
+ * SSSP primitive; weights are non-negative integers, Sec. VII-A).  A
+ * frontier traversal whose advance relaxes every out-edge of the frontier
+ * (Bellman-Ford frontier form); converges when no distance improves.
+ * dist: device uint32[n], receives the shortest-path weight from src or
+ * UINT32_MAX if unreachable.  parent: device int32[n] or NULL; receives the
+ * smallest-id u with an edge u->v and dist[u] + w(u,v) == dist[v]
+ * (parent[src] = src, -1 if unreachable), which is unique.  ws: at least
+ * fg_workspace_bytes(g, FG_PRIM_SSSP, 0) bytes.  Errors: FG_EINVAL (graph
+ * without weights, src out of range, NULL dist / ws), FG_ENOMEM,
+ * FG_EDEVICE; stats->status = FG_EOVERFLOW if a distance reaches 2^32 - 1.
+ */
+fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts* opts, void* ws,
+                  size_t ws_bytes, uint32_t* dist, int32_t* parent, fg_run_stats* stats,
+                  void* stream);
+
 /* ----------------------------------------------------------- BFS operators */
 
 /*

@@ -71,6 +71,15 @@ class BfsOpts(ctypes.Structure):
     ]
 
 
+class SsspOpts(ctypes.Structure):
+    _fields_ = [
+        ("small_frontier", ctypes.c_int32),
+        ("small_edges", ctypes.c_int32),
+        ("big_degree", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+    ]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -99,6 +108,8 @@ SIGNATURES = {
     "fg_stats_read": (_I32, [_P, ctypes.POINTER(RunStats), _P]),
     "fg_bfs_opts_default": (None, [ctypes.POINTER(BfsOpts)]),
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
+    "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _I64, _P, _P, _SZ, _P]),
     "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
@@ -244,6 +255,33 @@ def bfs(g, src, mode=FG_MODE_DO, parents=True, opts=None, **kw):
     bfs_into(g, src, depth, parent, o, stats=stats)
     st = read_stats(stats)
     return depth, parent, st
+
+
+def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0):
+    o = SsspOpts()
+    lib().fg_sssp_opts_default(ctypes.byref(o))
+    o.small_frontier, o.small_edges = small_frontier, small_edges
+    o.big_degree, o.blocks_per_cu = big_degree, blocks_per_cu
+    return o
+
+
+def sssp_into(g, src, dist, parent=None, opts=None, ws=None, stats=None, stream=None):
+    """Enqueue fg_sssp on `stream` into caller-provided device tensors."""
+    ws = ws if ws is not None else g.workspace(FG_PRIM_SSSP)
+    _check(lib().fg_sssp(g.handle, int(src), ctypes.byref(opts) if opts is not None else None,
+                         _ptr(ws), ws.numel(), _ptr(dist), _ptr(parent), _ptr(stats),
+                         _stream(stream)))
+
+
+def sssp(g, src, parents=True, opts=None, **kw):
+    """Run one SSSP; returns (dist as int64 tensor, parent or None, RunStats)."""
+    dev = g.off.device
+    dist = torch.empty(g.n, dtype=torch.int32, device=dev)  # uint32 bits
+    parent = torch.empty(g.n, dtype=torch.int32, device=dev) if parents else None
+    stats = new_stats(dev)
+    sssp_into(g, src, dist, parent, opts if opts is not None else sssp_opts(**kw), stats=stats)
+    st = read_stats(stats)
+    return dist.to(torch.int64) & 0xFFFFFFFF, parent, st
 
 
 def advance(g, frontier, capacity=None, ws=None):

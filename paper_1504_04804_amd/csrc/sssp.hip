@@ -1,0 +1,579 @@
+// Single-source shortest paths with non-negative integer weights (Table I:
+// SSSP is a frontier traversal whose advance relaxes edges, W in O(b|E_i|)).
+//
+// Frontier Bellman-Ford on one GPU in one cooperative launch.  Each vertex
+// keeps a packed 64-bit key (distance << 32 | predecessor); a relaxation is
+// one 64-bit atomicMin, so at convergence the key holds the shortest
+// distance and the smallest-id tight predecessor (every tight predecessor
+// relaxes the vertex with its final distance once, and only tight ones can
+// produce the final distance).  A vertex whose distance strictly improved
+// joins the next frontier once, through a test-and-set membership bitmap.
+//
+// Load balance, small-frontier mode and the barrier follow the BFS push
+// kernel.  Data layout in HBM (caller workspace, 256-B aligned):
+//   key     uint64[n]                 packed distance / predecessor
+//   inq     2 x uint32[ceil(n/32)]    membership of the next frontier
+//   queue   2 x int32[n]              input / output frontier
+//   desc    int2[m/CH + n + 64]       edge-chunk descriptors
+//   control barrier, counters, small-frontier hand-back state
+#include <string.h>
+
+#include "frontier.h"
+
+namespace {
+using namespace fgk;
+
+constexpr int PB = 1024;
+constexpr int PWAVES = PB / FG_WAVE;
+constexpr int CH = 256;
+constexpr int STAGE = 512;
+constexpr int DSTAGE = 128;
+constexpr int32_t DEF_SMALL_Q = 1024;
+constexpr int64_t DEF_SMALL_E = 4096;
+constexpr int32_t DEF_BIG_DEG = 64;
+constexpr ull KEY_INF = ~0ull;
+
+struct CtrSlot {
+  Line64 q;
+  Line64 desc;
+  Line64 insp;
+};
+
+// Zero when a launch starts (fresh workspaces are zero-filled; the last
+// workgroup of each launch clears it again).
+struct alignas(256) SsspCtl {
+  uint32_t bar[FG_BAR_WORDS];
+  uint32_t sm_signal;
+  uint32_t pad0[63];
+  uint32_t exit_count;
+  uint32_t pad1[63];
+  uint32_t overflow;
+  uint32_t pad2[63];
+  Line64 reached;
+  CtrSlot slot[2];
+  int32_t pub_k, pub_qsel, pub_force;
+  int64_t pub_qlen, pub_insp_sum;
+};
+
+struct SsspParams {
+  const int32_t* __restrict__ off;
+  const int32_t* __restrict__ col;
+  const uint32_t* __restrict__ w;
+  int32_t n;
+  int32_t nw32;  // ceil(n / 32)
+  int32_t src;
+  uint32_t* dist;
+  int32_t* parent;
+  ull* key;
+  uint32_t* inq[2];
+  int32_t* q[2];
+  int2* desc;
+  SsspCtl* ctl;
+  fg_run_stats* stats;
+  int32_t small_q;
+  int64_t small_e;
+  int32_t big_deg;
+  int32_t clock_khz;
+};
+
+struct St {
+  int32_t k;
+  int32_t qsel;
+  int64_t qlen;
+  int64_t insp_sum;
+  ull b0q, b0desc, b0insp;
+  ull b1q, b1desc, b1insp;
+};
+
+struct Bases {
+  ull q, desc, insp;
+};
+
+__device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
+  const ull m = 0ull - (ull)odd;
+  return (a1 & m) | (a0 & ~m);
+}
+__device__ __forceinline__ Bases get_bases(const St& S) {
+  const bool odd = S.k & 1;
+  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1desc, S.b0desc), sel(odd, S.b1insp, S.b0insp)};
+}
+__device__ __forceinline__ void set_bases(St& S, const Bases& b) {
+  const bool odd = S.k & 1;
+  S.b1q = sel(odd, b.q, S.b1q);
+  S.b1desc = sel(odd, b.desc, S.b1desc);
+  S.b1insp = sel(odd, b.insp, S.b1insp);
+  S.b0q = sel(odd, S.b0q, b.q);
+  S.b0desc = sel(odd, S.b0desc, b.desc);
+  S.b0insp = sel(odd, S.b0insp, b.insp);
+}
+
+struct Lds {
+  int32_t stage[PWAVES][STAGE];
+  int2 dstage[PWAVES][DSTAGE];
+  int32_t w_sc[PWAVES][FG_WAVE];
+  int32_t w_u[PWAVES][FG_WAVE];
+  int32_t w_b[PWAVES][FG_WAVE];
+  uint32_t w_d[PWAVES][FG_WAVE];
+  int32_t b_sc[PB];
+  int32_t b_u[PB];
+  int32_t b_b[PB];
+  uint32_t b_d[PB];
+  int64_t red[PWAVES + 1];
+  int32_t red32[PWAVES + 1];
+  int32_t newcnt;
+  int32_t flag;
+  int64_t bcast[8];
+};
+
+__device__ __forceinline__ void trace_iter(const St& S, const SsspParams& P) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && S.k < FG_TRACE_MAX) {
+    P.stats->dir[S.k] = 0;
+    P.stats->frontier[S.k] = S.qlen;
+  }
+}
+
+__device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const SsspParams& P) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && k < FG_TRACE_MAX) {
+    P.stats->inspected[k] = insp;
+    P.stats->t_end[k] = (int64_t)wall_clock64();
+  }
+}
+
+// Relax v through u with candidate distance du + wt.  Returns true when v's
+// distance strictly improved and v was not yet in the next frontier.
+__device__ __forceinline__ bool relax(int32_t v, int32_t u, uint32_t du, uint32_t wt,
+                                      uint32_t* inq_next, const SsspParams& P) {
+  const ull nd = (ull)du + (ull)wt;
+  if (nd >= 0xFFFFFFFFull) {
+    P.ctl->overflow = 1u;  // distance does not fit the uint32 output
+    return false;
+  }
+  const ull nk = (nd << 32) | (ull)(uint32_t)u;
+  // the source keeps (0, src): with zero-weight edges a neighbour at
+  // distance 0 would otherwise replace its predecessor
+  if (v == P.src || nk >= P.key[v]) return false;  // plain pre-check; keys only decrease
+  const ull old = atomicMin(&P.key[v], nk);
+  if (nd >= (old >> 32)) return false;  // no distance improvement (maybe a better parent)
+  const uint32_t bit = 1u << (v & 31);
+  const uint32_t o = atomicOr(&inq_next[v >> 5], bit);
+  return !(o & bit);
+}
+
+// Full grid, phase A: 64-entry frontier chunks per wave; low-degree vertices
+// by scan-gather, high-degree ones into CH-edge descriptors.  Each frontier
+// vertex also clears its word of the current membership bitmap (every bit
+// set there belongs to a current frontier vertex, and nothing sets bits in
+// it during this iteration).
+__device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int32_t* Qin = P.q[S.qsel];
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  uint32_t* inq_cur = P.inq[S.k & 1];
+  uint32_t* inq_nxt = P.inq[(S.k + 1) & 1];
+  int32_t* sc = L.w_sc[wid];
+  int32_t* su = L.w_u[wid];
+  int32_t* sb = L.w_b[wid];
+  uint32_t* sd = L.w_d[wid];
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  const Bases B = get_bases(S);
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  int64_t insp = 0;
+  for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
+    const int64_t i = base + lane;
+    int32_t u = 0, b = 0, deg = 0;
+    uint32_t du = 0;
+    if (i < S.qlen) {
+      u = Qin[i];
+      b = P.off[u];
+      deg = P.off[u + 1] - b;
+      du = (uint32_t)(P.key[u] >> 32);
+      inq_cur[u >> 5] = 0u;
+    }
+    insp += deg;
+    const bool big = deg >= P.big_deg;
+    const int32_t nd = big ? (deg + CH - 1) / CH : 0;
+    const int32_t ndi = fg_wave_incl_scan(nd);
+    const int32_t ND = __shfl(ndi, FG_WAVE - 1, FG_WAVE);
+    if (ND > 0) {
+      wave_lds_fence();
+      sc[lane] = ndi - nd;
+      su[lane] = u;
+      sb[lane] = b;
+      wave_lds_fence();
+      for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
+        const int32_t t = t0 + lane;
+        int2 dsc = make_int2(0, 0);
+        if (t < ND) {
+          const int32_t j = upper_idx(sc, FG_WAVE, t);
+          dsc = make_int2(su[j], sb[j] + (t - sc[j]) * CH);
+        }
+        dst.push(t < ND, dsc, &C.desc.v, B.desc, P.desc);
+      }
+    }
+    const int32_t d = big ? 0 : deg;
+    const int32_t inc = fg_wave_incl_scan(d);
+    const int32_t T = __shfl(inc, FG_WAVE - 1, FG_WAVE);
+    if (T == 0) continue;
+    wave_lds_fence();
+    sc[lane] = inc - d;
+    su[lane] = u;
+    sb[lane] = b;
+    sd[lane] = du;
+    wave_lds_fence();
+    for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
+      const int32_t t = t0 + lane;
+      bool won = false;
+      int32_t v = 0;
+      if (t < T) {
+        const int32_t j = upper_idx(sc, FG_WAVE, t);
+        const int32_t e = sb[j] + (t - sc[j]);
+        v = P.col[e];
+        won = relax(v, su[j], sd[j], P.w[e], inq_nxt, P);
+      }
+      st.push(won, v, &C.q.v, B.q, Qout);
+    }
+  }
+  st.flush(&C.q.v, B.q, Qout);
+  dst.flush(&C.desc.v, B.desc, P.desc);
+  const int64_t tot = fg_block_sum<PB>(insp, L.red);
+  if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
+}
+
+// Full grid, phase B: descriptors taken by every wave in turn.
+__device__ void phase_b(const SsspParams& P, const St& S, int64_t ndesc, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  uint32_t* inq_nxt = P.inq[(S.k + 1) & 1];
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  const Bases B = get_bases(S);
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  for (int64_t i = gw; i < ndesc; i += W) {
+    const int2 dsc = P.desc[i];
+    const int32_t u = dsc.x;
+    const int32_t e_end = P.off[u + 1];
+    const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
+    const uint32_t du = (uint32_t)(P.key[u] >> 32);
+    int32_t vv[CH / FG_WAVE];
+    uint32_t ww[CH / FG_WAVE];
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t e = dsc.y + r * FG_WAVE + lane;
+      vv[r] = e < e1 ? P.col[e] : -1;
+      ww[r] = e < e1 ? P.w[e] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t v = vv[r];
+      const bool won = v >= 0 && relax(v, u, du, ww[r], inq_nxt, P);
+      st.push(won, v, &C.q.v, B.q, Qout);
+    }
+  }
+  st.flush(&C.q.v, B.q, Qout);
+}
+
+// Workgroup 0 alone while the frontier is small (see the BFS kernel).
+__device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) {
+  const int tid = threadIdx.x;
+  *force_full = 0;
+  for (;;) {
+    const int32_t* Qin = P.q[S.qsel];
+    int32_t* Qout = P.q[S.qsel ^ 1];
+    uint32_t* inq_cur = P.inq[S.k & 1];
+    uint32_t* inq_nxt = P.inq[(S.k + 1) & 1];
+    int64_t s = 0;
+    for (int64_t i = tid; i < S.qlen; i += PB) {
+      const int32_t u = Qin[i];
+      s += P.off[u + 1] - P.off[u];
+    }
+    const int64_t sum = fg_block_sum<PB>(s, L.red);
+    if (sum > P.small_e) {
+      *force_full = 1;
+      return;
+    }
+    if (tid == 0) L.newcnt = 0;
+    for (int64_t c0 = 0; c0 < S.qlen; c0 += PB) {
+      const int64_t i = c0 + tid;
+      int32_t u = 0, b = 0, d = 0;
+      uint32_t du = 0;
+      if (i < S.qlen) {
+        u = Qin[i];
+        b = P.off[u];
+        d = P.off[u + 1] - b;
+        du = (uint32_t)(P.key[u] >> 32);
+        inq_cur[u >> 5] = 0u;
+      }
+      int32_t T = 0;
+      const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &T);
+      L.b_sc[tid] = ex;
+      L.b_u[tid] = u;
+      L.b_b[tid] = b;
+      L.b_d[tid] = du;
+      __syncthreads();
+      const int32_t cnt = (int32_t)((S.qlen - c0) < PB ? (S.qlen - c0) : PB);
+      for (int32_t t0 = 0; t0 < T; t0 += PB) {
+        const int32_t t = t0 + tid;
+        bool won = false;
+        int32_t v = 0;
+        if (t < T) {
+          const int32_t j = upper_idx(L.b_sc, cnt, t);
+          const int32_t e = L.b_b[j] + (t - L.b_sc[j]);
+          v = P.col[e];
+          won = relax(v, L.b_u[j], L.b_d[j], P.w[e], inq_nxt, P);
+        }
+        const uint64_t mask = __ballot(won);
+        if (mask) {
+          int32_t pos = 0;
+          if (fg_lane() == 0) pos = atomicAdd(&L.newcnt, __popcll(mask));
+          pos = __shfl(pos, 0, FG_WAVE);
+          if (won) Qout[pos + fg_mbcnt(mask)] = v;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t nq = L.newcnt;
+    trace_insp(S.k, sum, P);
+    S.insp_sum += sum;
+    S.k++;
+    S.qsel ^= 1;
+    S.qlen = nq;
+    trace_iter(S, P);
+    __syncthreads();
+    if (nq == 0 || nq > P.small_q) return;
+  }
+}
+
+__global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
+  __shared__ Lds L;
+  fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
+  St S = {};
+  S.qlen = 1;
+  uint32_t sm_seen = 0;
+  int force_full = 0;
+  bool ok = true;
+  const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * PB;
+  // init: every key infinite except the source, membership bitmaps clear
+  if (blockIdx.x == 0 && P.stats) {
+    uint32_t* sw = (uint32_t*)P.stats;
+    for (int i = threadIdx.x; i < (int)(sizeof(fg_run_stats) / 4); i += PB) sw[i] = 0u;
+  }
+  for (int64_t v = tid; v < P.n; v += nth)
+    P.key[v] = v == P.src ? (ull)(uint32_t)P.src : KEY_INF;
+  for (int64_t i = tid; i < P.nw32; i += nth) {
+    P.inq[0][i] = 0u;
+    P.inq[1][i] = 0u;
+  }
+  if (tid == 0) P.q[0][0] = P.src;
+  if (!gs.sync(&L.flag)) ok = false;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
+    P.stats->t_start = (int64_t)wall_clock64();
+    P.stats->clock_khz = P.clock_khz;
+  }
+  trace_iter(S, P);
+  while (ok && S.qlen > 0) {
+    if (!force_full && S.qlen <= P.small_q) {
+      sm_seen++;
+      if (blockIdx.x == 0) {
+        int ff = 0;
+        small_mode(P, S, L, &ff);
+        if (threadIdx.x == 0) {
+          SsspCtl* c = P.ctl;
+          c->pub_k = S.k;
+          c->pub_qsel = S.qsel;
+          c->pub_force = ff;
+          c->pub_qlen = S.qlen;
+          c->pub_insp_sum = S.insp_sum;
+          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        force_full = ff;
+        __syncthreads();
+      } else {
+        if (threadIdx.x == 0) {
+          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 64);
+          L.flag = bad;
+          if (!bad) {
+            const SsspCtl* c = P.ctl;
+            L.bcast[0] = c->pub_k;
+            L.bcast[1] = c->pub_qsel;
+            L.bcast[2] = c->pub_force;
+            L.bcast[3] = c->pub_qlen;
+            L.bcast[4] = c->pub_insp_sum;
+          }
+        }
+        __syncthreads();
+        if (L.flag) {
+          ok = false;
+          break;
+        }
+        S.k = (int32_t)L.bcast[0];
+        S.qsel = (int32_t)L.bcast[1];
+        force_full = (int)L.bcast[2];
+        S.qlen = L.bcast[3];
+        S.insp_sum = L.bcast[4];
+        __syncthreads();
+      }
+      continue;
+    }
+    force_full = 0;
+    CtrSlot& C = P.ctl->slot[S.k & 1];
+    Bases B = get_bases(S);
+    phase_a(P, S, L);
+    if (!(ok = gs.sync(&L.flag))) break;
+    const ull dt = fg_atomic_load_u64(&C.desc.v);
+    const int64_t ndesc = (int64_t)(dt - B.desc);
+    if (ndesc > 0) {
+      phase_b(P, S, ndesc, L);
+      if (!(ok = gs.sync(&L.flag))) break;
+    }
+    B.desc = dt;
+    const ull qt = fg_atomic_load_u64(&C.q.v);
+    const ull it = fg_atomic_load_u64(&C.insp.v);
+    const int64_t nq = (int64_t)(qt - B.q);
+    const int64_t insp = (int64_t)(it - B.insp);
+    B.q = qt;
+    B.insp = it;
+    set_bases(S, B);
+    trace_insp(S.k, insp, P);
+    S.insp_sum += insp;
+    S.k++;
+    S.qsel ^= 1;
+    S.qlen = nq;
+    trace_iter(S, P);
+  }
+  // unpack keys into the outputs, count reached vertices
+  int32_t reached = 0;
+  if (ok) {
+    for (int64_t v = tid; v < P.n; v += nth) {
+      const ull kk = P.key[v];
+      const bool r = kk != KEY_INF;
+      P.dist[v] = r ? (uint32_t)(kk >> 32) : 0xFFFFFFFFu;
+      if (P.parent) P.parent[v] = r ? (int32_t)(uint32_t)kk : -1;
+      reached += r;
+    }
+  }
+  const int32_t rb = fg_block_sum<PB>(reached, L.red32);
+  if (threadIdx.x == 0 && rb) atomicAdd(&P.ctl->reached.v, (ull)rb);
+  const bool ok2 = gs.sync(&L.flag);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
+    fg_run_stats* stt = P.stats;
+    const uint32_t ovf = __hip_atomic_load(&P.ctl->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    stt->status = (ok && ok2) ? (ovf ? FG_EOVERFLOW : FG_OK) : FG_EDEVICE;
+    stt->iterations = S.k;
+    stt->reached = (int64_t)fg_atomic_load_u64(&P.ctl->reached.v);
+    stt->edges_inspected = S.insp_sum;
+    stt->grid_blocks = (int32_t)gridDim.x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(&P.ctl->exit_count, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    L.flag = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (L.flag) {
+    uint32_t* w = (uint32_t*)P.ctl;
+    for (int i = threadIdx.x; i < (int)(sizeof(SsspCtl) / 4); i += PB) w[i] = 0u;
+  }
+}
+
+struct SsspLayout {
+  SsspCtl* ctl;
+  ull* key;
+  uint32_t* inq[2];
+  int32_t* q[2];
+  int2* desc;
+  size_t bytes;
+};
+
+SsspLayout sssp_layout(const fg_graph* g, void* ws) {
+  fg_carver c(ws);
+  SsspLayout L;
+  L.ctl = c.take<SsspCtl>(1);
+  L.key = c.take<ull>(g->n);
+  const size_t nw32 = ((size_t)g->n + 31) / 32;
+  L.inq[0] = c.take<uint32_t>(nw32);
+  L.inq[1] = c.take<uint32_t>(nw32);
+  L.q[0] = c.take<int32_t>(g->n);
+  L.q[1] = c.take<int32_t>(g->n);
+  L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
+  L.bytes = c.used;
+  return L;
+}
+
+int g_sssp_occ[64];
+
+}  // namespace
+
+size_t fg_sssp_workspace_bytes(const fg_graph* g) { return sssp_layout(g, nullptr).bytes; }
+
+extern "C" void fg_sssp_opts_default(fg_sssp_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+}
+
+extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts* opts, void* ws,
+                             size_t ws_bytes, uint32_t* dist, int32_t* parent,
+                             fg_run_stats* stats, void* stream) {
+  if (!g) return fg_set_error(FG_EINVAL, "fg_sssp: graph is NULL");
+  if (src < 0 || src >= g->n)
+    return fg_set_error(FG_EINVAL, "fg_sssp: src=%d outside [0, %d)", src, g->n);
+  if (!dist) return fg_set_error(FG_EINVAL, "fg_sssp: dist is NULL");
+  if (!ws) return fg_set_error(FG_EINVAL, "fg_sssp: workspace is NULL");
+  if (!g->w) return fg_set_error(FG_EINVAL, "fg_sssp: the graph was loaded without weights");
+  fg_sssp_opts o;
+  if (opts) o = *opts; else fg_sssp_opts_default(&o);
+  SsspLayout lay = sssp_layout(g, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_sssp: workspace of %zu bytes < required %zu", ws_bytes,
+                        lay.bytes);
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  fg_device_props pr = fg_props(dev);
+  if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_sssp: device lacks cooperative launch");
+  if (dev >= 0 && dev < 64 && g_sssp_occ[dev] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sssp_persistent, PB, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_sssp_occ[dev] = nb;
+  }
+  int bpc = (dev >= 0 && dev < 64) ? g_sssp_occ[dev] : 1;
+  if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
+  if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
+  const int grid = pr.cus * bpc;
+
+  SsspParams P;
+  memset(&P, 0, sizeof(P));
+  P.off = g->off;
+  P.col = g->col;
+  P.w = g->w;
+  P.n = g->n;
+  P.nw32 = (int32_t)(((int64_t)g->n + 31) / 32);
+  P.src = src;
+  P.dist = dist;
+  P.parent = parent;
+  P.key = lay.key;
+  P.inq[0] = lay.inq[0];
+  P.inq[1] = lay.inq[1];
+  P.q[0] = lay.q[0];
+  P.q[1] = lay.q[1];
+  P.desc = lay.desc;
+  P.ctl = lay.ctl;
+  P.stats = stats;
+  P.small_q = o.small_frontier > 0 ? o.small_frontier : DEF_SMALL_Q;
+  if (P.small_q > PB) P.small_q = PB;
+  P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
+  P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
+  P.clock_khz = pr.clock_khz;
+  void* args[] = {&P};
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)sssp_persistent, dim3(grid), dim3(PB), args,
+                                        0, (hipStream_t)stream));
+  return FG_OK;
+}

@@ -1,0 +1,116 @@
+"""Parity of the HIP SSSP path with the oracle's Dijkstra: distances and the
+canonical (smallest-id tight) parents must match bit-exactly."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import announce, gpu, need_gpu, to_np
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def fg():
+    need_gpu()
+    import paper_1504_04804_amd as fg
+    fg.lib()
+    return fg
+
+
+def check(fg, orc, g, off, col, w, src, **kw):
+    announce(f"sssp n={len(off)-1} m={len(col)} src={src} {kw}")
+    dist, parent, st = fg.sssp(g, src, **kw)
+    d = to_np(dist).astype(np.uint32)
+    p = to_np(parent)
+    wd, wp = orc.dijkstra(off, col, w, src)
+    assert st.status == 0
+    assert np.array_equal(d, wd), f"dist mismatch at {np.flatnonzero(d != wd)[:10]}"
+    assert np.array_equal(p, wp), f"parent mismatch at {np.flatnonzero(p != wp)[:10]}"
+    assert orc.check_sssp(off, col, w, src, d, p) is None
+    assert st.reached == int((wd != 0xFFFFFFFF).sum())
+    return st
+
+
+@pytest.mark.parametrize("scale", [10, 12, 16])
+def test_rmat_weighted(fg, orc, scale):
+    off, col = synth.rmat_csr(scale)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    for s in [0] + list(synth.sources(off, 3, seed=scale)):
+        check(fg, orc, g, off, col, w, int(s))
+    check(fg, orc, g, off, col, w, 0, small_frontier=1, small_edges=1)
+    check(fg, orc, g, off, col, w, 0, big_degree=2)
+
+
+def test_closed_forms(fg, orc):
+    n = 200
+    off, col = synth.from_edge_pairs(n, [(i, i + 1) for i in range(n - 1)])
+    wt = np.arange(1, n, dtype=np.uint32)
+    w = np.array([wt[min(u, col[k])] for u in range(n) for k in range(off[u], off[u + 1])], np.uint32)
+    g = fg.Graph(off, col, weights=w)
+    st = check(fg, orc, g, off, col, w, 0)
+    R, C = 40, 50
+    off, col = synth.grid_csr(R, C)
+    w = np.full(len(col), 7, np.uint32)
+    g = fg.Graph(off, col, weights=w)
+    dist, parent, st = fg.sssp(g, 0)
+    d = to_np(dist)
+    assert d.tolist() == [7 * (r + c) for r in range(R) for c in range(C)]
+    check(fg, orc, g, off, col, w, R * C // 2 + 7)
+
+
+def test_zero_weights_and_isolated(fg, orc):
+    off, col = synth.rmat_csr(11)
+    w = synth.weights(off, col) % 3  # many zero weights (symmetric)
+    g = fg.Graph(off, col, weights=w)
+    for s in (0, 17):
+        check(fg, orc, g, off, col, w, s)
+    off, col = synth.from_edge_pairs(6, [(0, 1), (1, 2)])
+    w = np.ones(len(col), np.uint32)
+    g = fg.Graph(off, col, weights=w)
+    check(fg, orc, g, off, col, w, 5)  # isolated source
+
+
+def test_directed_graph(fg, orc):
+    rng = np.random.default_rng(3)
+    n = 3000
+    eu = rng.integers(0, n, 20000)
+    ev = rng.integers(0, n, 20000)
+    keep = eu != ev
+    pairs = np.unique(np.stack([eu[keep], ev[keep]], 1), axis=0)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    pairs = pairs[order]
+    off = np.zeros(n + 1, np.int32)
+    np.add.at(off, pairs[:, 0] + 1, 1)
+    off = np.cumsum(off).astype(np.int32)
+    col = pairs[:, 1].astype(np.int32)
+    w = rng.integers(1, 65, len(col)).astype(np.uint32)
+    g = fg.Graph(off, col, weights=w, symmetric=False)
+    for s in (0, 1, 2):
+        check(fg, orc, g, off, col, w, s)
+
+
+def test_overflow_reported(fg):
+    off, col = synth.from_edge_pairs(3, [(0, 1), (1, 2)])
+    w = np.full(len(col), 0x90000000, np.uint32)
+    g = fg.Graph(off, col, weights=w)
+    dist, parent, st = fg.sssp(g, 0)
+    assert st.status == fg.FG_EOVERFLOW
+
+
+def test_sssp_needs_weights(fg):
+    off, col = synth.from_edge_pairs(3, [(0, 1)])
+    g = fg.Graph(off, col)
+    with pytest.raises(fg.FGError) as e:
+        fg.sssp(g, 0)
+    assert e.value.status == fg.FG_EINVAL
+
+
+@pytest.mark.slow
+def test_config_rmat22_sssp_sampled(fg, orc):
+    off, col = synth.rmat_csr(22)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    for s in synth.sources(off, 64)[:2]:
+        check(fg, orc, g, off, col, w, int(s))
