@@ -100,6 +100,12 @@ typedef struct {
 
 fg_status fg_graph_info(const fg_graph* g, fg_graph_info_t* info);
 
+/* Device pointers of the graph's CSR arrays (read-only, owned by the graph
+ * unless it was created with FG_BORROW); weights is NULL if none.  Any
+ * output pointer may be NULL. */
+fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets, const int32_t** col_idx,
+                       const uint32_t** weights);
+
 /* -------------------------------------------------------------- workspace */
 
 #define FG_PRIM_BFS 0          /* fg_bfs, modes FG_MODE_DO / FG_MODE_PUSH      */
@@ -271,6 +277,73 @@ fg_status fg_queue_to_bitmap(const fg_graph* g, const int32_t* queue,
 fg_status fg_bitmap_to_queue(const fg_graph* g, const uint64_t* bits,
                              int32_t* out_q, int32_t* out_len, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------- partition + package */
+
+typedef struct fg_share fg_share;
+
+/*
+ * One GPU's share of a vertex-partitioned graph (Sec. III-C duplicate-1-hop;
+ * the random partitioner of Sec. V-C supplies `owner`).  Hosted vertices
+ * (owner == part) get local ids 0..n_local-1 in ascending global order;
+ * remote neighbours of hosted vertices become proxies n_local..n_total-1 in
+ * ascending global order; a hosted row keeps its neighbours' global order,
+ * renamed to local ids; proxies have no out-edges.  For each local vertex the
+ * share keeps its owner, its id on the owner (conv = rank among the owner's
+ * hosted vertices) and its global id.  row_offsets / col_idx / owner are host
+ * arrays (int32[n+1], int32[m], uint8[n]); 1 <= nparts <= 16; n < 2^28.
+ * Errors: FG_EINVAL, FG_EUNSUPPORTED (n too large), FG_ENOMEM, FG_EDEVICE.
+ */
+fg_status fg_share_create(int32_t n, int64_t m, const int32_t* row_offsets,
+                          const int32_t* col_idx, const uint8_t* owner, int32_t nparts,
+                          int32_t part, void* stream, fg_share** out);
+fg_status fg_share_destroy(fg_share* s);
+
+typedef struct {
+  int32_t n_global;
+  int32_t n_local;
+  int32_t n_total;
+  int32_t nparts;
+  int32_t part;
+  int32_t reserved;
+  int64_t m_local;
+} fg_share_info_t;
+
+fg_status fg_share_info(const fg_share* s, fg_share_info_t* info);
+
+/* The share's local CSR as a graph (owned by the share; push traversals). */
+const fg_graph* fg_share_graph(const fg_share* s);
+
+/* Device tables of the share (owned by it): owner uint8[n_total],
+ * conv int32[n_total], l2g int32[n_total].  Any output pointer may be NULL. */
+fg_status fg_share_tables(const fg_share* s, const uint8_t** owner, const int32_t** conv,
+                          const int32_t** l2g);
+
+typedef struct {
+  int32_t* ids;         /* device int32[nparts * capacity]; peer p at p*capacity */
+  int32_t* depth;       /* same layout: depth[v] of each packaged vertex         */
+  int32_t* parent;      /* same layout: global id of parent[v], or NULL          */
+  int32_t* counts;      /* device int32[nparts]; counts[part] = 0                 */
+  int32_t* local;       /* device int32[capacity] local sub-frontier, or NULL     */
+  int32_t* local_count; /* device int32[1], or NULL                               */
+  int64_t capacity;     /* entries per buffer, >= len                             */
+} fg_peer_bufs;
+
+/* Workspace bytes fg_package needs for frontiers of up to max_len entries. */
+size_t fg_package_workspace_bytes(const fg_share* s, int32_t max_len);
+
+/*
+ * Split + package (Sec. III-B): walk frontier[0..len) (device, local ids) in
+ * order; vertices v < n_local go to the local sub-frontier; every proxy v is
+ * appended to the buffer of its owner p as (conv[v], depth[v], global id of
+ * parent[v] if parent != NULL).  Buffers keep frontier order (stable), so the
+ * result is deterministic.  depth / parent are device int32[n_total] (local
+ * ids).  Errors: FG_EINVAL (len outside [0, n_total], capacity < len, NULL
+ * buffers), FG_ENOMEM (workspace), FG_EDEVICE.
+ */
+fg_status fg_package(const fg_share* s, const int32_t* frontier, int32_t len,
+                     const int32_t* depth, const int32_t* parent, const fg_peer_bufs* out,
+                     void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

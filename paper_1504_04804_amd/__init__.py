@@ -93,6 +93,30 @@ class GraphInfo(ctypes.Structure):
     ]
 
 
+class ShareInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_global", ctypes.c_int32),
+        ("n_local", ctypes.c_int32),
+        ("n_total", ctypes.c_int32),
+        ("nparts", ctypes.c_int32),
+        ("part", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("m_local", ctypes.c_int64),
+    ]
+
+
+class PeerBufs(ctypes.Structure):
+    _fields_ = [
+        ("ids", ctypes.c_void_p),
+        ("depth", ctypes.c_void_p),
+        ("parent", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p),
+        ("local", ctypes.c_void_p),
+        ("local_count", ctypes.c_void_p),
+        ("capacity", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 # Every symbol declared in include/fg.h, with (restype, argtypes).
@@ -110,6 +134,14 @@ SIGNATURES = {
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
     "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_graph_csr": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "fg_share_create": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I32, _P, ctypes.POINTER(_P)]),
+    "fg_share_destroy": (_I32, [_P]),
+    "fg_share_info": (_I32, [_P, ctypes.POINTER(ShareInfo)]),
+    "fg_share_graph": (_P, [_P]),
+    "fg_share_tables": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "fg_package_workspace_bytes": (_SZ, [_P, _I32]),
+    "fg_package": (_I32, [_P, _P, _I32, _P, _P, ctypes.POINTER(PeerBufs), _P, _SZ, _P]),
     "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _I64, _P, _P, _SZ, _P]),
     "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
@@ -317,3 +349,100 @@ def bitmap_to_queue(g, bits, out_q, out_len, ws=None):
     ws = ws if ws is not None else g.workspace(FG_PRIM_BFS_UNFUSED)
     _check(lib().fg_bitmap_to_queue(g.handle, _ptr(bits), _ptr(out_q), _ptr(out_len), _ptr(ws),
                                     ws.numel(), _stream()))
+
+
+class Share:
+    """One partition of a graph under an owner map (fg_share_create)."""
+
+    def __init__(self, row_offsets, col_idx, owner, nparts, part):
+        import numpy as np
+        L = lib()
+        off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+        col = np.ascontiguousarray(col_idx, dtype=np.int32)
+        own = np.ascontiguousarray(owner, dtype=np.uint8)
+        h = ctypes.c_void_p()
+        _check(L.fg_share_create(len(off) - 1, len(col), off.ctypes.data, col.ctypes.data,
+                                 own.ctypes.data, nparts, part, _stream(), ctypes.byref(h)))
+        self.handle = h
+        i = ShareInfo()
+        _check(L.fg_share_info(h, ctypes.byref(i)))
+        self.n_local, self.n_total, self.nparts, self.part = i.n_local, i.n_total, i.nparts, i.part
+        self.m_local = i.m_local
+        self.graph_handle = L.fg_share_graph(h)
+
+    def tables(self):
+        """(owner uint8, conv int32, l2g int32) copied to host numpy arrays."""
+        import numpy as np
+        po, pc, pl = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().fg_share_tables(self.handle, ctypes.byref(po), ctypes.byref(pc),
+                                     ctypes.byref(pl)))
+        torch.cuda.synchronize()
+        out = []
+        for p, dt, sz in ((po, np.uint8, 1), (pc, np.int32, 4), (pl, np.int32, 4)):
+            a = np.empty(self.n_total, dt)
+            _memcpy_d2h(a, p.value, self.n_total * sz)
+            out.append(a)
+        return tuple(out)
+
+    def csr(self):
+        """The share's local CSR (row_offsets, cols) copied to host numpy arrays."""
+        return graph_csr(self.graph_handle, self.n_total, self.m_local)
+
+    def workspace(self, max_len):
+        nb = int(lib().fg_package_workspace_bytes(self.handle, int(max_len)))
+        return torch.zeros(max(nb, 256), dtype=torch.uint8, device="cuda")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fg_share_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _memcpy_d2h(dst_np, src_dev_ptr, nbytes):
+    """Copy device memory owned by the library into a host numpy array."""
+    rt = ctypes.CDLL("libamdhip64.so.7")
+    rt.hipMemcpy.restype = ctypes.c_int
+    rt.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    err = rt.hipMemcpy(ctypes.c_void_p(dst_np.ctypes.data), ctypes.c_void_p(src_dev_ptr),
+                       nbytes, 2)  # hipMemcpyDeviceToHost
+    if err != 0:
+        raise RuntimeError(f"hipMemcpy failed ({err})")
+
+
+def package(share, frontier, length, depth, parent=None, capacity=None, ws=None):
+    """fg_package: returns device tensors (ids, depth, parent, counts, local, local_count)."""
+    cap = int(capacity if capacity is not None else max(length, 1))
+    P = share.nparts
+    dev = "cuda"
+    ids = torch.full((P * cap,), -7, dtype=torch.int32, device=dev)
+    dep = torch.full((P * cap,), -7, dtype=torch.int32, device=dev)
+    par = torch.full((P * cap,), -7, dtype=torch.int32, device=dev) if parent is not None else None
+    counts = torch.zeros(P, dtype=torch.int32, device=dev)
+    local = torch.full((cap,), -7, dtype=torch.int32, device=dev)
+    lc = torch.zeros(1, dtype=torch.int32, device=dev)
+    bufs = PeerBufs(ids.data_ptr(), dep.data_ptr(), par.data_ptr() if par is not None else None,
+                    counts.data_ptr(), local.data_ptr(), lc.data_ptr(), cap)
+    ws = ws if ws is not None else share.workspace(length)
+    _check(lib().fg_package(share.handle, _ptr(frontier), int(length), _ptr(depth), _ptr(parent),
+                            ctypes.byref(bufs), _ptr(ws), ws.numel(), _stream()))
+    return ids, dep, par, counts, local, lc
+
+
+def graph_csr(handle, n, m):
+    """Host copies of a graph's device CSR arrays (fg_graph_csr)."""
+    import numpy as np
+    po, pc, pw = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib().fg_graph_csr(handle, ctypes.byref(po), ctypes.byref(pc), ctypes.byref(pw)))
+    torch.cuda.synchronize()
+    off = np.empty(n + 1, np.int32)
+    col = np.empty(m, np.int32)
+    _memcpy_d2h(off, po.value, 4 * (n + 1))
+    if m:
+        _memcpy_d2h(col, pc.value, 4 * m)
+    return off, col

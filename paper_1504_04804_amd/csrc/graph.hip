@@ -247,3 +247,12 @@ extern "C" fg_status fg_graph_info(const fg_graph* g, fg_graph_info_t* info) {
   info->resident_bytes = g->resident_bytes;
   return FG_OK;
 }
+
+extern "C" fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets,
+                                  const int32_t** col_idx, const uint32_t** weights) {
+  if (!g) return fg_set_error(FG_EINVAL, "fg_graph_csr: graph is NULL");
+  if (row_offsets) *row_offsets = g->off;
+  if (col_idx) *col_idx = g->col;
+  if (weights) *weights = g->w;
+  return FG_OK;
+}
