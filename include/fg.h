@@ -278,6 +278,53 @@ fg_status fg_bitmap_to_queue(const fg_graph* g, const uint64_t* bits,
                              int32_t* out_q, int32_t* out_len, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------ batched BFS (64 lanes) */
+
+typedef struct fg_msbfs fg_msbfs;
+
+typedef struct {
+  int32_t big_degree;    /* push: degree from which edges go to descriptors (0 = 64) */
+  int32_t pull_div;      /* push -> pull when active vertices > n / pull_div (0 = 64) */
+  int32_t push_div;      /* pull -> push when active vertices < n / push_div (0 = 512) */
+  int32_t blocks_per_cu; /* persistent launch width (0 = default)                     */
+} fg_msbfs_opts;
+
+void fg_msbfs_opts_default(fg_msbfs_opts* opts);
+
+/*
+ * A batch of up to 64 independent BFS queries (lanes) that share one
+ * traversal with one bit per lane in each vertex word.  Each lane's depths
+ * equal fg_bfs's depths from its source.  Lanes are admitted at any step
+ * boundary (continuous batching) and are done when their frontier empties.
+ * ws: device workspace of fg_workspace_bytes(g, FG_PRIM_MSBFS, lanes) bytes,
+ * owned by the caller, used exclusively by this batch until fg_msbfs_close.
+ * fg_msbfs_open clears the batch state (asynchronously on `stream`).
+ */
+fg_status fg_msbfs_open(const fg_graph* g, int32_t lanes, void* ws, size_t ws_bytes,
+                        const fg_msbfs_opts* opts, void* stream, fg_msbfs** out);
+fg_status fg_msbfs_close(fg_msbfs* b);
+
+/* Queue query `src` for lane `lane`; it starts at the next fg_msbfs_step.
+ * The lane's previous result is discarded.  FG_EINVAL for a bad lane / src
+ * or a lane already pending. */
+fg_status fg_msbfs_admit(fg_msbfs* b, int32_t lane, int32_t src);
+
+/* Run at most k_iters BFS levels for every live lane (fewer if all lanes
+ * finish), asynchronously on `stream`. */
+fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream);
+
+/* Synchronise `stream`; *done_lanes = admitted lanes whose traversal has
+ * finished; *iterations = levels run since fg_msbfs_open.  Either pointer
+ * may be NULL. */
+fg_status fg_msbfs_poll(fg_msbfs* b, uint64_t* done_lanes, int32_t* iterations, void* stream);
+
+/* Copy lane's depths (int32[n], -1 = unreached) to device memory `depth`
+ * (asynchronous on `stream`). */
+fg_status fg_msbfs_read(fg_msbfs* b, int32_t lane, int32_t* depth, void* stream);
+
+/* Forget the query held by `lane` (it no longer reports as done). */
+fg_status fg_msbfs_release(fg_msbfs* b, int32_t lane);
+
 /* ----------------------------------------------------- partition + package */
 
 typedef struct fg_share fg_share;

@@ -80,6 +80,15 @@ class SsspOpts(ctypes.Structure):
     ]
 
 
+class MsOpts(ctypes.Structure):
+    _fields_ = [
+        ("big_degree", ctypes.c_int32),
+        ("pull_div", ctypes.c_int32),
+        ("push_div", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+    ]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -134,6 +143,14 @@ SIGNATURES = {
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
     "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_msbfs_opts_default": (None, [ctypes.POINTER(MsOpts)]),
+    "fg_msbfs_open": (_I32, [_P, _I32, _P, _SZ, ctypes.POINTER(MsOpts), _P, ctypes.POINTER(_P)]),
+    "fg_msbfs_close": (_I32, [_P]),
+    "fg_msbfs_admit": (_I32, [_P, _I32, _I32]),
+    "fg_msbfs_step": (_I32, [_P, _I32, _P]),
+    "fg_msbfs_poll": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I32), _P]),
+    "fg_msbfs_read": (_I32, [_P, _I32, _P, _P]),
+    "fg_msbfs_release": (_I32, [_P, _I32]),
     "fg_graph_csr": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "fg_share_create": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I32, _P, ctypes.POINTER(_P)]),
     "fg_share_destroy": (_I32, [_P]),
@@ -446,3 +463,70 @@ def graph_csr(handle, n, m):
     if m:
         _memcpy_d2h(col, pc.value, 4 * m)
     return off, col
+
+
+def msbfs_opts(big_degree=0, pull_div=0, push_div=0, blocks_per_cu=0):
+    o = MsOpts()
+    lib().fg_msbfs_opts_default(ctypes.byref(o))
+    o.big_degree, o.pull_div, o.push_div, o.blocks_per_cu = big_degree, pull_div, push_div, blocks_per_cu
+    return o
+
+
+class MsBatch:
+    """Up to 64 BFS queries sharing one traversal (fg_msbfs_*)."""
+
+    def __init__(self, g, lanes=64, opts=None, stream=None):
+        self.g = g
+        self.lanes = lanes
+        nb = g.workspace_bytes(FG_PRIM_MSBFS, lanes)
+        self.ws = torch.zeros(max(nb, 256), dtype=torch.uint8, device=g.off.device)
+        h = ctypes.c_void_p()
+        o = opts if opts is not None else msbfs_opts()
+        _check(lib().fg_msbfs_open(g.handle, lanes, _ptr(self.ws), self.ws.numel(),
+                                   ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.admitted = 0
+
+    def admit(self, lane, src):
+        _check(lib().fg_msbfs_admit(self.handle, int(lane), int(src)))
+        self.admitted |= 1 << int(lane)
+
+    def step(self, k_iters, stream=None):
+        _check(lib().fg_msbfs_step(self.handle, int(k_iters), _stream(stream)))
+
+    def poll(self, stream=None):
+        done = ctypes.c_uint64()
+        it = ctypes.c_int32()
+        _check(lib().fg_msbfs_poll(self.handle, ctypes.byref(done), ctypes.byref(it),
+                                   _stream(stream)))
+        return int(done.value), int(it.value)
+
+    def read(self, lane, out=None, stream=None):
+        out = out if out is not None else torch.empty(self.g.n, dtype=torch.int32,
+                                                      device=self.g.off.device)
+        _check(lib().fg_msbfs_read(self.handle, int(lane), _ptr(out), _stream(stream)))
+        return out
+
+    def release(self, lane):
+        _check(lib().fg_msbfs_release(self.handle, int(lane)))
+        self.admitted &= ~(1 << int(lane))
+
+    def run(self, k_iters=16, max_steps=1 << 20):
+        """Step until every admitted lane is done; returns the done mask."""
+        for _ in range(max_steps):
+            self.step(k_iters)
+            done, _ = self.poll()
+            if done & self.admitted == self.admitted:
+                return done
+        raise RuntimeError("msbfs did not finish")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fg_msbfs_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfg.so")
 
-SOURCES = ["abi.cpp", "graph.hip", "bfs.hip", "ops.hip", "sssp.hip", "package.hip", "stubs.hip"]
+SOURCES = ["abi.cpp", "graph.hip", "bfs.hip", "ops.hip", "sssp.hip", "package.hip", "msbfs.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

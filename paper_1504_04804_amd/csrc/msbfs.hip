@@ -1,0 +1,622 @@
+// Batched multi-source BFS: up to 64 independent BFS queries (lanes) share
+// one traversal.  Every vertex holds a 64-bit word per structure, one bit per
+// lane: `visit` (lanes that reached it), and two frontier words F[0] / F[1]
+// (lanes for which it is in the current / next frontier).  Each lane's
+// depths equal those of a single-source BFS from its source; lanes can be
+// admitted at any step boundary (continuous batching) and retire when their
+// frontier empties.
+//
+// Per iteration, on the device, one of two directions (as in Sec. VI-A):
+//   push: for every active vertex u and edge u->v, next[v] |= F[u] & ~visit[v]
+//         (64-bit atomicOr); a vertex whose next word was 0 joins the next
+//         active list; a finalise pass keeps only unvisited lanes, marks them
+//         visited and writes their depths.
+//   pull: every vertex with unvisited live lanes ORs F[u] over its neighbours
+//         in CSR order and stops as soon as every wanted lane is covered;
+//         whole-word writes, no atomics.
+// Push load balance reuses the scan-gather + edge-chunk descriptors of the
+// BFS kernel.  Data layout in HBM (caller workspace):
+//   state   iteration counter, direction, live / used lanes, lane start
+//           iterations (persists across steps)
+//   visit, F[0], F[1]   uint64[n]
+//   queue   2 x int32[n]        active vertices (push)
+//   desc    int2[m/CH + n + 64]
+//   depth   int32[lanes][n]     lane-major, so each lane's result is contiguous
+//   control barrier and counters of one launch (cleared on exit)
+#include <string.h>
+
+#include "frontier.h"
+
+namespace {
+using namespace fgk;
+
+constexpr int PB = 1024;
+constexpr int PWAVES = PB / FG_WAVE;
+constexpr int CH = 256;
+constexpr int STAGE = 512;
+constexpr int DSTAGE = 128;
+constexpr int MAXL = 64;
+
+struct MsState {
+  int32_t it;      // global iteration counter
+  int32_t mode;    // 0 push (active list valid), 1 pull
+  int32_t qsel;    // queue of the current active list
+  int32_t fsel;    // F array of the current frontier
+  int64_t qlen;    // active vertices of the current frontier
+  ull live;        // lanes with a non-empty current frontier
+  ull used;        // lanes admitted at least once
+  int32_t start[MAXL];
+  int32_t pad[16];
+};
+
+// Monotone counters of one iteration parity (see the BFS kernel).
+struct CtrSlot {
+  Line64 q;
+  Line64 desc;
+  Line64 cnt;
+};
+
+struct alignas(256) MsCtl {
+  uint32_t bar[FG_BAR_WORDS];
+  uint32_t exit_count;
+  uint32_t pad0[63];
+  CtrSlot slot[2];
+  // OR of the lanes discovered in iteration k lives in livew[k % 3]; it is
+  // zeroed at the start of iteration k-1, after its previous use (k-3) was
+  // read by every workgroup
+  Line64 livew[3];
+  int64_t pub_qlen;
+  ull pub_live;
+};
+
+struct MsParams {
+  const int32_t* __restrict__ off;
+  const int32_t* __restrict__ col;
+  int32_t n;
+  int64_t m;
+  int32_t lanes;
+  ull* visit;
+  ull* F[2];
+  int32_t* q[2];
+  int2* desc;
+  int32_t* depth;  // [lanes][n]
+  MsState* state;
+  MsCtl* ctl;
+  int32_t k_iters;
+  int32_t npend;
+  int32_t pend_lane[MAXL];
+  int32_t pend_src[MAXL];
+  int32_t big_deg;
+  int32_t pull_div;  // push -> pull when active vertices > n / pull_div
+  int32_t push_div;  // pull -> push when active vertices < n / push_div
+};
+
+struct Lds {
+  int32_t stage[PWAVES][STAGE];
+  int2 dstage[PWAVES][DSTAGE];
+  int32_t w_sc[PWAVES][FG_WAVE];
+  int32_t w_u[PWAVES][FG_WAVE];
+  int32_t w_b[PWAVES][FG_WAVE];
+  int64_t red[PWAVES + 1];
+  ull redu[PWAVES + 1];
+  int32_t flag;
+  int64_t bcast[4];
+};
+
+__device__ __forceinline__ ull block_or(ull x, ull* scratch) {
+#pragma unroll
+  for (int d = FG_WAVE / 2; d > 0; d >>= 1) x |= __shfl_xor(x, d, FG_WAVE);
+  const int wid = threadIdx.x / FG_WAVE;
+  __syncthreads();
+  if (fg_lane() == 0) scratch[wid] = x;
+  __syncthreads();
+  ull s = 0;
+#pragma unroll
+  for (int i = 0; i < PWAVES; ++i) s |= scratch[i];
+  return s;
+}
+
+// depth[l][v] = d for every lane l set in `bits`.
+__device__ __forceinline__ void write_depths(const MsParams& P, int32_t v, ull bits, int32_t it1) {
+  while (bits) {
+    const int l = __builtin_ctzll(bits);
+    bits &= bits - 1;
+    P.depth[(int64_t)l * P.n + v] = it1 - P.state->start[l];
+  }
+}
+
+// ---- push expansion (scan-gather for low degree, descriptors for high)
+__device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int64_t qlen,
+                            ull qbase, ull dbase, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int32_t* Qin = P.q[S.qsel];
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  const ull* Fc = P.F[S.fsel];
+  ull* Fn = P.F[S.fsel ^ 1];
+  int32_t* sc = L.w_sc[wid];
+  int32_t* su = L.w_u[wid];
+  int32_t* sb = L.w_b[wid];
+  CtrSlot& C = P.ctl->slot[k & 1];
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  for (int64_t base = gw * FG_WAVE; base < qlen; base += W * FG_WAVE) {
+    const int64_t i = base + lane;
+    int32_t u = 0, b = 0, deg = 0;
+    if (i < qlen) {
+      u = Qin[i];
+      b = P.off[u];
+      deg = P.off[u + 1] - b;
+      if (Fc[u] == 0ull) deg = 0;  // listed but without lanes
+    }
+    const bool big = deg >= P.big_deg;
+    const int32_t nd = big ? (deg + CH - 1) / CH : 0;
+    const int32_t ndi = fg_wave_incl_scan(nd);
+    const int32_t ND = __shfl(ndi, FG_WAVE - 1, FG_WAVE);
+    if (ND > 0) {
+      wave_lds_fence();
+      sc[lane] = ndi - nd;
+      su[lane] = u;
+      sb[lane] = b;
+      wave_lds_fence();
+      for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
+        const int32_t t = t0 + lane;
+        int2 dsc = make_int2(0, 0);
+        if (t < ND) {
+          const int32_t j = upper_idx(sc, FG_WAVE, t);
+          dsc = make_int2(su[j], sb[j] + (t - sc[j]) * CH);
+        }
+        dst.push(t < ND, dsc, &C.desc.v, dbase, P.desc);
+      }
+    }
+    const int32_t d = big ? 0 : deg;
+    const int32_t inc = fg_wave_incl_scan(d);
+    const int32_t T = __shfl(inc, FG_WAVE - 1, FG_WAVE);
+    if (T == 0) continue;
+    wave_lds_fence();
+    sc[lane] = inc - d;
+    su[lane] = u;
+    sb[lane] = b;
+    wave_lds_fence();
+    for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
+      const int32_t t = t0 + lane;
+      bool first = false;
+      int32_t v = 0;
+      if (t < T) {
+        const int32_t j = upper_idx(sc, FG_WAVE, t);
+        v = P.col[sb[j] + (t - sc[j])];
+        const ull nb = Fc[su[j]] & ~P.visit[v];
+        if (nb && (Fn[v] & nb) != nb) first = atomicOr(&Fn[v], nb) == 0ull;
+      }
+      st.push(first, v, &C.q.v, qbase, Qout);
+    }
+  }
+  st.flush(&C.q.v, qbase, Qout);
+  dst.flush(&C.desc.v, dbase, P.desc);
+}
+
+__device__ void push_desc(const MsParams& P, const MsState& S, int32_t k, int64_t ndesc,
+                          ull qbase, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  const ull* Fc = P.F[S.fsel];
+  ull* Fn = P.F[S.fsel ^ 1];
+  CtrSlot& C = P.ctl->slot[k & 1];
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  for (int64_t i = gw; i < ndesc; i += W) {
+    const int2 dsc = P.desc[i];
+    const int32_t u = dsc.x;
+    const int32_t e_end = P.off[u + 1];
+    const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
+    const ull fu = Fc[u];
+    int32_t vv[CH / FG_WAVE];
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t e = dsc.y + r * FG_WAVE + lane;
+      vv[r] = e < e1 ? P.col[e] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < CH / FG_WAVE; ++r) {
+      const int32_t v = vv[r];
+      bool first = false;
+      if (v >= 0) {
+        const ull nb = fu & ~P.visit[v];
+        if (nb && (Fn[v] & nb) != nb) first = atomicOr(&Fn[v], nb) == 0ull;
+      }
+      st.push(first, v, &C.q.v, qbase, Qout);
+    }
+  }
+  st.flush(&C.q.v, qbase, Qout);
+}
+
+__global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
+  __shared__ Lds L;
+  fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
+  const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * PB;
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  MsState S = *P.state;  // read by every workgroup before anyone writes it
+  bool ok = gs.sync(&L.flag);
+  // per-parity bases of the monotone counters, as scalars (a dynamically
+  // indexed array would live in scratch memory)
+  ull qb0 = 0, qb1 = 0, db0 = 0, db1 = 0, cb0 = 0, cb1 = 0;
+
+  // ---- admissions: clear reused lanes, fill their depth rows, seed sources
+  if (ok && P.npend > 0) {
+    ull mask = 0;
+    for (int i = 0; i < P.npend; ++i) mask |= 1ull << P.pend_lane[i];
+    const ull reused = mask & S.used;
+    if (reused) {
+      for (int64_t v = tid; v < P.n; v += nth) {
+        P.visit[v] &= ~reused;
+        P.F[0][v] &= ~reused;
+        P.F[1][v] &= ~reused;
+      }
+    }
+    for (int i = 0; i < P.npend; ++i) {
+      int32_t* row = P.depth + (int64_t)P.pend_lane[i] * P.n;
+      for (int64_t v = tid; v < P.n; v += nth) row[v] = -1;
+    }
+    ok = gs.sync(&L.flag);
+    if (ok && tid == 0) {
+      MsState* st = P.state;
+      int64_t ql = S.qlen;
+      for (int i = 0; i < P.npend; ++i) {
+        const int32_t l = P.pend_lane[i], s = P.pend_src[i];
+        const ull bit = 1ull << l;
+        P.visit[s] |= bit;
+        if (S.mode == 0 && P.F[S.fsel][s] == 0ull) P.q[S.qsel][ql++] = s;
+        P.F[S.fsel][s] |= bit;
+        P.depth[(int64_t)l * P.n + s] = 0;
+        st->start[l] = S.it;
+      }
+      if (S.mode == 1) ql = S.qlen + P.npend;  // pull: an estimate is enough
+      S.qlen = ql;
+      S.live |= mask;
+      S.used |= mask;
+      P.ctl->pub_qlen = ql;
+      P.ctl->pub_live = S.live;
+    }
+    ok = ok && gs.sync(&L.flag);
+    S.qlen = P.ctl->pub_qlen;
+    S.live = P.ctl->pub_live;
+    S.used |= mask;
+  }
+
+  for (int32_t k = 0; ok && k < P.k_iters && S.live != 0ull; ++k) {
+    const int32_t it1 = S.it + 1;
+    const bool want_pull = S.mode == 0 ? S.qlen > P.n / P.pull_div : S.qlen >= P.n / P.push_div;
+    CtrSlot& C = P.ctl->slot[k & 1];
+    const bool odd = k & 1;
+    const ull msk = 0ull - (ull)odd;
+    ull qbp = (qb1 & msk) | (qb0 & ~msk);
+    ull dbp = (db1 & msk) | (db0 & ~msk);
+    ull cbp = (cb1 & msk) | (cb0 & ~msk);
+    ull* livew = &P.ctl->livew[k % 3].v;
+    if (tid == 0)
+      __hip_atomic_store(&P.ctl->livew[(k + 1) % 3].v, 0ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (!want_pull && S.mode == 1) {
+      // pull -> push: list the active vertices, clear the next F array
+      const ull* Fc = P.F[S.fsel];
+      ull* Fn = P.F[S.fsel ^ 1];
+      WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+      for (int64_t v0 = gw * FG_WAVE; v0 < P.n; v0 += W * FG_WAVE) {
+        const int64_t v = v0 + lane;
+        bool act = false;
+        if (v < P.n) {
+          act = Fc[v] != 0ull;
+          Fn[v] = 0ull;
+        }
+        st.push(act, (int32_t)v, &C.cnt.v, cbp, P.q[S.qsel]);
+      }
+      st.flush(&C.cnt.v, cbp, P.q[S.qsel]);
+      if (!(ok = gs.sync(&L.flag))) break;
+      const ull ct = fg_atomic_load_u64(&C.cnt.v);
+      S.qlen = (int64_t)(ct - cbp);
+      cbp = ct;
+      S.mode = 0;
+    }
+    if (want_pull) {
+      // ---- pull: lane per vertex, early exit when every wanted lane is seen
+      const ull* Fc = P.F[S.fsel];
+      ull* Fn = P.F[S.fsel ^ 1];
+      ull lor = 0;
+      int64_t act = 0;
+      for (int64_t v0 = gw * FG_WAVE; v0 < P.n; v0 += W * FG_WAVE) {
+        const int64_t v = v0 + lane;
+        ull nw = 0;
+        if (v < P.n) {
+          const ull vis = P.visit[v];
+          const ull want = S.live & ~vis;
+          if (want) {
+            const int32_t e = P.off[v + 1];
+            for (int32_t i = P.off[v]; i < e; ++i) {
+              nw |= Fc[P.col[i]] & want;
+              if (nw == want) break;
+            }
+            if (nw) {
+              P.visit[v] = vis | nw;
+              write_depths(P, (int32_t)v, nw, it1 - 0);
+            }
+          }
+          Fn[v] = nw;
+        }
+        lor |= nw;
+        act += nw != 0ull;
+      }
+      const ull bor = block_or(lor, L.redu);
+      const int64_t bact = fg_block_sum<PB>(act, L.red);
+      if (threadIdx.x == 0) {
+        if (bor) atomicOr(livew, bor);
+        if (bact) atomicAdd(&C.cnt.v, (ull)bact);
+      }
+      if (!(ok = gs.sync(&L.flag))) break;
+      const ull lv = fg_atomic_load_u64(livew);
+      const ull ct = fg_atomic_load_u64(&C.cnt.v);
+      S.qlen = (int64_t)(ct - cbp);
+      cbp = ct;
+      S.live = lv;
+      S.fsel ^= 1;
+      S.mode = 1;
+    } else {
+      // ---- push
+      push_expand(P, S, k, S.qlen, qbp, dbp, L);
+      if (!(ok = gs.sync(&L.flag))) break;
+      const ull dt = fg_atomic_load_u64(&C.desc.v);
+      const int64_t ndesc = (int64_t)(dt - dbp);
+      if (ndesc > 0) {
+        push_desc(P, S, k, ndesc, qbp, L);
+        if (!(ok = gs.sync(&L.flag))) break;
+      }
+      dbp = dt;
+      const ull qt = fg_atomic_load_u64(&C.q.v);
+      const int64_t qn = (int64_t)(qt - qbp);
+      qbp = qt;
+      // finalise: keep unvisited lanes, mark them, write depths; clear the
+      // current frontier words so the array is zero again outside the list
+      const int32_t* Qn = P.q[S.qsel ^ 1];
+      ull* Fn = P.F[S.fsel ^ 1];
+      ull lor = 0;
+      for (int64_t i = tid; i < qn; i += nth) {
+        const int32_t v = Qn[i];
+        const ull vis = P.visit[v];
+        const ull nw = Fn[v] & ~vis;
+        Fn[v] = nw;
+        if (nw) {
+          P.visit[v] = vis | nw;
+          write_depths(P, v, nw, it1);
+        }
+        lor |= nw;
+      }
+      const int32_t* Qc = P.q[S.qsel];
+      ull* Fc = P.F[S.fsel];
+      for (int64_t i = tid; i < S.qlen; i += nth) Fc[Qc[i]] = 0ull;
+      const ull bor = block_or(lor, L.redu);
+      if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
+      if (!(ok = gs.sync(&L.flag))) break;
+      S.live = fg_atomic_load_u64(livew);
+      S.qlen = qn;
+      S.qsel ^= 1;
+      S.fsel ^= 1;
+      S.mode = 0;
+    }
+    qb1 = (qbp & msk) | (qb1 & ~msk);
+    qb0 = (qb0 & msk) | (qbp & ~msk);
+    db1 = (dbp & msk) | (db1 & ~msk);
+    db0 = (db0 & msk) | (dbp & ~msk);
+    cb1 = (cbp & msk) | (cb1 & ~msk);
+    cb0 = (cb0 & msk) | (cbp & ~msk);
+    S.it = it1;
+  }
+  if (tid == 0) {
+    MsState* st = P.state;
+    st->it = S.it;
+    st->mode = S.mode;
+    st->qsel = S.qsel;
+    st->fsel = S.fsel;
+    st->qlen = S.qlen;
+    st->live = ok ? S.live : 0ull;
+    st->used = S.used;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(&P.ctl->exit_count, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    L.flag = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (L.flag) {
+    uint32_t* w = (uint32_t*)P.ctl;
+    for (int i = threadIdx.x; i < (int)(sizeof(MsCtl) / 4); i += PB) w[i] = 0u;
+  }
+}
+
+struct MsLayout {
+  MsState* state;
+  MsCtl* ctl;
+  ull* visit;
+  ull* F[2];
+  int32_t* q[2];
+  int2* desc;
+  int32_t* depth;
+  size_t bytes;
+};
+
+MsLayout ms_layout(const fg_graph* g, int32_t lanes, void* ws) {
+  fg_carver c(ws);
+  MsLayout L;
+  L.state = c.take<MsState>(1);
+  L.ctl = c.take<MsCtl>(1);
+  L.visit = c.take<ull>(g->n);
+  L.F[0] = c.take<ull>(g->n);
+  L.F[1] = c.take<ull>(g->n);
+  L.q[0] = c.take<int32_t>(g->n);
+  L.q[1] = c.take<int32_t>(g->n);
+  L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
+  L.depth = c.take<int32_t>((size_t)lanes * (size_t)g->n);
+  L.bytes = c.used;
+  return L;
+}
+
+int g_ms_occ[64];
+
+}  // namespace
+
+struct fg_msbfs {
+  const fg_graph* g = nullptr;
+  int32_t lanes = 0;
+  MsLayout lay;
+  int32_t npend = 0;
+  int32_t pend_lane[MAXL];
+  int32_t pend_src[MAXL];
+  uint64_t admitted = 0;  // lanes holding a query (host view)
+  fg_msbfs_opts opts;
+};
+
+size_t fg_msbfs_workspace_bytes(const fg_graph* g, int32_t lanes) {
+  return ms_layout(g, lanes, nullptr).bytes;
+}
+
+extern "C" void fg_msbfs_opts_default(fg_msbfs_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+}
+
+extern "C" fg_status fg_msbfs_open(const fg_graph* g, int32_t lanes, void* ws, size_t ws_bytes,
+                                   const fg_msbfs_opts* opts, void* stream, fg_msbfs** out) {
+  if (!out) return fg_set_error(FG_EINVAL, "fg_msbfs_open: out is NULL");
+  *out = nullptr;
+  if (!g || !ws) return fg_set_error(FG_EINVAL, "fg_msbfs_open: NULL graph or workspace");
+  if (lanes < 1 || lanes > MAXL)
+    return fg_set_error(FG_EINVAL, "fg_msbfs_open: lanes=%d outside [1, 64]", lanes);
+  MsLayout lay = ms_layout(g, lanes, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_msbfs_open: workspace of %zu bytes < required %zu",
+                        ws_bytes, lay.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  // fresh state: visit / F all zero, no lanes
+  FG_HIP_TRY(hipMemsetAsync(lay.state, 0, sizeof(MsState), s));
+  FG_HIP_TRY(hipMemsetAsync(lay.ctl, 0, sizeof(MsCtl), s));
+  FG_HIP_TRY(hipMemsetAsync(lay.visit, 0, sizeof(ull) * (size_t)g->n, s));
+  FG_HIP_TRY(hipMemsetAsync(lay.F[0], 0, sizeof(ull) * (size_t)g->n, s));
+  FG_HIP_TRY(hipMemsetAsync(lay.F[1], 0, sizeof(ull) * (size_t)g->n, s));
+  fg_msbfs* b = new fg_msbfs();
+  b->g = g;
+  b->lanes = lanes;
+  b->lay = lay;
+  if (opts) b->opts = *opts; else fg_msbfs_opts_default(&b->opts);
+  *out = b;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_close(fg_msbfs* b) {
+  delete b;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_admit(fg_msbfs* b, int32_t lane, int32_t src) {
+  if (!b) return fg_set_error(FG_EINVAL, "fg_msbfs_admit: batch is NULL");
+  if (lane < 0 || lane >= b->lanes)
+    return fg_set_error(FG_EINVAL, "fg_msbfs_admit: lane=%d outside [0, %d)", lane, b->lanes);
+  if (src < 0 || src >= b->g->n)
+    return fg_set_error(FG_EINVAL, "fg_msbfs_admit: src=%d outside [0, %d)", src, b->g->n);
+  for (int i = 0; i < b->npend; ++i)
+    if (b->pend_lane[i] == lane)
+      return fg_set_error(FG_EINVAL, "fg_msbfs_admit: lane %d already pending", lane);
+  b->pend_lane[b->npend] = lane;
+  b->pend_src[b->npend] = src;
+  b->npend++;
+  b->admitted |= 1ull << lane;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
+  if (!b) return fg_set_error(FG_EINVAL, "fg_msbfs_step: batch is NULL");
+  if (k_iters < 0) return fg_set_error(FG_EINVAL, "fg_msbfs_step: negative k_iters");
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  fg_device_props pr = fg_props(dev);
+  if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_msbfs_step: no cooperative launch");
+  if (dev >= 0 && dev < 64 && g_ms_occ[dev] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, msbfs_persistent, PB, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_ms_occ[dev] = nb;
+  }
+  int bpc = (dev >= 0 && dev < 64) ? g_ms_occ[dev] : 1;
+  if (bpc > 2) bpc = 2;
+  if (b->opts.blocks_per_cu > 0 && b->opts.blocks_per_cu < bpc) bpc = b->opts.blocks_per_cu;
+  const fg_graph* g = b->g;
+  MsParams P;
+  memset(&P, 0, sizeof(P));
+  P.off = g->off;
+  P.col = g->col;
+  P.n = g->n;
+  P.m = g->m;
+  P.lanes = b->lanes;
+  P.visit = b->lay.visit;
+  P.F[0] = b->lay.F[0];
+  P.F[1] = b->lay.F[1];
+  P.q[0] = b->lay.q[0];
+  P.q[1] = b->lay.q[1];
+  P.desc = b->lay.desc;
+  P.depth = b->lay.depth;
+  P.state = b->lay.state;
+  P.ctl = b->lay.ctl;
+  P.k_iters = k_iters;
+  P.npend = b->npend;
+  for (int i = 0; i < b->npend; ++i) {
+    P.pend_lane[i] = b->pend_lane[i];
+    P.pend_src[i] = b->pend_src[i];
+  }
+  P.big_deg = b->opts.big_degree > 0 ? b->opts.big_degree : 64;
+  P.pull_div = b->opts.pull_div > 0 ? b->opts.pull_div : 64;
+  P.push_div = b->opts.push_div > 0 ? b->opts.push_div : 512;
+  void* args[] = {&P};
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)msbfs_persistent, dim3(pr.cus * bpc),
+                                        dim3(PB), args, 0, (hipStream_t)stream));
+  b->npend = 0;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_poll(fg_msbfs* b, uint64_t* done_lanes, int32_t* iterations,
+                                   void* stream) {
+  if (!b) return fg_set_error(FG_EINVAL, "fg_msbfs_poll: batch is NULL");
+  MsState hs;
+  hipStream_t s = (hipStream_t)stream;
+  FG_HIP_TRY(hipMemcpyAsync(&hs, b->lay.state, sizeof(MsState), hipMemcpyDeviceToHost, s));
+  FG_HIP_TRY(hipStreamSynchronize(s));
+  uint64_t pend = 0;
+  for (int i = 0; i < b->npend; ++i) pend |= 1ull << b->pend_lane[i];
+  if (done_lanes) *done_lanes = b->admitted & ~hs.live & ~pend;
+  if (iterations) *iterations = hs.it;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_read(fg_msbfs* b, int32_t lane, int32_t* depth, void* stream) {
+  if (!b || !depth) return fg_set_error(FG_EINVAL, "fg_msbfs_read: NULL argument");
+  if (lane < 0 || lane >= b->lanes)
+    return fg_set_error(FG_EINVAL, "fg_msbfs_read: lane=%d outside [0, %d)", lane, b->lanes);
+  FG_HIP_TRY(hipMemcpyAsync(depth, b->lay.depth + (size_t)lane * b->g->n,
+                            sizeof(int32_t) * (size_t)b->g->n, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_release(fg_msbfs* b, int32_t lane) {
+  if (!b) return fg_set_error(FG_EINVAL, "fg_msbfs_release: batch is NULL");
+  if (lane < 0 || lane >= b->lanes)
+    return fg_set_error(FG_EINVAL, "fg_msbfs_release: lane=%d outside [0, %d)", lane, b->lanes);
+  b->admitted &= ~(1ull << lane);
+  return FG_OK;
+}

@@ -1,0 +1,151 @@
+"""Parity of the 64-lane batched BFS: every lane's depths equal the oracle's
+BFS from that lane's source (and fg_bfs's), alone or in the mix, including
+lanes admitted mid-flight and lanes reused after release."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import announce, gpu, need_gpu, to_np
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def fg():
+    need_gpu()
+    import paper_1504_04804_amd as fg
+    fg.lib()
+    return fg
+
+
+def check_lanes(fg, orc, b, off, col, srcs):
+    for lane, s in srcs.items():
+        got = to_np(b.read(lane))
+        want = orc.bfs(off, col, int(s))[0]
+        assert np.array_equal(got, want), f"lane {lane} src {s}: {np.flatnonzero(got != want)[:8]}"
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(pull_div=1), dict(pull_div=1 << 30, push_div=1 << 30),
+                                  dict(big_degree=4)])
+def test_rmat12_64_lanes(fg, orc, opts):
+    off, col = synth.rmat_csr(12)
+    g = fg.Graph(off, col)
+    srcs = {i: int(s) for i, s in enumerate(synth.sources(off, 64, seed=11))}
+    announce(f"msbfs rmat12 64 lanes {opts}")
+    b = fg.MsBatch(g, 64, fg.msbfs_opts(**opts))
+    for lane, s in srcs.items():
+        b.admit(lane, s)
+    b.run(k_iters=4)
+    check_lanes(fg, orc, b, off, col, srcs)
+
+
+def test_few_lanes_duplicates_isolated(fg, orc):
+    off, col = synth.from_edge_pairs(300, [(i, i + 1) for i in range(250)] + [(0, 260)])
+    g = fg.Graph(off, col)
+    srcs = {0: 5, 1: 5, 2: 299, 3: 120, 7: 0}
+    b = fg.MsBatch(g, 8)
+    for lane, s in srcs.items():
+        b.admit(lane, s)
+    b.run(k_iters=64)
+    check_lanes(fg, orc, b, off, col, srcs)
+
+
+def test_continuous_admission_and_reuse(fg, orc):
+    off, col = synth.rmat_csr(13)
+    g = fg.Graph(off, col)
+    src = synth.sources(off, 96, seed=5)
+    b = fg.MsBatch(g, 64)
+    first = {i: int(src[i]) for i in range(32)}
+    for lane, s in first.items():
+        b.admit(lane, s)
+    b.step(2)                       # mid-flight
+    second = {32 + i: int(src[32 + i]) for i in range(32)}
+    for lane, s in second.items():
+        b.admit(lane, s)
+    b.run(k_iters=3)
+    check_lanes(fg, orc, b, off, col, {**first, **second})
+    # reuse lanes 3, 40, 63 for new queries while the others stay done
+    again = {3: int(src[64]), 40: int(src[65]), 63: int(src[66])}
+    for lane in again:
+        b.release(lane)
+    for lane, s in again.items():
+        b.admit(lane, s)
+    b.run(k_iters=5)
+    check_lanes(fg, orc, b, off, col, again)
+    check_lanes(fg, orc, b, off, col, {5: first[5], 50: second[50]})  # untouched lanes
+
+
+def test_alone_equals_in_the_mix(fg, orc):
+    off, col = synth.rmat_csr(12)
+    g = fg.Graph(off, col)
+    srcs = [int(s) for s in synth.sources(off, 64, seed=2)]
+    b = fg.MsBatch(g, 64)
+    for lane, s in enumerate(srcs):
+        b.admit(lane, s)
+    b.run()
+    alone = fg.MsBatch(g, 1)
+    for lane in (0, 17, 63):
+        single, _, _ = fg.bfs(g, srcs[lane], mode=fg.FG_MODE_DO)
+        mix = to_np(b.read(lane))
+        alone.admit(0, srcs[lane])
+        alone.run()
+        assert np.array_equal(mix, to_np(single))
+        assert np.array_equal(mix, to_np(alone.read(0)))
+
+
+def test_grid_64_sources_closed_form(fg):
+    R = C = 96
+    off, col = synth.grid_csr(R, C)
+    g = fg.Graph(off, col)
+    rng = np.random.default_rng(4)
+    srcs = rng.choice(R * C, 64, replace=False)
+    b = fg.MsBatch(g, 64)
+    for lane, s in enumerate(srcs):
+        b.admit(lane, int(s))
+    b.run(k_iters=32)
+    rr, cc = np.divmod(np.arange(R * C), C)
+    for lane, s in enumerate(srcs):
+        r0, c0 = divmod(int(s), C)
+        assert np.array_equal(to_np(b.read(lane)), np.abs(rr - r0) + np.abs(cc - c0))
+
+
+def test_msbfs_argument_errors(fg):
+    off, col = synth.from_edge_pairs(4, [(0, 1)])
+    g = fg.Graph(off, col)
+    b = fg.MsBatch(g, 4)
+    for bad in ((4, 0), (-1, 0), (0, 4), (0, -1)):
+        with pytest.raises(fg.FGError):
+            b.admit(*bad)
+    b.admit(1, 0)
+    with pytest.raises(fg.FGError):
+        b.admit(1, 2)  # already pending
+
+
+@pytest.mark.slow
+def test_config_rmat23_64_sources(fg, orc):
+    off, col = synth.rmat_csr(23)
+    g = fg.Graph(off, col)
+    srcs = [int(s) for s in synth.sources(off, 64, seed=23)]
+    b = fg.MsBatch(g, 64)
+    for lane, s in enumerate(srcs):
+        b.admit(lane, s)
+    b.run(k_iters=8)
+    check_lanes(fg, orc, b, off, col, {lane: srcs[lane] for lane in (0, 31, 63)})
+
+
+@pytest.mark.slow
+def test_config_grid2048_64_sources(fg):
+    R = 2048
+    off, col = synth.grid_csr(R, R)
+    g = fg.Graph(off, col)
+    rng = np.random.default_rng(7)
+    srcs = rng.choice(R * R, 64, replace=False)
+    b = fg.MsBatch(g, 64)
+    for lane, s in enumerate(srcs):
+        b.admit(lane, int(s))
+    b.run(k_iters=512)
+    rr, cc = np.divmod(np.arange(R * R, dtype=np.int64), R)
+    for lane in range(0, 64, 9):
+        r0, c0 = divmod(int(srcs[lane]), R)
+        assert np.array_equal(to_np(b.read(lane)), np.abs(rr - r0) + np.abs(cc - c0))
