@@ -261,6 +261,33 @@ def main():
         "device_status_errors": status_bad,
         "timed_region_ms": round(total_ms, 3),
     }
+    # batched queries (the same 64 sources on the same graph, one 64-lane
+    # batched traversal), outside the step: queries/s and per-query latency
+    b = fg.MsBatch(g, NSRC)
+    bt = []
+    for rep in range(3):
+        for lane, s in enumerate(srcs):
+            if rep:
+                b.release(lane)
+            b.admit(lane, int(s))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(1 << 20, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bt.append(e0.elapsed_time(e1))
+    done, _ = b.poll()
+    ms_b = float(np.median(bt))
+    out["batched"] = {
+        "queries": NSRC, "ms_per_batch": round(ms_b, 3),
+        "queries_per_s": round(NSRC / (ms_b * 1e-3), 1),
+        "latency_ms_p50": round(ms_b, 3), "latency_ms_p99": round(float(np.max(bt)), 3),
+        "all_done": done == (1 << NSRC) - 1,
+        "vs_one_at_a_time_qps": round((NSRC / (ms_b * 1e-3)) / (1000.0 / do_ms), 2),
+        "note": "64-lane batched BFS (depths only) over the same sources; every query of a batch "
+                "completes at the batch end, so p50 = the batch time",
+    }
+    b.close()
     if not args.no_cpu:
         nsamp = max(1, min(args.cpu_sources, NSRC))
         gteps, secs = cpu_baseline(off, col, srcs[:nsamp], goff, gcol)

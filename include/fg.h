@@ -168,6 +168,10 @@ typedef struct {
   int32_t big_degree;     /* push: vertices of at least this degree are
                              expanded by the whole grid (0 = default)         */
   int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
+  int32_t team_blocks;    /* team mode width: workgroups that run medium
+                             levels alone (0 = default, < 0 = off); used only
+                             when every degree is below big_degree          */
+  int32_t team_frontier;  /* team mode while |Q| <= this (0 = default)       */
 } fg_bfs_opts;
 
 /* Fill *opts with the defaults (DO mode, do_a = 1/100, do_b = 1/10). */

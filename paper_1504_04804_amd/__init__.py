@@ -68,6 +68,8 @@ class BfsOpts(ctypes.Structure):
         ("small_edges", ctypes.c_int32),
         ("big_degree", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
+        ("team_blocks", ctypes.c_int32),
+        ("team_frontier", ctypes.c_int32),
     ]
 
 
@@ -206,7 +208,7 @@ def last_error():
 
 
 def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, small_edges=0,
-             big_degree=0, blocks_per_cu=0):
+             big_degree=0, blocks_per_cu=0, team_blocks=0, team_frontier=0):
     o = BfsOpts()
     lib().fg_bfs_opts_default(ctypes.byref(o))
     o.mode = mode
@@ -216,6 +218,8 @@ def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, sma
     o.small_edges = small_edges
     o.big_degree = big_degree
     o.blocks_per_cu = blocks_per_cu
+    o.team_blocks = team_blocks
+    o.team_frontier = team_frontier
     return o
 
 
@@ -234,6 +238,7 @@ class Graph:
             w = w.to(device).contiguous()
         self.n = off.numel() - 1
         self.m = col.numel()
+        self.symmetric = bool(symmetric)
         # the library keeps its own copies (no FG_BORROW)
         flags = FG_DEVICE_PTRS | (FG_VALIDATE if validate else 0) | (FG_SYMMETRIC if symmetric else 0)
         h = ctypes.c_void_p()

@@ -36,6 +36,8 @@ constexpr int DIR_PUSH = 0, DIR_PULL = 1;
 constexpr int32_t DEF_SMALL_Q = 1024;
 constexpr int64_t DEF_SMALL_E = 4096;
 constexpr int32_t DEF_BIG_DEG = 64;
+constexpr int32_t DEF_TEAM = 16;
+constexpr int64_t DEF_TEAM_Q = 65536;
 
 typedef unsigned __int128 u128;
 typedef unsigned long long ull;
@@ -59,12 +61,15 @@ struct alignas(256) BfsCtl {
   uint32_t pad2[63];
   uint32_t exit_count;         // workgroups that left the launch
   uint32_t pad3[63];
+  uint32_t team_arrive;        // barrier of the team (workgroups 0..team-1)
+  uint32_t pad4[63];
   Line64 aux;                  // entries written by bitmap -> queue conversion
   CtrSlot slot[2];
-  // state published by workgroup 0 when a small-frontier episode ends
+  // state published by workgroup 0 when a small-frontier / team episode ends
   int32_t pub_k, pub_dir, pub_prevdir, pub_switched, pub_qsel, pub_force;
   int64_t pub_qlen, pub_p, pub_insp_sum;
   int32_t pub_switches;
+  ull pub_b[6];
 };
 
 struct BfsParams {
@@ -88,6 +93,8 @@ struct BfsParams {
   int64_t small_e;
   int32_t big_deg;
   int32_t clock_khz;
+  int32_t team;     // workgroups of the team mode (0 = off)
+  int64_t team_q;   // team mode while small_q < |Q| <= team_q
 };
 
 // Per-iteration state, identical in every workgroup.
@@ -210,7 +217,7 @@ struct Lds {
 // ---- push, full grid, phase A: each wave takes 64-entry chunks of the
 // frontier (static stride).  Vertices below big_deg are expanded by a
 // wave-level scan-gather; the others become CH-edge descriptors.
-__device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
+__device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t nblocks) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int32_t* Qin = P.q[S.qsel];
@@ -225,7 +232,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L) {
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
   WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
-  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  const int64_t W = (int64_t)nblocks * PWAVES;
   int64_t insp = 0;
   for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
@@ -476,6 +483,55 @@ __device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
   }
 }
 
+// ---- team mode: workgroups 0..team-1 run push levels back to back with a
+// barrier among themselves while small_q < |Q| <= team_q; the other
+// workgroups wait.  Used only when no vertex reaches big_degree, so every
+// vertex is expanded by the scan-gather (no descriptors, one barrier per
+// level).
+struct TeamSync {
+  uint32_t* arrive;
+  uint32_t* abort_flag;
+  uint32_t T;
+  uint32_t count;
+
+  __device__ bool sync(int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+};
+
+template <int MODE>
+__device__ bool team_mode(const BfsParams& P, St& S, Lds& L, TeamSync& ts) {
+  for (;;) {
+    CtrSlot& C = P.ctl->slot[S.k & 1];
+    Bases B = get_bases(S);
+    push_phase_a(P, S, L, ts.T);
+    if (!ts.sync(&L.flag)) return false;
+    const ull qt = fg_atomic_load_u64(&C.q.v);
+    const ull it = fg_atomic_load_u64(&C.insp.v);
+    const int64_t nq = (int64_t)(qt - B.q);
+    const int64_t insp = (int64_t)(it - B.insp);
+    B.q = qt;
+    B.insp = it;
+    set_bases(S, B);
+    trace_insp(S.k, insp, P);
+    S.insp_sum += insp;
+    S.k++;
+    S.qsel ^= 1;
+    S.qlen = nq;
+    S.p += nq;
+    decide<MODE>(S, P);
+    trace_iter(S, P);
+    if (nq == 0 || S.dir != DIR_PUSH || nq > P.team_q || nq <= P.small_q) return true;
+  }
+}
+
 // MODE is FG_MODE_DO or FG_MODE_PUSH (one kernel per mode).
 template <int MODE>
 __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
@@ -489,6 +545,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   uint32_t sm_seen = 0;
   int force_full = 0;
   bool ok = true;
+  TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
   {
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
@@ -542,12 +599,20 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
       S.prevdir = DIR_PUSH;
     }
-    if (S.dir == DIR_PUSH && !force_full && S.qlen <= P.small_q) {
+    const bool small_ep = S.dir == DIR_PUSH && !force_full && S.qlen <= P.small_q;
+    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qlen <= P.team_q &&
+                         (S.qlen > P.small_q || force_full);
+    if (small_ep || team_ep) {
       sm_seen++;
-      if (blockIdx.x == 0) {
+      const bool member = small_ep ? blockIdx.x == 0 : blockIdx.x < (uint32_t)P.team;
+      if (member) {
         int ff = 0;
-        small_mode<MODE>(P, S, L, &ff);
-        if (threadIdx.x == 0) {
+        if (small_ep) {
+          small_mode<MODE>(P, S, L, &ff);
+        } else if (!team_mode<MODE>(P, S, L, ts)) {
+          ok = false;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
           BfsCtl* c = P.ctl;
           c->pub_k = S.k;
           c->pub_dir = S.dir;
@@ -559,10 +624,17 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
           c->pub_p = S.p;
           c->pub_insp_sum = S.insp_sum;
           c->pub_switches = S.switches;
+          c->pub_b[0] = S.b0q;
+          c->pub_b[1] = S.b0desc;
+          c->pub_b[2] = S.b0insp;
+          c->pub_b[3] = S.b1q;
+          c->pub_b[4] = S.b1desc;
+          c->pub_b[5] = S.b1insp;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         force_full = ff;
         __syncthreads();
+        if (!ok) break;
       } else {
         if (threadIdx.x == 0) {
           const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 64);
@@ -579,6 +651,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
             L.bcast[7] = c->pub_p;
             L.bcast[8] = c->pub_insp_sum;
             L.bcast[9] = c->pub_switches;
+            for (int i = 0; i < 6; ++i) L.bcast[10 + i] = (int64_t)c->pub_b[i];
           }
         }
         __syncthreads();
@@ -596,6 +669,12 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         S.p = L.bcast[7];
         S.insp_sum = L.bcast[8];
         S.switches = (int32_t)L.bcast[9];
+        S.b0q = (ull)L.bcast[10];
+        S.b0desc = (ull)L.bcast[11];
+        S.b0insp = (ull)L.bcast[12];
+        S.b1q = (ull)L.bcast[13];
+        S.b1desc = (ull)L.bcast[14];
+        S.b1insp = (ull)L.bcast[15];
         __syncthreads();
       }
       continue;
@@ -604,7 +683,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
     if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
-      push_phase_a(P, S, L);
+      push_phase_a(P, S, L, gridDim.x);
       if (!(ok = gs.sync(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - B.desc);

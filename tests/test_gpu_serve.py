@@ -1,0 +1,63 @@
+"""Serving: continuous batching over resident graphs.  Every result of the
+mixed stream must equal the oracle's answer for that query alone, and the
+one-at-a-time path must give the same answers."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import announce, gpu, need_gpu, to_np
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    need_gpu()
+    import paper_1504_04804_amd as fg
+    from paper_1504_04804_amd import serve
+    specs, graphs, csr = {}, {}, {}
+    for name, (off, col) in {
+        "rmat10": synth.rmat_csr(10), "rmat12": synth.rmat_csr(12),
+        "grid40": synth.grid_csr(40, 40), "grid24x70": synth.grid_csr(24, 70),
+    }.items():
+        w = synth.weights(off, col)
+        graphs[name] = fg.Graph(off, col, weights=w)
+        specs[name] = (off, True)
+        csr[name] = (off, col, w)
+    return fg, serve, specs, graphs, csr
+
+
+def check_results(orc, csr, done, serve):
+    for r in done:
+        off, col, w = csr[r.graph]
+        got = to_np(r.result)
+        if r.kind == serve.BFS:
+            want = orc.bfs(off, col, r.src)[0]
+            assert np.array_equal(got, want), (r.rid, r.graph, r.src)
+        else:
+            want = orc.dijkstra(off, col, w, r.src)[0]
+            assert np.array_equal(got.astype(np.uint32), want), (r.rid, r.graph, r.src)
+
+
+@pytest.mark.parametrize("budget,k", [(32 << 30, 4), (1 << 22, 1)])
+def test_served_mix_equals_alone(env, orc, budget, k):
+    fg, serve, specs, graphs, csr = env
+    reqs = serve.make_requests(specs, 160, qps=20000.0, seed=budget & 0xFFFF)
+    announce(f"serve 160 requests budget={budget} k={k}")
+    srv = serve.Server(graphs, hbm_budget=budget, k_iters=k)
+    done = serve.serve_stream(srv, reqs, time_limit=120)
+    assert len(done) == len(reqs)
+    assert all(r.done >= r.arrival for r in done)
+    check_results(orc, csr, done, serve)
+    # lanes really were shared: some batched steps ran with several queries
+    st = serve.latency_stats(done)
+    assert st["n"] == len(reqs)
+
+
+def test_fifo_path_same_answers(env, orc):
+    fg, serve, specs, graphs, csr = env
+    reqs = serve.make_requests(specs, 40, qps=5000.0, seed=3)
+    ws = {n: g.workspace(fg.FG_PRIM_SSSP) for n, g in graphs.items()}
+    done = serve.serve_fifo(graphs, reqs, ws, time_limit=120)
+    check_results(orc, csr, done, serve)
