@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sources", type=int, default=8)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy three times (for the "
+                         "rocprof FETCH_SIZE / WRITE_SIZE scale factor)")
     return ap.parse_args()
 
 
@@ -116,6 +119,13 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.calibration_copy:
+        a = torch.ones(128 << 20, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.time()
     off, col = synth.rmat_csr(SCALE, EDGE_FACTOR)
     srcs = synth.sources(off, NSRC)

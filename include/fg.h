@@ -169,9 +169,9 @@ typedef struct {
                              expanded by the whole grid (0 = default)         */
   int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
   int32_t team_blocks;    /* team mode width: workgroups that run medium
-                             levels alone (0 = default, < 0 = off); used only
-                             when every degree is below big_degree          */
-  int32_t team_frontier;  /* team mode while |Q| <= this (0 = default)       */
+                             levels alone (0 = default, < 0 = off)          */
+  int32_t team_edges;     /* team mode while the frontier's degree sum is at
+                             most this (0 = default)                         */
 } fg_bfs_opts;
 
 /* Fill *opts with the defaults (DO mode, do_a = 1/100, do_b = 1/10). */
@@ -395,6 +395,20 @@ size_t fg_package_workspace_bytes(const fg_share* s, int32_t max_len);
 fg_status fg_package(const fg_share* s, const int32_t* frontier, int32_t len,
                      const int32_t* depth, const int32_t* parent, const fg_peer_bufs* out,
                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Combine (Sec. III-B merge step; Alg. 1 combination rule): for each
+ * received vertex ids[i] (device, local ids of the receiving share) that is
+ * not yet set in `visited` (device uint32 bitmask, bit v%32 of word v/32),
+ * atomically mark it, set depth[v] = labels[i] (and parent[v] = parents[i]
+ * when both are given) and append v to out_q at position atomicAdd(out_len).
+ * *out_len (device int32) is not reset, so received vertices can be appended
+ * after the local sub-frontier.  A vertex received several times is taken
+ * once.  Errors: FG_EINVAL.
+ */
+fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int32_t* labels,
+                     const int32_t* parents, int32_t len, uint32_t* visited, int32_t* depth,
+                     int32_t* parent, int32_t* out_q, int32_t* out_len, void* stream);
 
 #ifdef __cplusplus
 }

@@ -69,7 +69,7 @@ class BfsOpts(ctypes.Structure):
         ("big_degree", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
         ("team_blocks", ctypes.c_int32),
-        ("team_frontier", ctypes.c_int32),
+        ("team_edges", ctypes.c_int32),
     ]
 
 
@@ -161,6 +161,7 @@ SIGNATURES = {
     "fg_share_tables": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "fg_package_workspace_bytes": (_SZ, [_P, _I32]),
     "fg_package": (_I32, [_P, _P, _I32, _P, _P, ctypes.POINTER(PeerBufs), _P, _SZ, _P]),
+    "fg_combine": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _I64, _P, _P, _SZ, _P]),
     "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
@@ -208,7 +209,7 @@ def last_error():
 
 
 def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, small_edges=0,
-             big_degree=0, blocks_per_cu=0, team_blocks=0, team_frontier=0):
+             big_degree=0, blocks_per_cu=0, team_blocks=0, team_edges=0):
     o = BfsOpts()
     lib().fg_bfs_opts_default(ctypes.byref(o))
     o.mode = mode
@@ -219,7 +220,7 @@ def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, sma
     o.big_degree = big_degree
     o.blocks_per_cu = blocks_per_cu
     o.team_blocks = team_blocks
-    o.team_frontier = team_frontier
+    o.team_edges = team_edges
     return o
 
 
@@ -535,3 +536,14 @@ class MsBatch:
             self.close()
         except Exception:
             pass
+
+
+def combine(graph_handle, ids, labels, parents, length, visited, depth, parent, out_q, out_len):
+    """fg_combine on the graph handle (e.g. Share.graph_handle)."""
+    _check(lib().fg_combine(graph_handle, _ptr(ids), _ptr(labels), _ptr(parents), int(length),
+                            _ptr(visited), _ptr(depth), _ptr(parent), _ptr(out_q), _ptr(out_len),
+                            _stream()))
+
+
+def _op_handle(g):
+    return g.handle if isinstance(g, Graph) else g

@@ -37,7 +37,7 @@ constexpr int32_t DEF_SMALL_Q = 1024;
 constexpr int64_t DEF_SMALL_E = 4096;
 constexpr int32_t DEF_BIG_DEG = 64;
 constexpr int32_t DEF_TEAM = 16;
-constexpr int64_t DEF_TEAM_Q = 65536;
+constexpr int64_t DEF_TEAM_E = 65536;
 
 typedef unsigned __int128 u128;
 typedef unsigned long long ull;
@@ -50,6 +50,7 @@ struct CtrSlot {
   Line64 q;      // vertices discovered
   Line64 desc;   // edge-chunk descriptors written
   Line64 insp;   // CSR entries read
+  Line64 deg;    // sum of the degrees of the discovered vertices
 };
 
 // The control block is zero when a launch starts: a fresh workspace is
@@ -69,7 +70,8 @@ struct alignas(256) BfsCtl {
   int32_t pub_k, pub_dir, pub_prevdir, pub_switched, pub_qsel, pub_force;
   int64_t pub_qlen, pub_p, pub_insp_sum;
   int32_t pub_switches;
-  ull pub_b[6];
+  int64_t pub_qdeg;
+  ull pub_b[8];
 };
 
 struct BfsParams {
@@ -94,7 +96,7 @@ struct BfsParams {
   int32_t big_deg;
   int32_t clock_khz;
   int32_t team;     // workgroups of the team mode (0 = off)
-  int64_t team_q;   // team mode while small_q < |Q| <= team_q
+  int64_t team_e;   // team mode while the frontier's degree sum <= team_e
 };
 
 // Per-iteration state, identical in every workgroup.
@@ -107,17 +109,18 @@ struct St {
   int32_t cur;       // visited bitmap holding levels <= k
   int32_t switches;
   int64_t qlen;      // |Q| of iteration k
+  int64_t qdeg;      // sum of the degrees of Q (edges a push would read)
   int64_t p;         // |P|: vertices with a depth, Q included
   int64_t insp_sum;  // CSR entries read so far
   // last read value of slot[p].{q, desc, insp}; kept as scalars so the
   // parity select does not force the state into scratch memory
-  ull b0q, b0desc, b0insp;
-  ull b1q, b1desc, b1insp;
+  ull b0q, b0desc, b0insp, b0deg;
+  ull b1q, b1desc, b1insp, b1deg;
   ull auxbase;
 };
 
 struct Bases {
-  ull q, desc, insp;
+  ull q, desc, insp, deg;
 };
 
 __device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
@@ -128,7 +131,8 @@ __device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
 
 __device__ __forceinline__ Bases get_bases(const St& S) {
   const bool odd = S.k & 1;
-  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1desc, S.b0desc), sel(odd, S.b1insp, S.b0insp)};
+  return Bases{sel(odd, S.b1q, S.b0q), sel(odd, S.b1desc, S.b0desc), sel(odd, S.b1insp, S.b0insp),
+               sel(odd, S.b1deg, S.b0deg)};
 }
 
 __device__ __forceinline__ void set_bases(St& S, const Bases& b) {
@@ -136,9 +140,11 @@ __device__ __forceinline__ void set_bases(St& S, const Bases& b) {
   S.b1q = sel(odd, b.q, S.b1q);
   S.b1desc = sel(odd, b.desc, S.b1desc);
   S.b1insp = sel(odd, b.insp, S.b1insp);
+  S.b1deg = sel(odd, b.deg, S.b1deg);
   S.b0q = sel(odd, S.b0q, b.q);
   S.b0desc = sel(odd, S.b0desc, b.desc);
   S.b0insp = sel(odd, S.b0insp, b.insp);
+  S.b0deg = sel(odd, S.b0deg, b.deg);
 }
 
 // Direction rule of Sec. VI-A for the iteration described by S (k >= 1):
@@ -211,7 +217,7 @@ struct Lds {
   int32_t red32[PWAVES + 1];
   int32_t newcnt;
   int32_t flag;
-  int64_t bcast[16];
+  int64_t bcast[20];
 };
 
 // ---- push, full grid, phase A: each wave takes 64-entry chunks of the
@@ -233,7 +239,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
   WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)nblocks * PWAVES;
-  int64_t insp = 0;
+  int64_t insp = 0, ndeg = 0;
   for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
     int32_t u = 0, b = 0, deg = 0;
@@ -282,6 +288,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
         const int32_t j = upper_idx(sc, FG_WAVE, t);
         v = P.col[sb[j] + (t - sc[j])];
         won = try_visit(v, su[j], d_new, vis32, P);
+        if (won) ndeg += P.off[v + 1] - P.off[v];
       }
       st.push(won, v, &C.q.v, B.q, Qout);
     }
@@ -289,17 +296,23 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
   st.flush(&C.q.v, B.q, Qout);
   dst.flush(&C.desc.v, B.desc, P.desc);
   const int64_t tot = fg_block_sum<PB>(insp, L.red);
-  if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
+  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
+  if (threadIdx.x == 0) {
+    if (tot) atomicAdd(&C.insp.v, (ull)tot);
+    if (tdeg) atomicAdd(&C.deg.v, (ull)tdeg);
+  }
 }
 
 // ---- push, full grid, phase B: waves take descriptors in turn; the CH
 // edges of a descriptor are contiguous, so each round is one coalesced read
 // of 64 column indices and no search is needed.
-__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds& L) {
+__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds& L,
+                             uint32_t nblocks) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
-  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  const int64_t W = (int64_t)nblocks * PWAVES;
+  int64_t ndeg = 0;
   int32_t* Qout = P.q[S.qsel ^ 1];
   uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
   const int32_t d_new = S.k + 1;
@@ -322,10 +335,13 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
     for (int r = 0; r < CH / FG_WAVE; ++r) {
       const int32_t v = vv[r];
       const bool won = v >= 0 && try_visit(v, u, d_new, vis32, P);
+      if (won) ndeg += P.off[v + 1] - P.off[v];
       st.push(won, v, &C.q.v, B.q, Qout);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
+  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
+  if (threadIdx.x == 0 && tdeg) atomicAdd(&C.deg.v, (ull)tdeg);
 }
 
 // ---- pull, full grid: each wave owns 64 consecutive vertices (one bitmap
@@ -342,7 +358,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   const uint64_t* Vin = P.vis[S.cur];
   uint64_t* Vout = P.vis[S.cur ^ 1];
   const int32_t d_new = S.k + 1;
-  int64_t insp = 0;
+  int64_t insp = 0, ndeg = 0;
   int32_t nnew = 0;
   for (int64_t w = gw; w < P.nwords; w += W) {
     const uint64_t vis = Vin[w];
@@ -353,8 +369,9 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
       bool found = false;
       int32_t pu = -1;
       if ((act >> lane) & 1ull) {
+        const int32_t b0 = P.off[v];
         const int32_t e = P.off[v + 1];
-        for (int32_t i = P.off[v]; i < e; ++i) {
+        for (int32_t i = b0; i < e; ++i) {
           const int32_t u = P.col[i];
           insp++;
           if ((Vin[u >> 6] >> (u & 63)) & 1ull) {
@@ -363,6 +380,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
             break;
           }
         }
+        if (found) ndeg += e - b0;
       }
       nb = __ballot(found);
       if (found) {
@@ -375,10 +393,12 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   }
   if (lane != 0) nnew = 0;
   const int64_t tot = fg_block_sum<PB>(insp, L.red);
+  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
   const int32_t tn = fg_block_sum<PB>(nnew, L.red32);
   CtrSlot& C = P.ctl->slot[S.k & 1];
   if (threadIdx.x == 0) {
     if (tot) atomicAdd(&C.insp.v, (ull)tot);
+    if (tdeg) atomicAdd(&C.deg.v, (ull)tdeg);
     if (tn) atomicAdd(&C.q.v, (ull)tn);
   }
 }
@@ -413,28 +433,17 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S) {
 
 // ---- small-frontier mode, workgroup 0 only: push levels run back to back
 // with workgroup barriers while |Q| <= small_q and the frontier's degree sum
-// <= small_e.  Returns with S describing the next iteration; *force_full is
-// set when the degree sum was too large for iteration S.k.
+// <= small_e.  Returns with S describing the next iteration.
 template <int MODE>
-__device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
+__device__ void small_mode(const BfsParams& P, St& S, Lds& L) {
   const int tid = threadIdx.x;
-  *force_full = 0;
   for (;;) {
     const int32_t* Qin = P.q[S.qsel];
     int32_t* Qout = P.q[S.qsel ^ 1];
     uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
-    int64_t s = 0;
-    for (int64_t i = tid; i < S.qlen; i += PB) {
-      const int32_t u = Qin[i];
-      s += P.off[u + 1] - P.off[u];
-    }
-    const int64_t sum = fg_block_sum<PB>(s, L.red);
-    if (sum > P.small_e) {
-      *force_full = 1;
-      return;
-    }
     if (tid == 0) L.newcnt = 0;
     const int32_t d_new = S.k + 1;
+    int64_t ndeg = 0;
     for (int64_t c0 = 0; c0 < S.qlen; c0 += PB) {
       const int64_t i = c0 + tid;
       int32_t u = 0, b = 0, d = 0;
@@ -458,6 +467,7 @@ __device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
           const int32_t j = upper_idx(L.b_sc, cnt, t);
           v = P.col[L.b_b[j] + (t - L.b_sc[j])];
           won = try_visit(v, L.b_u[j], d_new, vis32, P);
+          if (won) ndeg += P.off[v + 1] - P.off[v];
         }
         const uint64_t mask = __ballot(won);
         if (mask) {
@@ -469,25 +479,25 @@ __device__ void small_mode(const BfsParams& P, St& S, Lds& L, int* force_full) {
       }
       __syncthreads();
     }
-    const int64_t nq = L.newcnt;
-    trace_insp(S.k, sum, P);
-    S.insp_sum += sum;
+    const int64_t nqdeg = fg_uni(fg_block_sum<PB>(ndeg, L.red));
+    const int64_t nq = fg_uni((int64_t)L.newcnt);
+    trace_insp(S.k, S.qdeg, P);
+    S.insp_sum += S.qdeg;
     S.k++;
     S.qsel ^= 1;
     S.qlen = nq;
+    S.qdeg = nqdeg;
     S.p += nq;
     decide<MODE>(S, P);
     trace_iter(S, P);
     __syncthreads();
-    if (nq == 0 || S.dir != DIR_PUSH || nq > P.small_q) return;
+    if (nq == 0 || S.dir != DIR_PUSH || nq > P.small_q || nqdeg > P.small_e) return;
   }
 }
 
 // ---- team mode: workgroups 0..team-1 run push levels back to back with a
-// barrier among themselves while small_q < |Q| <= team_q; the other
-// workgroups wait.  Used only when no vertex reaches big_degree, so every
-// vertex is expanded by the scan-gather (no descriptors, one barrier per
-// level).
+// barrier among themselves while the frontier's degree sum is at most
+// team_e (and above the small-frontier limits); the other workgroups wait.
 struct TeamSync {
   uint32_t* arrive;
   uint32_t* abort_flag;
@@ -513,22 +523,35 @@ __device__ bool team_mode(const BfsParams& P, St& S, Lds& L, TeamSync& ts) {
     Bases B = get_bases(S);
     push_phase_a(P, S, L, ts.T);
     if (!ts.sync(&L.flag)) return false;
+    const ull dt = fg_atomic_load_u64(&C.desc.v);
+    const int64_t ndesc = (int64_t)(dt - B.desc);
+    if (ndesc > 0) {
+      push_phase_b(P, S, ndesc, L, ts.T);
+      if (!ts.sync(&L.flag)) return false;
+    }
+    B.desc = dt;
     const ull qt = fg_atomic_load_u64(&C.q.v);
     const ull it = fg_atomic_load_u64(&C.insp.v);
+    const ull gt = fg_atomic_load_u64(&C.deg.v);
     const int64_t nq = (int64_t)(qt - B.q);
     const int64_t insp = (int64_t)(it - B.insp);
+    const int64_t nqdeg = (int64_t)(gt - B.deg);
     B.q = qt;
     B.insp = it;
+    B.deg = gt;
     set_bases(S, B);
     trace_insp(S.k, insp, P);
     S.insp_sum += insp;
     S.k++;
     S.qsel ^= 1;
     S.qlen = nq;
+    S.qdeg = nqdeg;
     S.p += nq;
     decide<MODE>(S, P);
     trace_iter(S, P);
-    if (nq == 0 || S.dir != DIR_PUSH || nq > P.team_q || nq <= P.small_q) return true;
+    if (nq == 0 || S.dir != DIR_PUSH || nqdeg > P.team_e ||
+        (nq <= P.small_q && nqdeg <= P.small_e))
+      return true;
   }
 }
 
@@ -543,7 +566,6 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   S.qlen = 1;
   S.p = 1;
   uint32_t sm_seen = 0;
-  int force_full = 0;
   bool ok = true;
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
@@ -590,6 +612,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     P.stats->t_start = (int64_t)wall_clock64();
     P.stats->clock_khz = P.clock_khz;
   }
+  S.qdeg = fg_uni((int32_t)(P.off[P.src + 1] - P.off[P.src]));
   trace_iter(S, P);
   while (ok && S.qlen > 0) {
     // backward -> forward: list the last pull's discoveries first
@@ -599,16 +622,14 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
       S.prevdir = DIR_PUSH;
     }
-    const bool small_ep = S.dir == DIR_PUSH && !force_full && S.qlen <= P.small_q;
-    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qlen <= P.team_q &&
-                         (S.qlen > P.small_q || force_full);
+    const bool small_ep = S.dir == DIR_PUSH && S.qlen <= P.small_q && S.qdeg <= P.small_e;
+    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qdeg <= P.team_e;
     if (small_ep || team_ep) {
       sm_seen++;
       const bool member = small_ep ? blockIdx.x == 0 : blockIdx.x < (uint32_t)P.team;
       if (member) {
-        int ff = 0;
         if (small_ep) {
-          small_mode<MODE>(P, S, L, &ff);
+          small_mode<MODE>(P, S, L);
         } else if (!team_mode<MODE>(P, S, L, ts)) {
           ok = false;
         }
@@ -619,20 +640,21 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
           c->pub_prevdir = S.prevdir;
           c->pub_switched = S.switched;
           c->pub_qsel = S.qsel;
-          c->pub_force = ff;
           c->pub_qlen = S.qlen;
+          c->pub_qdeg = S.qdeg;
           c->pub_p = S.p;
           c->pub_insp_sum = S.insp_sum;
           c->pub_switches = S.switches;
           c->pub_b[0] = S.b0q;
           c->pub_b[1] = S.b0desc;
           c->pub_b[2] = S.b0insp;
-          c->pub_b[3] = S.b1q;
-          c->pub_b[4] = S.b1desc;
-          c->pub_b[5] = S.b1insp;
+          c->pub_b[3] = S.b0deg;
+          c->pub_b[4] = S.b1q;
+          c->pub_b[5] = S.b1desc;
+          c->pub_b[6] = S.b1insp;
+          c->pub_b[7] = S.b1deg;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        force_full = ff;
         __syncthreads();
         if (!ok) break;
       } else {
@@ -646,12 +668,12 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
             L.bcast[2] = c->pub_prevdir;
             L.bcast[3] = c->pub_switched;
             L.bcast[4] = c->pub_qsel;
-            L.bcast[5] = c->pub_force;
+            L.bcast[5] = c->pub_qdeg;
             L.bcast[6] = c->pub_qlen;
             L.bcast[7] = c->pub_p;
             L.bcast[8] = c->pub_insp_sum;
             L.bcast[9] = c->pub_switches;
-            for (int i = 0; i < 6; ++i) L.bcast[10 + i] = (int64_t)c->pub_b[i];
+            for (int i = 0; i < 8; ++i) L.bcast[10 + i] = (int64_t)c->pub_b[i];
           }
         }
         __syncthreads();
@@ -659,27 +681,28 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
           ok = false;
           break;
         }
-        S.k = (int32_t)L.bcast[0];
-        S.dir = (int32_t)L.bcast[1];
-        S.prevdir = (int32_t)L.bcast[2];
-        S.switched = (int32_t)L.bcast[3];
-        S.qsel = (int32_t)L.bcast[4];
-        force_full = (int)L.bcast[5];
-        S.qlen = L.bcast[6];
-        S.p = L.bcast[7];
-        S.insp_sum = L.bcast[8];
-        S.switches = (int32_t)L.bcast[9];
-        S.b0q = (ull)L.bcast[10];
-        S.b0desc = (ull)L.bcast[11];
-        S.b0insp = (ull)L.bcast[12];
-        S.b1q = (ull)L.bcast[13];
-        S.b1desc = (ull)L.bcast[14];
-        S.b1insp = (ull)L.bcast[15];
+        S.k = fg_uni((int32_t)L.bcast[0]);
+        S.dir = fg_uni((int32_t)L.bcast[1]);
+        S.prevdir = fg_uni((int32_t)L.bcast[2]);
+        S.switched = fg_uni((int32_t)L.bcast[3]);
+        S.qsel = fg_uni((int32_t)L.bcast[4]);
+        S.qdeg = fg_uni(L.bcast[5]);
+        S.qlen = fg_uni(L.bcast[6]);
+        S.p = fg_uni(L.bcast[7]);
+        S.insp_sum = fg_uni(L.bcast[8]);
+        S.switches = fg_uni((int32_t)L.bcast[9]);
+        S.b0q = fg_uni((ull)L.bcast[10]);
+        S.b0desc = fg_uni((ull)L.bcast[11]);
+        S.b0insp = fg_uni((ull)L.bcast[12]);
+        S.b0deg = fg_uni((ull)L.bcast[13]);
+        S.b1q = fg_uni((ull)L.bcast[14]);
+        S.b1desc = fg_uni((ull)L.bcast[15]);
+        S.b1insp = fg_uni((ull)L.bcast[16]);
+        S.b1deg = fg_uni((ull)L.bcast[17]);
         __syncthreads();
       }
       continue;
     }
-    force_full = 0;
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
     if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
@@ -688,7 +711,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - B.desc);
       if (ndesc > 0) {
-        push_phase_b(P, S, ndesc, L);
+        push_phase_b(P, S, ndesc, L, gridDim.x);
         if (!(ok = gs.sync(&L.flag))) break;
       }
       B.desc = dt;
@@ -700,10 +723,13 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     }
     const ull qt = fg_atomic_load_u64(&C.q.v);
     const ull it = fg_atomic_load_u64(&C.insp.v);
+    const ull gt = fg_atomic_load_u64(&C.deg.v);
     const int64_t nq = (int64_t)(qt - B.q);
     const int64_t insp = (int64_t)(it - B.insp);
     B.q = qt;
     B.insp = it;
+    S.qdeg = (int64_t)(gt - B.deg);
+    B.deg = gt;
     set_bases(S, B);
     trace_insp(S.k, insp, P);
     S.insp_sum += insp;

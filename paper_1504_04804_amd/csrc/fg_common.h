@@ -101,11 +101,25 @@ __device__ __forceinline__ T fg_wave_sum(T x) {
   return x;
 }
 
+// Wave-uniform copies (scalar registers) of values every lane holds equally.
+__device__ __forceinline__ int32_t fg_uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t fg_uni(int64_t x) {
+  const int32_t lo = __builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(uint64_t)x);
+  const int32_t hi = __builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ unsigned long long fg_uni(unsigned long long x) {
+  return (unsigned long long)fg_uni((int64_t)x);
+}
+
 __device__ __forceinline__ uint32_t fg_atomic_load_u32(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Relaxed load of a counter every lane reads at the same address; the result
+// is made wave-uniform so the compiler keeps it in scalar registers.
 __device__ __forceinline__ unsigned long long fg_atomic_load_u64(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return fg_uni((unsigned long long)__hip_atomic_load(p, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
 }
 
 // Bounded wait: poll `*p` (relaxed, no cache invalidation per poll) until

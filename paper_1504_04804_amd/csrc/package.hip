@@ -148,6 +148,41 @@ __global__ void pkg_scatter_kernel(const int32_t* __restrict__ frontier, int32_t
   }
 }
 
+// Combine received vertices with the local state (the framework's merge
+// step; for BFS a received vertex not yet visited takes the received label
+// and joins the next input frontier).  Test-and-set on the visited bitmap,
+// so a vertex received from several peers (or also found locally) is
+// taken once.
+__global__ void combine_kernel(const int32_t* __restrict__ ids, const int32_t* __restrict__ labels,
+                               const int32_t* __restrict__ parents, int32_t len,
+                               uint32_t* __restrict__ visited, int32_t* __restrict__ depth,
+                               int32_t* __restrict__ parent, int32_t* __restrict__ out_q,
+                               int32_t* __restrict__ out_len) {
+  const int lane = fg_lane();
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < len; i0 += nth) {
+    const int64_t i = i0 + lane;
+    bool won = false;
+    int32_t v = 0;
+    if (i < len) {
+      v = ids[i];
+      const uint32_t bit = 1u << (v & 31);
+      if (!(visited[v >> 5] & bit) && !(atomicOr(&visited[v >> 5], bit) & bit)) {
+        won = true;
+        depth[v] = labels[i];
+        if (parent && parents) parent[v] = parents[i];
+      }
+    }
+    const uint64_t mask = __ballot(won);
+    if (mask) {
+      int32_t pos = 0;
+      if (lane == 0) pos = atomicAdd(out_len, __popcll(mask));
+      pos = __shfl(pos, 0, FG_WAVE);
+      if (won) out_q[pos + fg_mbcnt(mask)] = v;
+    }
+  }
+}
+
 __global__ void route_kernel(int32_t n, const uint8_t* __restrict__ owner,
                              const int32_t* __restrict__ conv, uint32_t* __restrict__ route) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -329,6 +364,23 @@ extern "C" fg_status fg_package(const fg_share* s, const int32_t* frontier, int3
                                              s->nparts, depth, parent, tile_cnt, out->capacity,
                                              out->ids, out->depth, parent ? out->parent : nullptr,
                                              out->local);
+  FG_HIP_TRY(hipGetLastError());
+  return FG_OK;
+}
+
+extern "C" fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int32_t* labels,
+                                const int32_t* parents, int32_t len, uint32_t* visited,
+                                int32_t* depth, int32_t* parent, int32_t* out_q,
+                                int32_t* out_len, void* stream) {
+  if (!g || !visited || !depth || !out_q || !out_len)
+    return fg_set_error(FG_EINVAL, "fg_combine: NULL argument");
+  if (len < 0) return fg_set_error(FG_EINVAL, "fg_combine: negative len");
+  if (len > 0 && (!ids || !labels)) return fg_set_error(FG_EINVAL, "fg_combine: NULL input");
+  if (len == 0) return FG_OK;
+  int blocks = (len + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  combine_kernel<<<blocks, 256, 0, (hipStream_t)stream>>>(ids, labels, parents, len, visited,
+                                                          depth, parent, out_q, out_len);
   FG_HIP_TRY(hipGetLastError());
   return FG_OK;
 }

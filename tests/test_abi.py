@@ -50,3 +50,35 @@ def test_argument_errors_without_gpu(fg):
     assert L.fg_stats_read(None, None, None) == fg.FG_EINVAL
     assert L.fg_graph_destroy(None) == fg.FG_OK
     assert fg.lib().fg_version().decode().count(".") == 2
+
+
+def test_new_entry_points_argument_errors(fg):
+    import numpy as np
+    L = fg.lib()
+    h = ctypes.c_void_p()
+    off = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    own = np.array([0, 1], np.uint8)
+    P = lambda a: a.ctypes.data
+    # share: bad n, bad nparts / part, owner out of range (all before any HIP call)
+    assert L.fg_share_create(0, 0, P(off), P(col), P(own), 2, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_share_create(2, 2, P(off), P(col), P(own), 0, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_share_create(2, 2, P(off), P(col), P(own), 2, 2, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_share_create(2, 2, P(off), P(col), P(own), 17, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
+    bad_own = np.array([0, 3], np.uint8)
+    assert L.fg_share_create(2, 2, P(off), P(col), P(bad_own), 2, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert "owner" in fg.last_error()
+    bad_off = np.array([0, 1, 3], np.int32)
+    assert L.fg_share_create(2, 2, P(bad_off), P(col), P(own), 2, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_share_destroy(None) == fg.FG_OK
+    assert L.fg_package(None, None, 0, None, None, None, None, 0, None) == fg.FG_EINVAL
+    assert L.fg_package_workspace_bytes(None, 10) == 0
+    # sssp / batched BFS
+    assert L.fg_sssp(None, 0, None, None, 0, None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_msbfs_open(None, 64, None, 0, None, None, ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_msbfs_admit(None, 0, 0) == fg.FG_EINVAL
+    assert L.fg_msbfs_step(None, 1, None) == fg.FG_EINVAL
+    assert L.fg_msbfs_read(None, 0, None, None) == fg.FG_EINVAL
+    assert L.fg_msbfs_close(None) == fg.FG_OK
+    assert L.fg_graph_csr(None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_share_graph(None) is None
