@@ -33,7 +33,17 @@ constexpr int PWAVES = PB / FG_WAVE;
 constexpr int CH = 256;           // edges per descriptor
 constexpr int DIR_PUSH = 0, DIR_PULL = 1;
 
-constexpr int32_t DEF_SMALL_Q = 1024;
+constexpr int QCAP = 2048;    // LDS frontier entries per workgroup in LDS-queue mode
+constexpr int TEAM_MAX = 64;  // widest team (one record per lane of a wave)
+// Fields of a team level word: arrivals, flagged members, vertices
+// discovered, degree sum (each member's degree sum capped at TW_CAP, so 64
+// members cannot carry out of the field; team_e < TW_CAP keeps every
+// team-mode decision exact).
+constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
+constexpr int64_t TW_CAP = (1 << 19) - 1;
+constexpr int TPV = 4;        // LDS-queue levels: vertices of degree <= TPV are
+                              // expanded by TPV lanes each, without a scan
+constexpr int32_t DEF_SMALL_Q = QCAP;
 constexpr int64_t DEF_SMALL_E = 4096;
 constexpr int32_t DEF_BIG_DEG = 64;
 constexpr int32_t DEF_TEAM = 16;
@@ -64,6 +74,15 @@ struct alignas(256) BfsCtl {
   uint32_t pad3[63];
   uint32_t team_arrive;        // barrier of the team (workgroups 0..team-1)
   uint32_t pad4[63];
+  // LDS-queue mode: per level parity and member, the level's totals of the
+  // member (vertices discovered, their degree sum), each word tagged with
+  // the level number + 1 in its upper 32 bits
+  ull team_rec[2][TEAM_MAX][2];
+  // LDS-queue mode: per team level mod 3, the word every member adds its
+  // arrival and totals to (fields TW_*)
+  Line64 team_word[3];
+  Line64 team_ovf;             // entries written to the global queue by the team
+  Line64 solo_ovf;             // ... by workgroup 0 alone
   Line64 aux;                  // entries written by bitmap -> queue conversion
   CtrSlot slot[2];
   // state published by workgroup 0 when a small-frontier / team episode ends
@@ -203,6 +222,14 @@ constexpr int STAGE = 512;   // per-wave LDS staging of discovered vertices
 constexpr int DSTAGE = 128;  // per-wave LDS staging of descriptors
 
 struct Lds {
+  // LDS-queue mode: frontier share of this workgroup as (vertex, first edge,
+  // end edge), double buffered
+  int32_t lq_v[2][QCAP];
+  int32_t lq_b[2][QCAP];
+  int32_t lq_e[2][QCAP];
+  int32_t lq_cnt[3];   // per level mod 3: entries appended
+  int32_t lq_deg[3];   // ... their degree sum
+  int32_t lq_big[3];   // ... an input vertex of degree > TPV was seen
   int32_t stage[PWAVES][STAGE];
   int2 dstage[PWAVES][DSTAGE];
   // per-wave scan-gather staging (push, full grid)
@@ -218,6 +245,7 @@ struct Lds {
   int32_t newcnt;
   int32_t flag;
   int64_t bcast[20];
+  int32_t tsum[6];
 };
 
 // ---- push, full grid, phase A: each wave takes 64-entry chunks of the
@@ -431,73 +459,20 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S) {
   }
 }
 
-// ---- small-frontier mode, workgroup 0 only: push levels run back to back
-// with workgroup barriers while |Q| <= small_q and the frontier's degree sum
-// <= small_e.  Returns with S describing the next iteration.
-template <int MODE>
-__device__ void small_mode(const BfsParams& P, St& S, Lds& L) {
-  const int tid = threadIdx.x;
-  for (;;) {
-    const int32_t* Qin = P.q[S.qsel];
-    int32_t* Qout = P.q[S.qsel ^ 1];
-    uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
-    if (tid == 0) L.newcnt = 0;
-    const int32_t d_new = S.k + 1;
-    int64_t ndeg = 0;
-    for (int64_t c0 = 0; c0 < S.qlen; c0 += PB) {
-      const int64_t i = c0 + tid;
-      int32_t u = 0, b = 0, d = 0;
-      if (i < S.qlen) {
-        u = Qin[i];
-        b = P.off[u];
-        d = P.off[u + 1] - b;
-      }
-      int32_t T = 0;
-      const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &T);
-      L.b_sc[tid] = ex;
-      L.b_u[tid] = u;
-      L.b_b[tid] = b;
-      __syncthreads();
-      const int32_t cnt = (int32_t)((S.qlen - c0) < PB ? (S.qlen - c0) : PB);
-      for (int32_t t0 = 0; t0 < T; t0 += PB) {
-        const int32_t t = t0 + tid;
-        bool won = false;
-        int32_t v = 0;
-        if (t < T) {
-          const int32_t j = upper_idx(L.b_sc, cnt, t);
-          v = P.col[L.b_b[j] + (t - L.b_sc[j])];
-          won = try_visit(v, L.b_u[j], d_new, vis32, P);
-          if (won) ndeg += P.off[v + 1] - P.off[v];
-        }
-        const uint64_t mask = __ballot(won);
-        if (mask) {
-          int32_t pos = 0;
-          if (fg_lane() == 0) pos = atomicAdd(&L.newcnt, __popcll(mask));
-          pos = __shfl(pos, 0, FG_WAVE);
-          if (won) Qout[pos + fg_mbcnt(mask)] = v;
-        }
-      }
-      __syncthreads();
-    }
-    const int64_t nqdeg = fg_uni(fg_block_sum<PB>(ndeg, L.red));
-    const int64_t nq = fg_uni((int64_t)L.newcnt);
-    trace_insp(S.k, S.qdeg, P);
-    S.insp_sum += S.qdeg;
-    S.k++;
-    S.qsel ^= 1;
-    S.qlen = nq;
-    S.qdeg = nqdeg;
-    S.p += nq;
-    decide<MODE>(S, P);
-    trace_iter(S, P);
-    __syncthreads();
-    if (nq == 0 || S.dir != DIR_PUSH || nq > P.small_q || nqdeg > P.small_e) return;
-  }
-}
-
-// ---- team mode: workgroups 0..team-1 run push levels back to back with a
-// barrier among themselves while the frontier's degree sum is at most
-// team_e (and above the small-frontier limits); the other workgroups wait.
+// ---- LDS-queue mode: a team of T workgroups (T = 1 for the smallest
+// frontiers) runs push levels back to back.  Each member keeps its share of
+// the frontier in LDS as (vertex, first edge, end edge) and appends each
+// vertex it discovers, with the offsets loaded alongside the visited
+// test-and-set, to its next LDS queue: no global queue, no global output
+// counter and no offset reloads.  A vertex of degree <= TPV is expanded by
+// TPV adjacent lanes, one edge each (no scan, no search); larger vertices
+// go through a block scan-gather.  Per level the dependent
+// memory chain is column load -> (visited atomic | winner's offsets), then
+// one workgroup barrier, plus the exchange of the members' totals when
+// T > 1.  A member whose LDS queue is full appends the overflow to the
+// global queue, which ends the episode.  On exit the members write their
+// LDS queues to the global queue, so the other modes continue from
+// Q[qsel] as usual.
 struct TeamSync {
   uint32_t* arrive;
   uint32_t* abort_flag;
@@ -516,42 +491,332 @@ struct TeamSync {
   }
 };
 
-template <int MODE>
-__device__ bool team_mode(const BfsParams& P, St& S, Lds& L, TeamSync& ts) {
-  for (;;) {
-    CtrSlot& C = P.ctl->slot[S.k & 1];
-    Bases B = get_bases(S);
-    push_phase_a(P, S, L, ts.T);
-    if (!ts.sync(&L.flag)) return false;
-    const ull dt = fg_atomic_load_u64(&C.desc.v);
-    const int64_t ndesc = (int64_t)(dt - B.desc);
-    if (ndesc > 0) {
-      push_phase_b(P, S, ndesc, L, ts.T);
-      if (!ts.sync(&L.flag)) return false;
+// Bases of the global-queue counters, held by the members (identical in
+// all of them).
+struct TeamBases {
+  ull ovf, solo_ovf;
+  uint32_t levels;  // team level exchanges so far
+};
+
+// Level totals of a team, fast path: every member adds one word to the
+// level's team word (arrival, flag, count, capped degree sum) and thread 0
+// polls that word until all T members are in: one atomic and one polled
+// address per level.  All are agent-scope atomics, so no cache write-back
+// or invalidation is needed: within an episode the members share nothing
+// but the visited bitmap, which is only touched by atomics.  The words
+// rotate over three slots; workgroup 0 clears the slot of the next level
+// (its last readers are done: they have all arrived at this level) and
+// makes its own arrival wait for the clear, which every later arrival at
+// that slot follows.  A member flags itself when its count exceeds `lim`.
+// L.tsum: [0] discovered, [1] degree sum, [2] flagged members.
+__device__ bool team_fast(const BfsParams& P, Lds& L, uint32_t T, uint32_t level, int32_t bcnt,
+                          int32_t bdeg, int32_t lim) {
+  if (threadIdx.x == 0) {
+    ull* w = &P.ctl->team_word[level % 3].v;
+    ull cleared = 0;
+    if (blockIdx.x == 0)
+      cleared = __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull,
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const ull g = bdeg < TW_CAP ? (ull)bdeg : (ull)TW_CAP;
+    const ull add = (1ull << TW_ARR) | ((ull)(bcnt > lim) << TW_FLAG) | ((ull)bcnt << TW_CNT) | g;
+    // the exchange's old value is consumed before the arrival is issued
+    asm volatile("" ::"v"(cleared) : "memory");
+    __hip_atomic_fetch_add(w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    uint32_t spins = 0;
+    int bad = 0;
+    ull x;
+    for (;;) {
+      x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((x >> TW_ARR) >= T) break;
+      if ((++spins & 31u) == 0 &&
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+      if (spins > FG_SPIN_LIMIT) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
-    B.desc = dt;
-    const ull qt = fg_atomic_load_u64(&C.q.v);
-    const ull it = fg_atomic_load_u64(&C.insp.v);
-    const ull gt = fg_atomic_load_u64(&C.deg.v);
-    const int64_t nq = (int64_t)(qt - B.q);
-    const int64_t insp = (int64_t)(it - B.insp);
-    const int64_t nqdeg = (int64_t)(gt - B.deg);
-    B.q = qt;
-    B.insp = it;
-    B.deg = gt;
-    set_bases(S, B);
-    trace_insp(S.k, insp, P);
-    S.insp_sum += insp;
+    L.tsum[0] = (int32_t)((x >> TW_CNT) & ((1ull << (TW_FLAG - TW_CNT)) - 1));
+    L.tsum[1] = (int32_t)(x & ((1ull << TW_CNT) - 1));
+    L.tsum[2] = (int32_t)((x >> TW_FLAG) & ((1ull << (TW_ARR - TW_FLAG)) - 1));
+    L.flag = bad;
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+// Slow path, taken when the episode ends or a member flagged itself: wave 0
+// reads every member's record (vertices discovered, exact degree sum; each
+// word tagged with the level, re-read until current, since a record and
+// the arrival are not ordered).  L.tsum: [2] members that overflowed their
+// LDS queue, [3] overflow entries in all, [4] entries kept in LDS by the
+// members before this one, [5] largest member count.
+__device__ bool team_records(const BfsParams& P, Lds& L, uint32_t T, uint32_t seq, int odd) {
+  const int tid = threadIdx.x;
+  if (tid < FG_WAVE) {
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    int32_t c = 0, bad = 0;
+    if ((uint32_t)tid < T) {
+      const ull* r = P.ctl->team_rec[odd][tid];
+      uint32_t spins = 0;
+      for (;;) {
+        const ull a = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(a >> 32) == seq) {
+          c = (int32_t)(uint32_t)a;
+          break;
+        }
+        if (++spins > FG_SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const int32_t keep = c < QCAP ? c : QCAP;
+    const int32_t keep_incl = fg_wave_incl_scan(keep);
+    const int32_t before = __builtin_amdgcn_readlane(keep_incl - keep, blockIdx.x);
+    const int32_t tof = fg_wave_sum(c > QCAP ? 1 : 0);
+    const int32_t tov = fg_wave_sum(c - keep);
+    int32_t mx = c;
+#pragma unroll
+    for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+      const int32_t y = __shfl_xor(mx, d, FG_WAVE);
+      mx = y > mx ? y : mx;
+    }
+    bad = fg_wave_sum(bad);
+    if (tid == 0) {
+      L.tsum[2] = tof;
+      L.tsum[3] = tov;
+      L.tsum[4] = before;
+      L.tsum[5] = mx;
+      L.flag = bad;
+    }
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+// Reserves `w` consecutive slots per lane behind `*counter` (LDS) for the
+// whole wave with one atomic; returns this lane's first slot.  Every lane of
+// the wave must take part.
+__device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
+  const int32_t incl = fg_wave_incl_scan(w);
+  const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+  int32_t base = 0;
+  if (tot) {
+    if (fg_lane() == 0) base = atomicAdd(counter, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+  }
+  return base + incl - w;
+}
+
+__device__ __forceinline__ void lq_put(Lds& L, int nxt, int32_t pos, int32_t v, int32_t vb,
+                                       int32_t ve, int32_t* Qo, ull* ovf, ull ovf_base) {
+  if (pos < QCAP) {
+    L.lq_v[nxt][pos] = v;
+    L.lq_b[nxt][pos] = vb;
+    L.lq_e[nxt][pos] = ve;
+  } else {
+    Qo[atomicAdd(ovf, 1ull) - ovf_base] = v;  // overflow: global queue
+  }
+}
+
+template <int MODE>
+__device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync& ts,
+                         TeamBases& tb) {
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  const bool solo = T == 1;
+  ull* ovf = solo ? &P.ctl->solo_ovf.v : &P.ctl->team_ovf.v;
+  ull ovf_base = solo ? tb.solo_ovf : tb.ovf;
+  // LDS counters rotate over three slots: the level's input, its output,
+  // and the one cleared for the next level (its last reader finished a
+  // barrier ago, its next writer starts a barrier later)
+  int cur = 0, ci = 0, ni = 1, ri = 2;
+  bool load = true;
+  for (;;) {
+    const int32_t* Qg = P.q[S.qsel];
+    int32_t* Qo = P.q[S.qsel ^ 1];
+    if (load) {
+      // my even slice of the global frontier -> LDS queue `cur`
+      load = false;
+      const int64_t lo = S.qlen * blockIdx.x / T, hi = S.qlen * (blockIdx.x + 1) / T;
+      const int32_t cnt = (int32_t)(hi - lo);
+      for (int32_t i = tid; i < cnt; i += PB) {
+        const int32_t u = Qg[lo + i];
+        L.lq_v[cur][i] = u;
+        L.lq_b[cur][i] = P.off[u];
+        L.lq_e[cur][i] = P.off[u + 1];
+      }
+      if (tid == 0) {
+        L.lq_cnt[ci] = cnt;
+        L.lq_cnt[ni] = 0;
+        L.lq_deg[ni] = 0;
+        L.lq_big[ni] = 0;
+      }
+      __syncthreads();
+    }
+    const int nxt = cur ^ 1;
+    const int32_t cnt = L.lq_cnt[ci];
+    if (tid == 0) {
+      L.lq_cnt[ri] = 0;
+      L.lq_deg[ri] = 0;
+      L.lq_big[ri] = 0;
+    }
+    uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
+    const int32_t d_new = S.k + 1;
+    bool big = false;
+    // vertices of degree <= TPV: TPV consecutive lanes per vertex, one edge
+    // each (the column loads of a vertex coalesce; one dependent chain)
+    for (int32_t c0 = 0; c0 < cnt; c0 += PB / TPV) {
+      const int32_t i = c0 + tid / TPV;
+      const int32_t j = tid % TPV;
+      int32_t u = 0, b = 0, d = 0;
+      if (i < cnt) {
+        u = L.lq_v[cur][i];
+        b = L.lq_b[cur][i];
+        d = L.lq_e[cur][i] - b;
+      }
+      big |= d > TPV;
+      bool won = false;
+      int32_t v = 0, vb = 0, ve = 0;
+      if (d <= TPV && j < d) {
+        v = P.col[b + j];
+        vb = P.off[v];
+        ve = P.off[v + 1];
+        const uint32_t bit = 1u << (v & 31);
+        won = !(atomicOr(&vis32[v >> 5], bit) & bit);
+        if (won) {
+          P.depth[v] = d_new;
+          if (P.parent) P.parent[v] = u;
+        }
+      }
+      const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+      const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+      if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+      if (won) lq_put(L, nxt, pos, v, vb, ve, Qo, ovf, ovf_base);
+    }
+    if (big) L.lq_big[ni] = 1;
+    __syncthreads();
+    if (L.lq_big[ni]) {
+      // vertices of degree > TPV: block scan-gather over their edges
+      for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
+        const int32_t i = c0 + tid;
+        int32_t u = 0, b = 0, d = 0;
+        if (i < cnt) {
+          u = L.lq_v[cur][i];
+          b = L.lq_b[cur][i];
+          d = L.lq_e[cur][i] - b;
+        }
+        if (d <= TPV) d = 0;
+        int32_t Tn = 0;
+        const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &Tn);
+        L.b_sc[tid] = ex;
+        L.b_u[tid] = u;
+        L.b_b[tid] = b;
+        __syncthreads();
+        const int32_t nc = cnt - c0 < PB ? cnt - c0 : PB;
+        for (int32_t t0 = 0; t0 < Tn; t0 += PB) {
+          const int32_t t = t0 + tid;
+          bool won = false;
+          int32_t v = 0, vb = 0, ve = 0, pu = 0;
+          if (t < Tn) {
+            const int32_t j = upper_idx(L.b_sc, nc, t);
+            pu = L.b_u[j];
+            v = P.col[L.b_b[j] + (t - L.b_sc[j])];
+            const uint32_t bit = 1u << (v & 31);
+            vb = P.off[v];
+            ve = P.off[v + 1];
+            if (!(atomicOr(&vis32[v >> 5], bit) & bit)) {
+              won = true;
+              P.depth[v] = d_new;
+              if (P.parent) P.parent[v] = pu;
+            }
+          }
+          const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+          const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+          if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+          if (won) lq_put(L, nxt, pos, v, vb, ve, Qo, ovf, ovf_base);
+        }
+        __syncthreads();
+      }
+    }
+    const int32_t bcnt = L.lq_cnt[ni];
+    const int32_t bdeg = L.lq_deg[ni];
+    int64_t nq, nqdeg, nflag;
+    if (solo) {
+      nq = bcnt;
+      nqdeg = bdeg;
+      nflag = bcnt > QCAP;
+    } else {
+      if (tid == 0) {
+        // the record behind the word, read only on the slow path
+        ull* r = P.ctl->team_rec[S.k & 1][blockIdx.x];
+        const ull tag = (ull)((uint32_t)S.k + 1u) << 32;
+        __hip_atomic_store(r, tag | (uint32_t)bcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const int64_t lim = 2 * S.qlen / T + 64;
+      if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP)))
+        return false;
+      tb.levels++;
+      nq = fg_uni(L.tsum[0]);
+      nqdeg = fg_uni(L.tsum[1]);
+      nflag = fg_uni(L.tsum[2]);
+    }
+    // a push level reads every CSR entry of its frontier: the degree sum
+    trace_insp(S.k, S.qdeg, P);
+    S.insp_sum += S.qdeg;
     S.k++;
-    S.qsel ^= 1;
     S.qlen = nq;
     S.qdeg = nqdeg;
     S.p += nq;
     decide<MODE>(S, P);
     trace_iter(S, P);
-    if (nq == 0 || S.dir != DIR_PUSH || nqdeg > P.team_e ||
-        (nq <= P.small_q && nqdeg <= P.small_e))
-      return true;
+    bool stay = nq > 0 && S.dir == DIR_PUSH &&
+                (solo ? (nq <= P.small_q && nqdeg <= P.small_e)
+                      : (nqdeg <= P.team_e && !(nq <= P.small_q && nqdeg <= P.small_e)));
+    int64_t nover = bcnt > QCAP ? bcnt - QCAP : 0, before = 0;
+    bool rebalance = false;
+    if (solo) {
+      stay = stay && nflag == 0;
+    } else if (!stay || nflag) {
+      if (!team_records(P, L, T, (uint32_t)S.k, (S.k - 1) & 1)) return false;
+      nover = fg_uni(L.tsum[3]);
+      before = fg_uni(L.tsum[4]);
+      stay = stay && fg_uni(L.tsum[2]) == 0;
+      // the frontier grows at its ends: even out the members' shares when
+      // the largest is well above the mean
+      rebalance = stay && fg_uni(L.tsum[5]) * (int64_t)T > 2 * nq + 64 * (int64_t)T;
+    }
+    if (!stay || rebalance) {
+      // global queue: the overflow entries, then every member's LDS queue
+      // in member order
+      const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
+      int32_t* dst = Qo + nover + before;
+      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      ovf_base += (ull)nover;
+      if (solo) {
+        tb.solo_ovf = ovf_base;
+        __syncthreads();
+      } else {
+        tb.ovf = ovf_base;
+        if (!ts.sync(&L.flag)) return false;
+      }
+      S.qsel ^= 1;
+      if (!stay) return true;
+      load = true;
+    }
+    cur = nxt;
+    const int t3 = ci;
+    ci = ni;
+    ni = ri;
+    ri = t3;
   }
 }
 
@@ -568,6 +833,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   uint32_t sm_seen = 0;
   bool ok = true;
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
+  TeamBases tb = {};
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
   {
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
@@ -623,16 +889,13 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       S.prevdir = DIR_PUSH;
     }
     const bool small_ep = S.dir == DIR_PUSH && S.qlen <= P.small_q && S.qdeg <= P.small_e;
-    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qdeg <= P.team_e;
+    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qdeg <= P.team_e &&
+                         S.qlen <= (int64_t)QCAP * P.team / 2;
     if (small_ep || team_ep) {
       sm_seen++;
       const bool member = small_ep ? blockIdx.x == 0 : blockIdx.x < (uint32_t)P.team;
       if (member) {
-        if (small_ep) {
-          small_mode<MODE>(P, S, L);
-        } else if (!team_mode<MODE>(P, S, L, ts)) {
-          ok = false;
-        }
+        if (!lds_mode<MODE>(P, S, L, small_ep ? 1u : (uint32_t)P.team, ts, tb)) ok = false;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           BfsCtl* c = P.ctl;
           c->pub_k = S.k;
@@ -659,7 +922,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         if (!ok) break;
       } else {
         if (threadIdx.x == 0) {
-          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 64);
+          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
           L.flag = bad;
           if (!bad) {
             const BfsCtl* c = P.ctl;
@@ -923,10 +1186,17 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   P.b_num = o.do_b_num;
   P.b_den = o.do_b_den;
   P.small_q = o.small_frontier > 0 ? o.small_frontier : DEF_SMALL_Q;
-  if (P.small_q > PB) P.small_q = PB;
+  if (P.small_q > QCAP) P.small_q = QCAP;
   P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
   P.clock_khz = pr.clock_khz;
+  P.team = o.team_blocks > 0 ? o.team_blocks : (o.team_blocks < 0 ? 0 : DEF_TEAM);
+  if (P.team > grid) P.team = grid;
+  if (P.team > TEAM_MAX) P.team = TEAM_MAX;
+  P.team_e = o.team_edges > 0 ? o.team_edges : DEF_TEAM_E;
+  // team decisions are exact below the word's degree cap
+  if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
+  if (P.small_e > TW_CAP - 1) P.small_e = TW_CAP - 1;
 
   void* args[] = {&P};
   const void* fn = o.mode == FG_MODE_DO ? (const void*)bfs_persistent<FG_MODE_DO>

@@ -94,11 +94,29 @@ __device__ __forceinline__ T fg_wave_incl_scan(T x) {
   return x;
 }
 
+// 32-bit version through DPP row shifts and row broadcasts: six VALU
+// operations and no LDS traffic (the generic one above waits on six
+// dependent cross-lane permutes).  All 64 lanes must be active.
+__device__ __forceinline__ int32_t fg_wave_incl_scan(int32_t x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
 template <class T>
 __device__ __forceinline__ T fg_wave_sum(T x) {
 #pragma unroll
   for (int d = FG_WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, FG_WAVE);
   return x;
+}
+
+// Wave total of 32-bit values (DPP scan, then the last lane's value).
+__device__ __forceinline__ int32_t fg_wave_sum(int32_t x) {
+  return __builtin_amdgcn_readlane(fg_wave_incl_scan(x), FG_WAVE - 1);
 }
 
 // Wave-uniform copies (scalar registers) of values every lane holds equally.
@@ -126,6 +144,9 @@ __device__ __forceinline__ unsigned long long fg_atomic_load_u64(const unsigned 
 // (int32)(*p - target) >= 0, then one agent-scope acquire fence.  Gives up
 // when `abort_flag` is set or after FG_SPIN_LIMIT polls (then sets it), so
 // every workgroup leaves the kernel even if a peer never arrives.
+// `sleep_cycles` sets the pause between polls: >= 4096 (about 4K clocks)
+// for waits expected to be long, which keeps idle workgroups from
+// hammering the counter's memory channel.
 #define FG_SPIN_LIMIT (1u << 24)
 
 __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
@@ -141,7 +162,8 @@ __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
       __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
-    if (sleep_cycles > 8) __builtin_amdgcn_s_sleep(8);
+    if (sleep_cycles >= 4096) __builtin_amdgcn_s_sleep(64);
+    else if (sleep_cycles > 8) __builtin_amdgcn_s_sleep(8);
     else __builtin_amdgcn_s_sleep(1);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

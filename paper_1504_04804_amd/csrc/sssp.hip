@@ -396,7 +396,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
         __syncthreads();
       } else {
         if (threadIdx.x == 0) {
-          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 64);
+          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
           L.flag = bad;
           if (!bad) {
             const SsspCtl* c = P.ctl;

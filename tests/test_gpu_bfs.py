@@ -120,6 +120,32 @@ def test_grid_high_diameter(fg, orc):
     for s in (0, 128 * 256 + 128):
         check_bfs(fg, orc, g, off, col, s, "push")
     check_bfs(fg, orc, g, off, col, 0, "push", small_frontier=1, small_edges=1)
+    # team levels whose shares drift apart (the frontier grows at its ends)
+    check_bfs(fg, orc, g, off, col, 0, "push", small_edges=1, team_blocks=8)
+    check_bfs(fg, orc, g, off, col, 128 * 256 + 128, "push", small_edges=1, team_blocks=64)
+
+
+def test_lds_queue_modes(fg, orc, rmat12):
+    """Levels run by one workgroup or a team from LDS queues: team widths
+    from 2 to the whole grid, and a hub whose 3000 neighbours exceed one
+    workgroup's LDS queue, so the overflow goes to the global queue."""
+    n = 6001
+    edges = [(0, i) for i in range(1, 3001)] + [(i, i + 3000) for i in range(1, 3001)]
+    off, col = synth.from_edge_pairs(n, edges)
+    g = fg.Graph(off, col)
+    for mode in ("do", "push"):
+        check_bfs(fg, orc, g, off, col, 0, mode)
+        check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=2)
+        check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=7, team_edges=1 << 20)
+        check_bfs(fg, orc, g, off, col, 4000, mode, small_frontier=1, team_blocks=3)
+    off, col, g = rmat12
+    for team in (-1, 2, 5, 64, 10**6):
+        for s in (0, 5):
+            check_bfs(fg, orc, g, off, col, s, "push", team_blocks=team)
+            check_bfs(fg, orc, g, off, col, s, "push", team_blocks=team, small_edges=1,
+                      team_edges=1 << 30)
+            check_bfs(fg, orc, g, off, col, s, "do", team_blocks=team, small_edges=1,
+                      team_edges=1 << 30)
 
 
 def test_repeat_determinism(fg, orc, rmat12):
