@@ -41,6 +41,8 @@ constexpr int TEAM_MAX = 64;  // widest team (one record per lane of a wave)
 // team-mode decision exact).
 constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
 constexpr int64_t TW_CAP = (1 << 19) - 1;
+constexpr int LDS_MEAN_DEG = 64;  // LDS-queue levels need a frontier of mean degree
+                                  // <= this (hubs are cut up by the whole grid)
 constexpr int TPV = 4;        // LDS-queue levels: vertices of degree <= TPV are
                               // expanded by TPV lanes each, without a scan
 constexpr int32_t DEF_SMALL_Q = QCAP;
@@ -97,6 +99,7 @@ struct BfsParams {
   const int32_t* __restrict__ off;
   const int32_t* __restrict__ col;
   const uint64_t* __restrict__ nz;
+  const int4* __restrict__ head;  // first four neighbours per vertex
   int32_t n;
   int32_t nwords;
   int64_t m;
@@ -218,6 +221,34 @@ __device__ __forceinline__ bool try_visit(int32_t v, int32_t src, int32_t d,
   return true;
 }
 
+// Filter step for up to four edges per lane, all in flight together: plain
+// visited pre-check of the four targets, then the test-and-sets of the
+// candidates, then depth / parent of the winners.  v[r] must be a vertex id
+// even where ok[r] is false.
+__device__ __forceinline__ void visit4(const BfsParams& P, uint32_t* vis32, int32_t d,
+                                       const int32_t (&v)[4], const int32_t (&pu)[4],
+                                       const bool (&ok)[4], bool (&won)[4]) {
+  uint32_t w[4], old[4];
+  bool cand[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w[r] = vis32[v[r] >> 5];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cand[r] = ok[r] && !((w[r] >> (v[r] & 31)) & 1u);
+  // old is only set and read where cand[r]: no merge with a default value,
+  // so the compiler need not wait inside each branch
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (cand[r]) old[r] = atomicOr(vis32 + (v[r] >> 5), 1u << (v[r] & 31));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    won[r] = cand[r] && !((old[r] >> (v[r] & 31)) & 1u);
+    if (won[r]) {
+      P.depth[v[r]] = d;
+      if (P.parent) P.parent[v[r]] = pu[r];
+    }
+  }
+}
+
 constexpr int STAGE = 512;   // per-wave LDS staging of discovered vertices
 constexpr int DSTAGE = 128;  // per-wave LDS staging of descriptors
 
@@ -236,6 +267,10 @@ struct Lds {
   int32_t w_sc[PWAVES][FG_WAVE];
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
+  // per-wave pull batch: unvisited vertices of nonzero degree per bitmap
+  // word, and the vertices found per word
+  uint64_t pw_act[PWAVES][FG_WAVE];
+  uint64_t pw_nb[PWAVES][FG_WAVE];
   // block-level staging (small-frontier mode)
   int32_t b_sc[PB];
   int32_t b_u[PB];
@@ -267,7 +302,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
   WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)nblocks * PWAVES;
-  int64_t insp = 0, ndeg = 0;
+  int64_t insp = 0;
   for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
     int32_t u = 0, b = 0, deg = 0;
@@ -308,27 +343,28 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
     su[lane] = u;
     sb[lane] = b;
     wave_lds_fence();
-    for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
-      const int32_t t = t0 + lane;
-      bool won = false;
-      int32_t v = 0;
-      if (t < T) {
-        const int32_t j = upper_idx(sc, FG_WAVE, t);
-        v = P.col[sb[j] + (t - sc[j])];
-        won = try_visit(v, su[j], d_new, vis32, P);
-        if (won) ndeg += P.off[v + 1] - P.off[v];
+    // four rounds of 64 edges per step, their loads and atomics overlapped
+    for (int32_t t0 = 0; t0 < T; t0 += 4 * FG_WAVE) {
+      int32_t v[4], pu[4];
+      bool ok[4], won[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int32_t t = t0 + r * FG_WAVE + lane;
+        ok[r] = t < T;
+        const int32_t j = upper_idx(sc, FG_WAVE, ok[r] ? t : T - 1);
+        pu[r] = su[j];
+        v[r] = P.col[sb[j] + ((ok[r] ? t : T - 1) - sc[j])];
       }
-      st.push(won, v, &C.q.v, B.q, Qout);
+      visit4(P, vis32, d_new, v, pu, ok, won);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
   dst.flush(&C.desc.v, B.desc, P.desc);
-  const int64_t tot = fg_block_sum<PB>(insp, L.red);
-  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
-  if (threadIdx.x == 0) {
-    if (tot) atomicAdd(&C.insp.v, (ull)tot);
-    if (tdeg) atomicAdd(&C.deg.v, (ull)tdeg);
-  }
+  // per workgroup and level the sum is at most m < 2^31
+  const int32_t tot = fg_block_sum<PB>((int32_t)insp, L.red32);
+  if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
 }
 
 // ---- push, full grid, phase B: waves take descriptors in turn; the CH
@@ -340,7 +376,6 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)nblocks * PWAVES;
-  int64_t ndeg = 0;
   int32_t* Qout = P.q[S.qsel ^ 1];
   uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
   const int32_t d_new = S.k + 1;
@@ -352,32 +387,80 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
     const int32_t u = dsc.x;
     const int32_t e_end = P.off[u + 1];
     const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
-    // CH / 64 rounds, loads first so the rounds' reads overlap
-    int32_t vv[CH / FG_WAVE];
+    // the CH / 64 = 4 rounds of a descriptor with their loads and atomics
+    // overlapped (indices past the chunk clamped to its last edge)
+    static_assert(CH == 4 * FG_WAVE, "one visit4 per descriptor");
+    int32_t v[4], pu[4];
+    bool ok[4], won[4];
 #pragma unroll
-    for (int r = 0; r < CH / FG_WAVE; ++r) {
+    for (int r = 0; r < 4; ++r) {
       const int32_t e = dsc.y + r * FG_WAVE + lane;
-      vv[r] = e < e1 ? P.col[e] : -1;
+      ok[r] = e < e1;
+      v[r] = P.col[ok[r] ? e : e1 - 1];
+      pu[r] = u;
     }
+    visit4(P, vis32, d_new, v, pu, ok, won);
 #pragma unroll
-    for (int r = 0; r < CH / FG_WAVE; ++r) {
-      const int32_t v = vv[r];
-      const bool won = v >= 0 && try_visit(v, u, d_new, vis32, P);
-      if (won) ndeg += P.off[v + 1] - P.off[v];
-      st.push(won, v, &C.q.v, B.q, Qout);
-    }
+    for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
   }
   st.flush(&C.q.v, B.q, Qout);
-  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
-  if (threadIdx.x == 0 && tdeg) atomicAdd(&C.deg.v, (ull)tdeg);
 }
 
-// ---- pull, full grid: each wave owns 64 consecutive vertices (one bitmap
-// word).  An unvisited vertex of nonzero degree scans its CSR row in order
-// and stops at the first visited neighbour: for an unvisited v every
-// visited neighbour has depth exactly k (depths differ by at most one across
-// an edge), so that neighbour is in the current frontier.  The next bitmap
-// word is written whole, so no atomics are needed.
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Position of the r-th set bit (r = 0 first) of x; x has more than r bits set.
+__device__ __forceinline__ int nth_bit(uint64_t x, int r) {
+  int pos = 0;
+#pragma unroll
+  for (int h = 32; h > 0; h >>= 1) {
+    const int c = __popcll(x & ((1ull << h) - 1));
+    if (r >= c) {
+      r -= c;
+      x >>= h;
+      pos += h;
+    }
+  }
+  return pos;
+}
+
+// Early-exit probe of up to four consecutive CSR entries [i0, min(i0+4, e))
+// (needs i0 < e): all column loads, then all visited-word loads, in flight
+// together.  The loads are unconditional (indices clamped to the last
+// entry) so that no per-entry branch makes the compiler wait between them.
+// Returns the offset of the first entry whose vertex is visited, or -1.
+__device__ __forceinline__ int32_t probe4(const BfsParams& P, const uint64_t* Vin, int32_t i0,
+                                          int32_t e, int32_t& pu) {
+  int32_t u[4];
+  uint64_t wv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) u[j] = P.col[i0 + j < e ? i0 + j : e - 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) wv[j] = Vin[u[j] >> 6];
+  int32_t hit = -1;
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    if (i0 + j < e && ((wv[j] >> (u[j] & 63)) & 1ull)) {
+      hit = j;
+      pu = u[j];
+    }
+  }
+  return hit;
+}
+
+// ---- pull (backward) iteration, vertex-parallel with early exit
+// (Sec. VI-A): an unvisited vertex scans its neighbours in CSR order and
+// stops at the first one in the frontier.  For an unvisited v, a visited
+// neighbour has depth exactly k, so the visited bitmap is the frontier
+// test.  Each wave takes bitmap words with a static stride, 64 at a time:
+// it loads the 64 words at once, lists their unvisited vertices of nonzero
+// degree, and runs them 64 per round.  A vertex probes its first four
+// entries itself; up to 16 entries it goes on four at a time, longer lists
+// are scanned by the whole wave, 64 entries per step.  Writes the next
+// visited bitmap Vout = Vin | found (whole words, no atomics).
 __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
@@ -386,42 +469,122 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   const uint64_t* Vin = P.vis[S.cur];
   uint64_t* Vout = P.vis[S.cur ^ 1];
   const int32_t d_new = S.k + 1;
-  int64_t insp = 0, ndeg = 0;
-  int32_t nnew = 0;
-  for (int64_t w = gw; w < P.nwords; w += W) {
-    const uint64_t vis = Vin[w];
-    const uint64_t act = P.nz[w] & ~vis;
-    uint64_t nb = 0;
-    if (act) {
-      const int32_t v = (int32_t)(w * 64 + lane);
+  int32_t* sc = L.w_sc[wid];
+  uint64_t* actw = L.pw_act[wid];
+  uint64_t* nbw = L.pw_nb[wid];
+  int32_t insp = 0, ndeg = 0, nnew = 0;
+  for (int64_t t0 = 0; gw + t0 * W < P.nwords; t0 += FG_WAVE) {
+    const int64_t wj = gw + (t0 + lane) * W;  // this lane's word of the batch
+    uint64_t vis = 0, act = 0;
+    if (wj < P.nwords) {
+      vis = Vin[wj];
+      act = P.nz[wj] & ~vis;
+    }
+    const int32_t c = __popcll(act);
+    const int32_t incl = fg_wave_incl_scan(c);
+    const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+    sc[lane] = incl - c;
+    actw[lane] = act;
+    nbw[lane] = 0;
+    wave_lds_fence();
+    for (int32_t a0 = 0; a0 < tot; a0 += FG_WAVE) {
+      const int32_t a = a0 + lane;
+      int32_t v = 0, b = 0, e = 0, jw = 0, bit = 0;
+      int4 hd = make_int4(0, 0, 0, 0);
+      const bool mine = a < tot;
+      if (mine) {
+        jw = upper_idx(sc, FG_WAVE, a);
+        bit = nth_bit(actw[jw], a - sc[jw]);
+        v = (int32_t)((gw + (t0 + jw) * W) * 64 + bit);
+        // the first four entries come from the head table: one coalesced
+        // 16-byte load issued with the offsets
+        b = P.off[v];
+        e = P.off[v + 1];
+        hd = P.head[v];
+      }
+      int32_t pu = -1, ins = 0;
       bool found = false;
-      int32_t pu = -1;
-      if ((act >> lane) & 1ull) {
-        const int32_t b0 = P.off[v];
-        const int32_t e = P.off[v + 1];
-        for (int32_t i = b0; i < e; ++i) {
-          const int32_t u = P.col[i];
-          insp++;
-          if ((Vin[u >> 6] >> (u & 63)) & 1ull) {
-            found = true;
-            pu = u;
-            break;
+      if (mine) {
+        const int32_t u[4] = {hd.x, hd.y, hd.z, hd.w};
+        uint64_t wv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wv[j] = Vin[u[j] >> 6];
+        int32_t h = -1;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+          if (j < e - b && ((wv[j] >> (u[j] & 63)) & 1ull)) {
+            h = j;
+            pu = u[j];
           }
         }
-        if (found) ndeg += e - b0;
+        found = h >= 0;
+        ins = found ? h + 1 : min(4, e - b);
       }
-      nb = __ballot(found);
+      // lists of up to 16 entries: four more at a time, lane by lane
+      bool shortl = mine && !found && e - b > 4 && e - b <= 16;
+      for (int32_t i0 = 4; i0 < 16 && __ballot(shortl); i0 += 4) {
+        if (shortl) {
+          if (b + i0 < e) {
+            const int32_t h = probe4(P, Vin, b + i0, e, pu);
+            if (h >= 0) {
+              found = true;
+              shortl = false;
+              ins += h + 1;
+            } else {
+              ins += min(4, e - b - i0);
+            }
+          } else {
+            shortl = false;
+          }
+        }
+      }
+      // longer lists: the whole wave scans one at a time
+      uint64_t pend = __ballot(mine && !found && e - b > 16);
+      while (pend) {
+        const int l = __builtin_ctzll(pend);
+        pend &= pend - 1;
+        const int32_t lb = __builtin_amdgcn_readlane(b, l) + 4;
+        const int32_t le = __builtin_amdgcn_readlane(e, l);
+        int32_t cnt = 0, hu = -1;
+        for (int32_t i0 = lb; i0 < le; i0 += FG_WAVE) {
+          const int32_t i = i0 + lane;
+          int32_t u = 0;
+          bool hb = false;
+          if (i < le) {
+            u = P.col[i];
+            hb = (Vin[u >> 6] >> (u & 63)) & 1ull;
+          }
+          const uint64_t m = __ballot(hb);
+          if (m) {
+            const int f = __builtin_ctzll(m);
+            cnt += f + 1;
+            hu = __builtin_amdgcn_readlane(u, f);
+            break;
+          }
+          cnt += min(FG_WAVE, le - i0);
+        }
+        if (lane == l) {
+          ins += cnt;
+          if (hu >= 0) {
+            found = true;
+            pu = hu;
+          }
+        }
+      }
+      insp += ins;
       if (found) {
         P.depth[v] = d_new;
         if (P.parent) P.parent[v] = pu;
+        ndeg += e - b;
+        nnew++;
+        atomicOr((unsigned long long*)&nbw[jw], 1ull << bit);
       }
-      nnew += __popcll(nb);
     }
-    if (lane == 0) Vout[w] = vis | nb;
+    wave_lds_fence();
+    if (wj < P.nwords) Vout[wj] = vis | nbw[lane];
   }
-  if (lane != 0) nnew = 0;
-  const int64_t tot = fg_block_sum<PB>(insp, L.red);
-  const int64_t tdeg = fg_block_sum<PB>(ndeg, L.red);
+  const int32_t tot = fg_block_sum<PB>(insp, L.red32);
+  const int32_t tdeg = fg_block_sum<PB>(ndeg, L.red32);
   const int32_t tn = fg_block_sum<PB>(nnew, L.red32);
   CtrSlot& C = P.ctl->slot[S.k & 1];
   if (threadIdx.x == 0) {
@@ -616,14 +779,24 @@ __device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
   return base + incl - w;
 }
 
-__device__ __forceinline__ void lq_put(Lds& L, int nxt, int32_t pos, int32_t v, int32_t vb,
-                                       int32_t ve, int32_t* Qo, ull* ovf, ull ovf_base) {
-  if (pos < QCAP) {
+// Stores this lane's discovered vertex (if `won`) at slot `pos` of the next
+// LDS queue; slots past QCAP go to the global queue, one atomic per wave.
+// Every lane of the wave must take part.
+__device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos, int32_t v,
+                                         int32_t vb, int32_t ve, int32_t* Qo, ull* ovf,
+                                         ull ovf_base) {
+  const bool over = won && pos >= QCAP;
+  if (won && !over) {
     L.lq_v[nxt][pos] = v;
     L.lq_b[nxt][pos] = vb;
     L.lq_e[nxt][pos] = ve;
-  } else {
-    Qo[atomicAdd(ovf, 1ull) - ovf_base] = v;  // overflow: global queue
+  }
+  const uint64_t om = __ballot(over);
+  if (om) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
+    base = fg_uni(base);
+    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
   }
 }
 
@@ -648,17 +821,33 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       load = false;
       const int64_t lo = S.qlen * blockIdx.x / T, hi = S.qlen * (blockIdx.x + 1) / T;
       const int32_t cnt = (int32_t)(hi - lo);
+      int32_t sd = 0;
       for (int32_t i = tid; i < cnt; i += PB) {
         const int32_t u = Qg[lo + i];
+        const int32_t b = P.off[u], e = P.off[u + 1];
         L.lq_v[cur][i] = u;
-        L.lq_b[cur][i] = P.off[u];
-        L.lq_e[cur][i] = P.off[u + 1];
+        L.lq_b[cur][i] = b;
+        L.lq_e[cur][i] = e;
+        sd += e - b;
       }
       if (tid == 0) {
         L.lq_cnt[ci] = cnt;
         L.lq_cnt[ni] = 0;
         L.lq_deg[ni] = 0;
         L.lq_big[ni] = 0;
+      }
+      if (S.qdeg < 0) {
+        // a full-grid push does not add up the degrees of what it finds:
+        // take the frontier's degree sum now and hand the level back if it
+        // does not suit this mode
+        int64_t qd = fg_block_sum<PB>(sd, L.red32);
+        if (!solo) {
+          if (!team_fast(P, L, T, tb.levels, cnt, (int32_t)qd, QCAP)) return false;
+          tb.levels++;
+          qd = fg_uni(L.tsum[1]);
+        }
+        S.qdeg = qd;
+        if (qd > LDS_MEAN_DEG * S.qlen || qd > (solo ? P.small_e : P.team_e)) return true;
       }
       __syncthreads();
     }
@@ -700,7 +889,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
       const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
       if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
-      if (won) lq_put(L, nxt, pos, v, vb, ve, Qo, ovf, ovf_base);
+      wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
     }
     if (big) L.lq_big[ni] = 1;
     __syncthreads();
@@ -742,7 +931,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
           const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
           const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
           if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
-          if (won) lq_put(L, nxt, pos, v, vb, ve, Qo, ovf, ovf_base);
+          wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
         }
         __syncthreads();
       }
@@ -778,7 +967,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
     S.p += nq;
     decide<MODE>(S, P);
     trace_iter(S, P);
-    bool stay = nq > 0 && S.dir == DIR_PUSH &&
+    bool stay = nq > 0 && S.dir == DIR_PUSH && nqdeg <= LDS_MEAN_DEG * nq &&
                 (solo ? (nq <= P.small_q && nqdeg <= P.small_e)
                       : (nqdeg <= P.team_e && !(nq <= P.small_q && nqdeg <= P.small_e)));
     int64_t nover = bcnt > QCAP ? bcnt - QCAP : 0, before = 0;
@@ -888,8 +1077,12 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
       S.prevdir = DIR_PUSH;
     }
-    const bool small_ep = S.dir == DIR_PUSH && S.qlen <= P.small_q && S.qdeg <= P.small_e;
-    const bool team_ep = !small_ep && S.dir == DIR_PUSH && P.team > 1 && S.qdeg <= P.team_e &&
+    // qdeg < 0: not known after a full-grid push; the LDS modes take it
+    // on entry and hand the level back when it does not fit
+    const bool qdu = S.qdeg < 0;
+    const bool lds_ok = S.dir == DIR_PUSH && (qdu || S.qdeg <= LDS_MEAN_DEG * S.qlen);
+    const bool small_ep = lds_ok && S.qlen <= P.small_q && (qdu || S.qdeg <= P.small_e);
+    const bool team_ep = !small_ep && lds_ok && P.team > 1 && (qdu || S.qdeg <= P.team_e) &&
                          S.qlen <= (int64_t)QCAP * P.team / 2;
     if (small_ep || team_ep) {
       sm_seen++;
@@ -991,7 +1184,8 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     const int64_t insp = (int64_t)(it - B.insp);
     B.q = qt;
     B.insp = it;
-    S.qdeg = (int64_t)(gt - B.deg);
+    // only a pull adds up the degrees of what it finds
+    S.qdeg = S.dir == DIR_PULL ? (int64_t)(gt - B.deg) : -1;
     B.deg = gt;
     set_bases(S, B);
     trace_insp(S.k, insp, P);
@@ -1167,6 +1361,7 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   P.off = g->off;
   P.col = g->col;
   P.nz = g->nzmask;
+  P.head = g->head;
   P.n = g->n;
   P.nwords = g->nwords;
   P.m = g->m;

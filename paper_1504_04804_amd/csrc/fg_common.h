@@ -28,6 +28,7 @@ struct fg_graph {
   const int32_t* col = nullptr;
   const uint32_t* w = nullptr;
   uint64_t* nzmask = nullptr;  // bit v set iff deg(v) > 0, nwords words
+  int4* head = nullptr;        // first four neighbours of each vertex (see graph.hip)
   void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t symmetric = 0;
   int32_t max_degree = 0;

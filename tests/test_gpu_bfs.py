@@ -138,6 +138,16 @@ def test_lds_queue_modes(fg, orc, rmat12):
         check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=2)
         check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=7, team_edges=1 << 20)
         check_bfs(fg, orc, g, off, col, 4000, mode, small_frontier=1, team_blocks=3)
+    # 100 vertices of degree 51 (mean degree low enough for LDS levels)
+    # discover 5000 leaves: more than one workgroup's LDS queue holds
+    edges = [(0, i) for i in range(1, 101)]
+    edges += [(i, 101 + 50 * (i - 1) + j) for i in range(1, 101) for j in range(50)]
+    off, col = synth.from_edge_pairs(5101, edges)
+    g = fg.Graph(off, col)
+    for mode in ("do", "push"):
+        check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1 << 18)
+        check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=2)
+        check_bfs(fg, orc, g, off, col, 0, mode, small_edges=1, team_blocks=3, team_edges=1 << 18)
     off, col, g = rmat12
     for team in (-1, 2, 5, 64, 10**6):
         for s in (0, 5):
