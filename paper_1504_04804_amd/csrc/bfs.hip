@@ -19,7 +19,7 @@
 // Data layout in HBM (all owned by the caller's workspace, 256-B aligned):
 //   visited   2 x uint64[ceil(n/64)]  current / next visited bitmap
 //   queue     2 x int32[n]            input / output vertex frontier
-//   desc      int2[m/CH + n + 64]     edge-chunk descriptors {vertex, first edge}
+//   desc      int4[m/CH + n + 64]     edge-chunk descriptors {vertex, first edge, end edge}
 //   control   barrier, counters, hand-back state of the small-frontier mode
 #include <string.h>
 
@@ -109,7 +109,7 @@ struct BfsParams {
   int32_t* parent;
   uint64_t* vis[2];
   int32_t* q[2];
-  int2* desc;
+  int4* desc;
   BfsCtl* ctl;
   fg_run_stats* stats;
   uint32_t a_num, a_den, b_num, b_den;
@@ -250,7 +250,7 @@ __device__ __forceinline__ void visit4(const BfsParams& P, uint32_t* vis32, int3
 }
 
 constexpr int STAGE = 512;   // per-wave LDS staging of discovered vertices
-constexpr int DSTAGE = 128;  // per-wave LDS staging of descriptors
+constexpr int DSTAGE = 64;   // per-wave LDS staging of descriptors
 
 struct Lds {
   // LDS-queue mode: frontier share of this workgroup as (vertex, first edge,
@@ -262,11 +262,12 @@ struct Lds {
   int32_t lq_deg[3];   // ... their degree sum
   int32_t lq_big[3];   // ... an input vertex of degree > TPV was seen
   int32_t stage[PWAVES][STAGE];
-  int2 dstage[PWAVES][DSTAGE];
+  int4 dstage[PWAVES][DSTAGE];
   // per-wave scan-gather staging (push, full grid)
   int32_t w_sc[PWAVES][FG_WAVE];
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
+  int32_t w_e[PWAVES][FG_WAVE];
   // per-wave pull batch: unvisited vertices of nonzero degree per bitmap
   // word, and the vertices found per word
   uint64_t pw_act[PWAVES][FG_WAVE];
@@ -299,7 +300,8 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  WaveStage<int4, DSTAGE> dst{L.dstage[wid], 0};
+  int32_t* se = L.w_e[wid];
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)nblocks * PWAVES;
   int64_t insp = 0;
@@ -322,13 +324,15 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
       sc[lane] = ndi - nd;
       su[lane] = u;
       sb[lane] = b;
+      se[lane] = b + deg;
       wave_lds_fence();
       for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
         const int32_t t = t0 + lane;
-        int2 dsc = make_int2(0, 0);
+        int4 dsc = make_int4(0, 0, 0, 0);
         if (t < ND) {
           const int32_t j = upper_idx(sc, FG_WAVE, t);
-          dsc = make_int2(su[j], sb[j] + (t - sc[j]) * CH);
+          const int32_t first = sb[j] + (t - sc[j]) * CH;
+          dsc = make_int4(su[j], first, first + CH < se[j] ? first + CH : se[j], 0);
         }
         dst.push(t < ND, dsc, &C.desc.v, B.desc, P.desc);
       }
@@ -382,11 +386,13 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  // the next descriptor is loaded while the current one is processed
+  int4 nd = gw < ndesc ? P.desc[gw] : make_int4(0, 0, 0, 0);
   for (int64_t i = gw; i < ndesc; i += W) {
-    const int2 dsc = P.desc[i];
+    const int4 dsc = nd;
+    if (i + W < ndesc) nd = P.desc[i + W];
     const int32_t u = dsc.x;
-    const int32_t e_end = P.off[u + 1];
-    const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
+    const int32_t e1 = dsc.z;
     // the CH / 64 = 4 rounds of a descriptor with their loads and atomics
     // overlapped (indices past the chunk clamped to its last edge)
     static_assert(CH == 4 * FG_WAVE, "one visit4 per descriptor");
@@ -596,29 +602,43 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
 
 // ---- backward -> forward switch: the new frontier is the set difference
 // of the current and the previous visited bitmap, listed into Q[qsel].
-__device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S) {
+__device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S, Lds& L) {
+  // each workgroup lists a contiguous range of bitmap words (a multiple of
+  // 64 words, 64 per wave and step) and reserves its queue slots with one
+  // atomic per step
   const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
   const uint64_t* Vnew = P.vis[S.cur];
   const uint64_t* Vold = P.vis[S.cur ^ 1];
   int32_t* Q = P.q[S.qsel];
-  const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
-  const int64_t nth = (int64_t)gridDim.x * PB;
-  for (int64_t w0 = tid - lane; w0 < P.nwords; w0 += nth) {
-    const int64_t w = w0 + lane;
-    uint64_t diff = 0;
-    if (w < P.nwords) diff = Vnew[w] & ~Vold[w];
-    const int32_t c = __popcll(diff);
+  const int64_t per = ((P.nwords + gridDim.x - 1) / gridDim.x + FG_WAVE - 1) / FG_WAVE * FG_WAVE;
+  const int64_t wb = (int64_t)blockIdx.x * per;
+  const int64_t we = wb + per < P.nwords ? wb + per : P.nwords;
+  for (int64_t c0 = wb; c0 < we; c0 += PWAVES * FG_WAVE) {
+    const int64_t w = c0 + wid * FG_WAVE + lane;
+    const uint64_t diff0 = w < we ? Vnew[w] & ~Vold[w] : 0ull;
+    const int32_t c = __popcll(diff0);
     const int32_t inc = fg_wave_incl_scan(c);
-    const int32_t tot = __shfl(inc, FG_WAVE - 1, FG_WAVE);
-    ull base = 0;
-    if (lane == FG_WAVE - 1 && tot) base = atomicAdd(&P.ctl->aux.v, (ull)tot);
-    base = __shfl(base, FG_WAVE - 1, FG_WAVE) - S.auxbase;
-    int64_t pos = (int64_t)base + inc - c;
+    if (lane == FG_WAVE - 1) L.red32[wid] = inc;
+    __syncthreads();
+    int32_t before = 0, btot = 0;
+#pragma unroll
+    for (int i = 0; i < PWAVES; ++i) {
+      const int32_t x = L.red32[i];
+      before += i < wid ? x : 0;
+      btot += x;
+    }
+    if (threadIdx.x == 0)
+      L.bcast[0] = btot ? (int64_t)(atomicAdd(&P.ctl->aux.v, (ull)btot) - S.auxbase) : 0;
+    __syncthreads();
+    int64_t pos = L.bcast[0] + before + inc - c;
+    uint64_t diff = diff0;
     while (diff) {
       const int bit = __builtin_ctzll(diff);
       diff &= diff - 1;
       Q[pos++] = (int32_t)(w * 64 + bit);
     }
+    __syncthreads();
   }
 }
 
@@ -1072,7 +1092,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   while (ok && S.qlen > 0) {
     // backward -> forward: list the last pull's discoveries first
     if (MODE == FG_MODE_DO && S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
-      bitmap_diff_to_queue(P, S);
+      bitmap_diff_to_queue(P, S, L);
       if (!(ok = gs.sync(&L.flag))) break;
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
       S.prevdir = DIR_PUSH;
@@ -1269,7 +1289,7 @@ struct BfsLayout {
   BfsCtl* ctl;
   uint64_t* vis[2];
   int32_t* q[2];
-  int2* desc;
+  int4* desc;
   size_t bytes;
 };
 
@@ -1281,7 +1301,7 @@ BfsLayout bfs_layout(const fg_graph* g, void* ws) {
   L.vis[1] = c.take<uint64_t>(g->nwords);
   L.q[0] = c.take<int32_t>(g->n);
   L.q[1] = c.take<int32_t>(g->n);
-  L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
+  L.desc = c.take<int4>((size_t)(g->m / CH) + (size_t)g->n + 64);
   L.bytes = c.used;
   return L;
 }

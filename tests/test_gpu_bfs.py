@@ -120,6 +120,11 @@ def test_grid_high_diameter(fg, orc):
     for s in (0, 128 * 256 + 128):
         check_bfs(fg, orc, g, off, col, s, "push")
     check_bfs(fg, orc, g, off, col, 0, "push", small_frontier=1, small_edges=1)
+    # full-grid levels only, every vertex cut into descriptors (phase B on
+    # every level), the same workspace reused across the runs
+    for src in (0, 255, 128 * 256 + 128):
+        check_bfs(fg, orc, g, off, col, src, "push", small_frontier=1, small_edges=1,
+                  team_blocks=-1, big_degree=2)
     # team levels whose shares drift apart (the frontier grows at its ends)
     check_bfs(fg, orc, g, off, col, 0, "push", small_edges=1, team_blocks=8)
     check_bfs(fg, orc, g, off, col, 128 * 256 + 128, "push", small_edges=1, team_blocks=64)
