@@ -46,9 +46,9 @@ constexpr int LDS_MEAN_DEG = 64;  // LDS-queue levels need a frontier of mean de
 constexpr int TPV = 4;        // LDS-queue levels: vertices of degree <= TPV are
                               // expanded by TPV lanes each, without a scan
 constexpr int32_t DEF_SMALL_Q = QCAP;
-constexpr int64_t DEF_SMALL_E = 4096;
+constexpr int64_t DEF_SMALL_E = 1536;
 constexpr int32_t DEF_BIG_DEG = 64;
-constexpr int32_t DEF_TEAM = 16;
+constexpr int32_t DEF_TEAM = 32;
 constexpr int64_t DEF_TEAM_E = 65536;
 
 typedef unsigned __int128 u128;
@@ -692,14 +692,19 @@ struct TeamBases {
 // makes its own arrival wait for the clear, which every later arrival at
 // that slot follows.  A member flags itself when its count exceeds `lim`.
 // L.tsum: [0] discovered, [1] degree sum, [2] flagged members.
+// Workgroup 0 clears the word of team level `level + 1` (issued early in
+// the level; team_fast waits for it before arriving).
+__device__ __forceinline__ ull team_clear_next(const BfsParams& P, uint32_t level) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    return __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
 __device__ bool team_fast(const BfsParams& P, Lds& L, uint32_t T, uint32_t level, int32_t bcnt,
-                          int32_t bdeg, int32_t lim) {
+                          int32_t bdeg, int32_t lim, ull cleared) {
   if (threadIdx.x == 0) {
     ull* w = &P.ctl->team_word[level % 3].v;
-    ull cleared = 0;
-    if (blockIdx.x == 0)
-      cleared = __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull,
-                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const ull g = bdeg < TW_CAP ? (ull)bdeg : (ull)TW_CAP;
     const ull add = (1ull << TW_ARR) | ((ull)(bcnt > lim) << TW_FLAG) | ((ull)bcnt << TW_CNT) | g;
     // the exchange's old value is consumed before the arrival is issued
@@ -862,7 +867,8 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
         // does not suit this mode
         int64_t qd = fg_block_sum<PB>(sd, L.red32);
         if (!solo) {
-          if (!team_fast(P, L, T, tb.levels, cnt, (int32_t)qd, QCAP)) return false;
+          if (!team_fast(P, L, T, tb.levels, cnt, (int32_t)qd, QCAP, team_clear_next(P, tb.levels)))
+            return false;
           tb.levels++;
           qd = fg_uni(L.tsum[1]);
         }
@@ -873,6 +879,9 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
     }
     const int nxt = cur ^ 1;
     const int32_t cnt = L.lq_cnt[ci];
+    // issued now, so that it is done by the time this level's exchange
+    // needs it
+    const ull cleared = solo ? 0ull : team_clear_next(P, tb.levels);
     if (tid == 0) {
       L.lq_cnt[ri] = 0;
       L.lq_deg[ri] = 0;
@@ -970,8 +979,8 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
         const ull tag = (ull)((uint32_t)S.k + 1u) << 32;
         __hip_atomic_store(r, tag | (uint32_t)bcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      const int64_t lim = 2 * S.qlen / T + 64;
-      if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP)))
+      const int64_t lim = (5 * S.qlen / T + 64) / 4;
+      if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP), cleared))
         return false;
       tb.levels++;
       nq = fg_uni(L.tsum[0]);
@@ -1000,8 +1009,8 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       before = fg_uni(L.tsum[4]);
       stay = stay && fg_uni(L.tsum[2]) == 0;
       // the frontier grows at its ends: even out the members' shares when
-      // the largest is well above the mean
-      rebalance = stay && fg_uni(L.tsum[5]) * (int64_t)T > 2 * nq + 64 * (int64_t)T;
+      // the largest is more than 1.25 times the mean (+16)
+      rebalance = stay && 4 * fg_uni(L.tsum[5]) * (int64_t)T > 5 * nq + 64 * (int64_t)T;
     }
     if (!stay || rebalance) {
       // global queue: the overflow entries, then every member's LDS queue
