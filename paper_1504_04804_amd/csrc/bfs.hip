@@ -412,12 +412,6 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
   st.flush(&C.q.v, B.q, Qout);
 }
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
-  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // Position of the r-th set bit (r = 0 first) of x; x has more than r bits set.
 __device__ __forceinline__ int nth_bit(uint64_t x, int r) {
   int pos = 0;

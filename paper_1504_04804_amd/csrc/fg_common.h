@@ -115,6 +115,31 @@ __device__ __forceinline__ T fg_wave_sum(T x) {
   return x;
 }
 
+// 64-bit value of lane l (l wave-uniform).
+__device__ __forceinline__ unsigned long long fg_readlane64(unsigned long long x, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Wave-wide OR of 32 / 64-bit values through DPP (all lanes active);
+// the result is wave-uniform.
+__device__ __forceinline__ uint32_t fg_wave_or32(uint32_t x) {
+  int32_t y = (int32_t)x;
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x111, 0xf, 0xf, false);  // row_shr:1
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x112, 0xf, 0xf, false);  // row_shr:2
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x114, 0xf, 0xf, false);  // row_shr:4
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x118, 0xf, 0xf, false);  // row_shr:8
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  y |= __builtin_amdgcn_update_dpp(0, y, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane(y, FG_WAVE - 1);
+}
+__device__ __forceinline__ unsigned long long fg_wave_or64(unsigned long long x) {
+  const uint32_t lo = fg_wave_or32((uint32_t)x);
+  const uint32_t hi = fg_wave_or32((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Wave total of 32-bit values (DPP scan, then the last lane's value).
 __device__ __forceinline__ int32_t fg_wave_sum(int32_t x) {
   return __builtin_amdgcn_readlane(fg_wave_incl_scan(x), FG_WAVE - 1);

@@ -72,6 +72,7 @@ struct alignas(256) MsCtl {
 struct MsParams {
   const int32_t* __restrict__ off;
   const int32_t* __restrict__ col;
+  const int4* __restrict__ head;  // first four neighbours per vertex
   int32_t n;
   int64_t m;
   int32_t lanes;
@@ -98,9 +99,11 @@ struct Lds {
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
   int64_t red[PWAVES + 1];
+  int32_t red32[PWAVES + 1];
   ull redu[PWAVES + 1];
   int32_t flag;
   int64_t bcast[4];
+  int32_t start[MAXL];  // iteration at which each lane was admitted
 };
 
 __device__ __forceinline__ ull block_or(ull x, ull* scratch) {
@@ -291,6 +294,8 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
     S.used |= mask;
   }
 
+  if (threadIdx.x < MAXL) L.start[threadIdx.x] = P.state->start[threadIdx.x];
+  __syncthreads();
   for (int32_t k = 0; ok && k < P.k_iters && S.live != 0ull; ++k) {
     const int32_t it1 = S.it + 1;
     const bool want_pull = S.mode == 0 ? S.qlen > P.n / P.pull_div : S.qlen >= P.n / P.push_div;
@@ -326,35 +331,74 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
       S.mode = 0;
     }
     if (want_pull) {
-      // ---- pull: lane per vertex, early exit when every wanted lane is seen
+      // ---- pull: lane per vertex, early exit when every wanted lane is
+      // seen.  The first four neighbours come from the head table (one
+      // coalesced load); lists of up to 32 go on four entries at a time,
+      // longer ones are scanned by the whole wave, 64 entries per step.
       const ull* Fc = P.F[S.fsel];
       ull* Fn = P.F[S.fsel ^ 1];
       ull lor = 0;
-      int64_t act = 0;
+      int32_t act = 0;
       for (int64_t v0 = gw * FG_WAVE; v0 < P.n; v0 += W * FG_WAVE) {
         const int64_t v = v0 + lane;
-        ull nw = 0;
+        ull vis = ~0ull, nw = 0;
+        int32_t b = 0, e = 0;
+        int4 hd = make_int4(0, 0, 0, 0);
         if (v < P.n) {
-          const ull vis = P.visit[v];
-          const ull want = S.live & ~vis;
-          if (want) {
-            const int32_t e = P.off[v + 1];
-            for (int32_t i = P.off[v]; i < e; ++i) {
-              nw |= Fc[P.col[i]] & want;
-              if (nw == want) break;
-            }
-            if (nw) {
-              P.visit[v] = vis | nw;
-              write_depths(P, (int32_t)v, nw, it1 - 0);
-            }
+          vis = P.visit[v];
+          b = P.off[v];
+          e = P.off[v + 1];
+          hd = P.head[v];
+        }
+        const ull want = S.live & ~vis;
+        if (want && e > b) {
+          const int32_t d = e - b;
+          const ull f0 = Fc[hd.x], f1 = Fc[hd.y], f2 = Fc[hd.z], f3 = Fc[hd.w];
+          nw = (f0 | (d > 1 ? f1 : 0ull) | (d > 2 ? f2 : 0ull) | (d > 3 ? f3 : 0ull)) & want;
+        }
+        bool shortl = want && nw != want && e - b > 4 && e - b <= 32;
+        for (int32_t i0 = 4; i0 < 32 && __ballot(shortl); i0 += 4) {
+          if (shortl) {
+            const int32_t i = b + i0, l = e - 1;
+            const int32_t u0 = P.col[i], u1 = P.col[i + 1 < l ? i + 1 : l],
+                          u2 = P.col[i + 2 < l ? i + 2 : l], u3 = P.col[i + 3 < l ? i + 3 : l];
+            const ull g = Fc[u0] | Fc[u1] | Fc[u2] | Fc[u3];
+            nw |= g & want;
+            if (nw == want || i + 4 >= e) shortl = false;
           }
+        }
+        uint64_t pend = __ballot(want && nw != want && e - b > 32);
+        while (pend) {
+          const int l = __builtin_ctzll(pend);
+          pend &= pend - 1;
+          const int32_t lb = __builtin_amdgcn_readlane(b, l) + 4;
+          const int32_t le = __builtin_amdgcn_readlane(e, l);
+          const ull lw = fg_readlane64(want, l);
+          ull acc = fg_readlane64(nw, l);
+          for (int32_t i0 = lb; i0 < le && (acc & lw) != lw; i0 += FG_WAVE) {
+            const int32_t i = i0 + lane;
+            ull x = 0;
+            if (i < le) x = Fc[P.col[i]] & lw;
+            acc |= fg_wave_or64(x);
+          }
+          if (lane == l) nw = acc & lw;
+        }
+        if (v < P.n) {
+          if (nw) P.visit[v] = vis | nw;
           Fn[v] = nw;
+        }
+        // depths, lane by lane over the wave's union: coalesced row stores
+        ull uni = fg_wave_or64(nw);
+        while (uni) {
+          const int l = __builtin_ctzll(uni);
+          uni &= uni - 1;
+          if ((nw >> l) & 1ull) P.depth[(int64_t)l * P.n + v] = it1 - L.start[l];
         }
         lor |= nw;
         act += nw != 0ull;
       }
       const ull bor = block_or(lor, L.redu);
-      const int64_t bact = fg_block_sum<PB>(act, L.red);
+      const int32_t bact = fg_block_sum<PB>(act, L.red32);
       if (threadIdx.x == 0) {
         if (bor) atomicOr(livew, bor);
         if (bact) atomicAdd(&C.cnt.v, (ull)bact);
@@ -561,6 +605,7 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   memset(&P, 0, sizeof(P));
   P.off = g->off;
   P.col = g->col;
+  P.head = g->head;
   P.n = g->n;
   P.m = g->m;
   P.lanes = b->lanes;
