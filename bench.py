@@ -31,6 +31,15 @@ SCALE = 22
 EDGE_FACTOR = 16
 NSRC = 64
 GRID = 4096
+# HBM bytes per launch of each BFS kernel from the two rocprofv3 counter
+# passes (read = 2 x FETCH_SIZE KiB, written = 1 x WRITE_SIZE KiB, factors
+# from a plain 512 MiB device copy; profiles/bfs_persistent_hbm_counters_
+# rmat22x64_grid4096.md).  They hold only for the kernel sources they were
+# taken with: `traffic` is null when these files hash differently.
+TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
+TRAFFIC_SHA256 = "5efa90092dc1a3241a1e82820d8235f6eab94be540c5186db02d45a2edfdb3ab"
+TRAFFIC_BYTES = {"bfs_persistent<DO>": 244264550, "bfs_persistent<PUSH>": 2923487539}
+
 # direction-switch thresholds of the DO runs (Sec. VI-A do_a, do_b), as
 # chosen for this workload by paper_1504_04804_amd.autotune (stage-1 sweep
 # over do_a in 1e-1..1e-5, do_b in 1e-1..10); the paper's own example
@@ -225,6 +234,12 @@ def main():
         k["frac"] = k["gbs"] / HBM_PEAK_GBS
     dom = max(kernels, key=lambda k: kernels[k]["share_ms"])
     dk = kernels[dom]
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1504_04804_amd", f), "rb") as fh:
+            hsh.update(fh.read())
+    traffic = TRAFFIC_BYTES.get(dom) if hsh.hexdigest() == TRAFFIC_SHA256 else None
     step_ms = ms_per_step
     value = edges_step / (step_ms * 1e-3) / 1e9
 
@@ -255,7 +270,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(dk["frac"], 5),
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": round(dk["ms"], 4),
             "alg_bytes_per_launch": round(dk["bytes"]),
         },
