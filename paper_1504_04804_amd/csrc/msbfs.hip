@@ -36,6 +36,11 @@ constexpr int CH = 256;
 constexpr int STAGE = 512;
 constexpr int DSTAGE = 128;
 constexpr int MAXL = 64;
+// Pull: vertices with more than LONG_PULL unresolved entries are not scanned
+// by their own wave (the hubs of an R-MAT graph sit in the first bitmap
+// words, so one wave would scan them all); they are listed and their lists
+// cut into CH-entry chunks that every wave takes in turn.
+constexpr int32_t LONG_PULL = 64;
 
 struct MsState {
   int32_t it;      // global iteration counter
@@ -337,6 +342,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
       // longer ones are scanned by the whole wave, 64 entries per step.
       const ull* Fc = P.F[S.fsel];
       ull* Fn = P.F[S.fsel ^ 1];
+      int32_t* Qlong = P.q[S.qsel ^ 1];  // queues are idle while pulling
       ull lor = 0;
       int32_t act = 0;
       for (int64_t v0 = gw * FG_WAVE; v0 < P.n; v0 += W * FG_WAVE) {
@@ -367,7 +373,15 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             if (nw == want || i + 4 >= e) shortl = false;
           }
         }
-        uint64_t pend = __ballot(want && nw != want && e - b > 32);
+        const bool lng = want && nw != want && e - b > LONG_PULL;
+        if (lng) {
+          // listed for the chunked scan; the lanes found so far stay in Fn
+          const int32_t nch = (e - b - 4 + CH - 1) / CH;
+          Qlong[atomicAdd(&C.q.v, 1ull) - qbp] = (int32_t)v;
+          const int64_t d0 = (int64_t)(atomicAdd(&C.desc.v, (ull)nch) - dbp);
+          for (int32_t c = 0; c < nch; ++c) P.desc[d0 + c] = make_int2((int32_t)v, b + 4 + c * CH);
+        }
+        uint64_t pend = __ballot(want && nw != want && e - b > 32 && !lng);
         while (pend) {
           const int l = __builtin_ctzll(pend);
           pend &= pend - 1;
@@ -384,9 +398,10 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           if (lane == l) nw = acc & lw;
         }
         if (v < P.n) {
-          if (nw) P.visit[v] = vis | nw;
+          if (nw && !lng) P.visit[v] = vis | nw;
           Fn[v] = nw;
         }
+        if (lng) nw = 0;  // finished after the chunked scan
         // depths, lane by lane over the wave's union: coalesced row stores
         ull uni = fg_wave_or64(nw);
         while (uni) {
@@ -397,13 +412,65 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         lor |= nw;
         act += nw != 0ull;
       }
-      const ull bor = block_or(lor, L.redu);
-      const int32_t bact = fg_block_sum<PB>(act, L.red32);
-      if (threadIdx.x == 0) {
-        if (bor) atomicOr(livew, bor);
-        if (bact) atomicAdd(&C.cnt.v, (ull)bact);
+      {
+        const ull bor = block_or(lor, L.redu);
+        const int32_t bact = fg_block_sum<PB>(act, L.red32);
+        if (threadIdx.x == 0) {
+          if (bor) atomicOr(livew, bor);
+          if (bact) atomicAdd(&C.cnt.v, (ull)bact);
+        }
       }
       if (!(ok = gs.sync(&L.flag))) break;
+      // ---- listed long vertices (if any): chunked scan by every wave, then
+      // finalise; without them the level costs one grid barrier as before
+      {
+        const ull lt = fg_atomic_load_u64(&C.q.v);
+        const ull dt = fg_atomic_load_u64(&C.desc.v);
+        const int64_t nlong = (int64_t)(lt - qbp), nch = (int64_t)(dt - dbp);
+        qbp = lt;
+        dbp = dt;
+        if (nch > 0) {
+          for (int64_t i = gw; i < nch; i += W) {
+            const int2 dsc = P.desc[i];
+            const int32_t v = dsc.x;
+            const ull want = S.live & ~P.visit[v];
+            const ull cur = fg_uni(__hip_atomic_load(&Fn[v], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+            if ((cur & want) == want) continue;  // every wanted lane already found
+            const int32_t e1 = min(dsc.y + CH, P.off[v + 1]);
+            ull x = 0;
+#pragma unroll
+            for (int r = 0; r < CH / FG_WAVE; ++r) {
+              const int32_t i2 = dsc.y + r * FG_WAVE + lane;
+              if (i2 < e1) x |= Fc[P.col[i2]];
+            }
+            x = fg_wave_or64(x & want);
+            if (lane == 0 && (x & ~cur)) atomicOr(&Fn[v], x);
+          }
+          if (!(ok = gs.sync(&L.flag))) break;
+          ull lor2 = 0;
+          int32_t act2 = 0;
+          for (int64_t i = tid; i < nlong; i += nth) {
+            const int32_t v = Qlong[i];
+            const ull vis = P.visit[v];
+            const ull nw = Fn[v] & S.live & ~vis;
+            Fn[v] = nw;
+            if (nw) {
+              P.visit[v] = vis | nw;
+              write_depths(P, v, nw, it1);
+            }
+            lor2 |= nw;
+            act2 += nw != 0ull;
+          }
+          const ull bor = block_or(lor2, L.redu);
+          const int32_t bact = fg_block_sum<PB>(act2, L.red32);
+          if (threadIdx.x == 0) {
+            if (bor) atomicOr(livew, bor);
+            if (bact) atomicAdd(&C.cnt.v, (ull)bact);
+          }
+          if (!(ok = gs.sync(&L.flag))) break;
+        }
+      }
       const ull lv = fg_atomic_load_u64(livew);
       const ull ct = fg_atomic_load_u64(&C.cnt.v);
       S.qlen = (int64_t)(ct - cbp);
