@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sources", type=int, default=8)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the per-config side measurements (SSSP, package, batched, serving)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 512 MiB device copy three times (for the "
                          "rocprof FETCH_SIZE / WRITE_SIZE scale factor)")
@@ -120,6 +122,277 @@ def cpu_baseline(off, col, srcs, goff, gcol):
     t_total += time.perf_counter() - t0
     edges += mc
     return edges / t_total / 1e9, t_total
+
+
+# ------------------------------------------------------- side measurements
+
+def _ev():
+    import torch
+    return torch.cuda.Event(enable_timing=True)
+
+
+def sssp_alg_bytes(st, n, nwords):
+    """SSSP bytes from the device statistics: init 8n + n/8; per iteration
+    16|F| (frontier id, 2 offsets, dist of u) + 12 per inspected edge (col,
+    weight, dist of v) + 4|F'|."""
+    total = 8 * n + nwords * 8
+    k_tr = min(st.iterations, 64)
+    fr = list(st.frontier[:k_tr])
+    ins = list(st.inspected[:k_tr])
+    for k in range(k_tr):
+        nxt = fr[k + 1] if k + 1 < k_tr else 0
+        total += 16 * fr[k] + 12 * ins[k] + 4 * nxt
+    if st.iterations > 64:
+        total += 12 * (st.edges_inspected - sum(ins))
+    return float(total)
+
+
+def side_sssp(fg, torch, off, col, srcs, stream, cpu):
+    """C3a: SSSP on R-MAT 22 with uint32 weights in [1, 64] from the first 16
+    of the DOBFS sources, one at a time."""
+    import synth
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w, symmetric=True, validate=False)
+    n = g.n
+    dist = torch.empty(n, dtype=torch.int32, device="cuda")
+    par = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = g.workspace(fg.FG_PRIM_SSSP)
+    st = fg.new_stats()
+    deg = torch.diff(g.off)
+    srcs = [int(x) for x in srcs[:16]]
+    m_comp = []
+    for s in srcs:
+        fg.sssp_into(g, s, dist, par, ws=ws, stats=st, stream=stream)
+        torch.cuda.synchronize()
+        m_comp.append(int(deg[dist != -1].sum().item()))
+    lat, byts = [], []
+    for s in srcs:
+        a, b = _ev(), _ev()
+        a.record(stream)
+        fg.sssp_into(g, s, dist, par, ws=ws, stats=st, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+        byts.append(sssp_alg_bytes(fg.read_stats(st), n, (n + 63) // 64))
+    ms = float(np.mean(lat))
+    gbs = float(np.mean(byts)) / (ms * 1e-3) / 1e9
+    out = {
+        "workload": "SSSP rmat22 ef16, uint32 weights in [1,64], first 16 of the 64 sources, one at a time",
+        "ms_per_source": round(ms, 4), "ms_p50": round(float(np.percentile(lat, 50)), 4),
+        "ms_p99": round(float(np.percentile(lat, 99)), 4),
+        "gteps": round(sum(m_comp) / (sum(lat) * 1e-3) / 1e9, 3),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 5),
+                     "alg_bytes_per_launch": round(float(np.mean(byts)))},
+    }
+    if cpu:
+        import oracle
+        orc = oracle.oracle()
+        t0 = time.perf_counter()
+        mc = 0
+        for s in srcs[:2]:
+            d = orc.dijkstra(off, col, w, s)[0]
+            mc += int(np.diff(off)[d != 0xFFFFFFFF].sum())
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(mc / t / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"binary-heap Dijkstra (oracle) from the first 2 sources, {t:.1f}s"}
+    g.close()
+    return out
+
+
+class _ShareGraph:
+    """The share's local graph as an fg.bfs_into target."""
+
+    def __init__(self, fg, torch, share):
+        self.handle = share.graph_handle
+        self.n = share.n_total
+        nb = int(fg.lib().fg_workspace_bytes(self.handle, fg.FG_PRIM_BFS, 0))
+        self.ws = torch.zeros(max(nb, 256), dtype=torch.uint8, device="cuda")
+
+    def workspace(self, prim):
+        return self.ws
+
+
+def side_package(fg, torch, stream, cpu, off, col):
+    """C3b: the package step (split + gather per peer) on one GPU's quarter
+    share of R-MAT 24 (random 4-way owners, duplicate-1-hop), timed on the
+    output frontiers of a push BFS over the local graph from local vertex 0."""
+    import ctypes
+    import synth
+    t0 = time.time()
+    owner = synth.owners(len(off) - 1, 4)
+    sh = fg.Share(off, col, owner, 4, 0)
+    print(f"[bench] rmat24 quarter share built in {time.time() - t0:.1f}s: "
+          f"n_local={sh.n_local} n_total={sh.n_total} m_local={sh.m_local}",
+          file=sys.stderr, flush=True)
+    lg = _ShareGraph(fg, torch, sh)
+    nt = sh.n_total
+    depth = torch.empty(nt, dtype=torch.int32, device="cuda")
+    parent = torch.empty(nt, dtype=torch.int32, device="cuda")
+    fg.bfs_into(lg, 0, depth, parent, fg.bfs_opts(mode=fg.FG_MODE_PUSH), ws=lg.ws, stream=stream)
+    torch.cuda.synchronize()
+    levels = int(depth.max().item())
+    fronts = [torch.nonzero(depth == k + 1).flatten().to(torch.int32) for k in range(levels)]
+    cap = max(int(f.numel()) for f in fronts)
+    P = 4
+    ids = torch.empty(P * cap, dtype=torch.int32, device="cuda")
+    dep = torch.empty(P * cap, dtype=torch.int32, device="cuda")
+    par = torch.empty(P * cap, dtype=torch.int32, device="cuda")
+    counts = torch.zeros(P, dtype=torch.int32, device="cuda")
+    local = torch.empty(cap, dtype=torch.int32, device="cuda")
+    lc = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pws = sh.workspace(cap)
+    bufs = fg.PeerBufs(ids.data_ptr(), dep.data_ptr(), par.data_ptr(), counts.data_ptr(),
+                       local.data_ptr(), lc.data_ptr(), cap)
+    L = fg.lib()
+    sp = fg._stream(stream)
+
+    def run_all(evs):
+        for k, f in enumerate(fronts):
+            if evs:
+                evs[k][0].record(stream)
+            fg._check(L.fg_package(sh.handle, fg._ptr(f), int(f.numel()), fg._ptr(depth),
+                                   fg._ptr(parent), ctypes.byref(bufs), fg._ptr(pws),
+                                   pws.numel(), sp))
+            if evs:
+                evs[k][1].record(stream)
+
+    run_all(None)
+    evs = [(_ev(), _ev()) for _ in fronts]
+    run_all(evs)
+    torch.cuda.synchronize()
+    us = [a.elapsed_time(b) * 1e3 for a, b in evs]
+    nv = [int(f.numel()) for f in fronts]
+    big = int(np.argmax(nv))
+    bpv = 4 + 1 + 4 + 4 + 4 + 4 + 4 + 4  # id, owner, conv, depth, parent in; id, depth, parent out
+    gbs_big = nv[big] * bpv / (us[big] * 1e-6) / 1e9
+    out = {
+        "workload": "package step on share 0 of 4 (rmat24 ef16, random owners, duplicate-1-hop), "
+                    "output frontiers of a push BFS on the local graph from local vertex 0, with parents",
+        "n_local": sh.n_local, "n_total": nt, "m_local": sh.m_local, "iterations": levels,
+        "frontier_sizes": nv, "us_per_iteration": [round(x, 2) for x in us],
+        "us_total": round(sum(us), 2),
+        "vertices_per_s": round(sum(nv) / (sum(us) * 1e-6), 1),
+        "roofline": {"bound": "hbm", "achieved": round(gbs_big, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs_big / HBM_PEAK_GBS, 5),
+                     "note": f"largest iteration ({nv[big]} vertices), {bpv} B per vertex"},
+    }
+    if cpu:
+        import oracle
+        orc = oracle.oracle()
+        own, conv, l2g = sh.tables()
+        fr = fronts[big].cpu().numpy()
+        dh = depth.cpu().numpy()
+        ph = parent.cpu().numpy()
+        t0 = time.perf_counter()
+        orc.package(fr, sh.n_local, own, conv, dh, ph, l2g, 4)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(fr) / t, 1), "unit": "vertices/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle package of the largest iteration ({len(fr)} vertices)"}
+    sh.close()
+    return out
+
+
+def side_batched(fg, torch, stream):
+    """C4: 64 sources per launch on R-MAT 23 and on a 2048 x 2048 grid,
+    against the one-source-at-a-time path on the same GPU."""
+    import synth
+    res = {}
+    for name in ("rmat23", "grid2048"):
+        if name == "rmat23":
+            off, col = synth.rmat_csr(23, EDGE_FACTOR)
+            srcs = [int(x) for x in synth.sources(off, 64)]
+            o1 = fg.bfs_opts(mode=fg.FG_MODE_DO, do_a=DO_A, do_b=DO_B)
+            n_single = 64
+        else:
+            off, col = synth.grid_csr(2048, 2048)
+            srcs = [int(x) for x in synth.sources(off, 64)]
+            o1 = fg.bfs_opts(mode=fg.FG_MODE_PUSH)
+            n_single = 8
+        g = fg.Graph(off, col, symmetric=True, validate=False)
+        b = fg.MsBatch(g, 64)
+        bt = []
+        for rep in range(3):
+            for lane, s in enumerate(srcs):
+                if rep:
+                    b.release(lane)
+                b.admit(lane, s)
+            e0, e1 = _ev(), _ev()
+            e0.record(stream)
+            b.step(1 << 30, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            bt.append(e0.elapsed_time(e1))
+        done, _ = b.poll()
+        b.close()
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        ws = g.workspace(fg.FG_PRIM_BFS)
+        fg.bfs_into(g, srcs[0], d, None, o1, ws=ws, stream=stream)
+        st = []
+        for s in srcs[:n_single]:
+            e0, e1 = _ev(), _ev()
+            e0.record(stream)
+            fg.bfs_into(g, s, d, None, o1, ws=ws, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st.append(e0.elapsed_time(e1))
+        ms_b = float(min(bt))
+        t1 = float(np.mean(st))
+        # 64 queries arriving together: batched, all finish at the batch end;
+        # one at a time, query i finishes after i + 1 traversals
+        fifo_lat = [t1 * (i + 1) for i in range(64)]
+        res[name] = {
+            "n": g.n, "m": int(g.m), "queries": 64, "all_done": done == (1 << 64) - 1,
+            "batched_ms": round(ms_b, 3), "batched_queries_per_s": round(64 / (ms_b * 1e-3), 1),
+            "batched_latency_ms_p50": round(ms_b, 3), "batched_latency_ms_p99": round(ms_b, 3),
+            "single_ms": round(t1, 4), "single_queries_per_s": round(1000.0 / t1, 1),
+            "single_fifo_latency_ms_p50": round(float(np.percentile(fifo_lat, 50)), 3),
+            "single_fifo_latency_ms_p99": round(float(np.percentile(fifo_lat, 99)), 3),
+            "qps_ratio": round((64 / (ms_b * 1e-3)) / (1000.0 / t1), 2),
+            "single_path": "DOBFS (autotuned thresholds)" if name == "rmat23" else "push BFS",
+        }
+        g.close()
+    return res
+
+
+def side_serving(fg, torch, cpu_graphs):
+    """C5: Poisson stream of BFS / SSSP queries over 8 resident graphs of
+    mixed size, HBM-budget admission and continuous batching, against the
+    one-at-a-time path at the same offered load."""
+    import synth
+    from paper_1504_04804_amd import serve
+    graphs, specs = {}, {}
+    for name, maker in (("rmat16", lambda: synth.rmat_csr(16, EDGE_FACTOR)),
+                        ("rmat18", lambda: synth.rmat_csr(18, EDGE_FACTOR)),
+                        ("rmat20", lambda: synth.rmat_csr(20, EDGE_FACTOR)),
+                        ("rmat22", lambda: cpu_graphs["rmat22"]),
+                        ("rmat24", lambda: cpu_graphs["rmat24"]),
+                        ("grid1024", lambda: synth.grid_csr(1024, 1024)),
+                        ("grid2048", lambda: synth.grid_csr(2048, 2048)),
+                        ("grid4096", lambda: cpu_graphs["grid4096"])):
+        off, col = maker()
+        w = synth.weights(off, col)
+        graphs[name] = fg.Graph(off, col, weights=w, symmetric=True, validate=False)
+        specs[name] = (off, True)
+    nreq, qps = 240, 400.0
+    reqs = serve.make_requests(specs, nreq, qps=qps, bfs_frac=0.8, seed=11)
+    srv = serve.Server(graphs, hbm_budget=32 << 30, k_iters=4, keep_results=False)
+    done = serve.serve_stream(srv, reqs, time_limit=300)
+    served = serve.latency_stats(done)
+    reqs2 = serve.make_requests(specs, nreq, qps=qps, bfs_frac=0.8, seed=11)
+    ws = {n: g.workspace(fg.FG_PRIM_SSSP) for n, g in graphs.items()}
+    done2 = serve.serve_fifo(graphs, reqs2, ws, time_limit=300)
+    fifo = serve.latency_stats(done2)
+    return {
+        "workload": f"{nreq} queries, Poisson {qps:.0f}/s, 80% BFS / 20% SSSP, uniform over 8 resident "
+                    "graphs (rmat16-24 ef16, grids 1024^2-4096^2, weights in [1,64]), "
+                    "HBM budget 32 GiB, 4 levels per batched step",
+        "served": {k: round(v, 3) for k, v in served.items()},
+        "fifo": {k: round(v, 3) for k, v in fifo.items()},
+        "p99_ratio_fifo_over_served": round(fifo["p99_ms"] / served["p99_ms"], 2),
+    }
 
 
 def main():
@@ -328,6 +601,22 @@ def main():
             "sample": f"serial FIFO-queue BFS (oracle) from the first {nsamp} of the {NSRC} "
                       f"R-MAT sources + the grid from vertex 0, {secs:.1f}s of CPU time",
         }
+    if not args.headline_only:
+        # per-config side measurements (outside the step)
+        del depth, parent, gdepth, gparent, ws, gws
+        out["sssp"] = side_sssp(fg, torch, off, col, srcs, stream, not args.no_cpu)
+        print(f"[bench] sssp done", file=sys.stderr, flush=True)
+        t0 = time.time()
+        off24, col24 = synth.rmat_csr(24, EDGE_FACTOR)
+        print(f"[bench] rmat24 generated in {time.time() - t0:.1f}s, m={len(col24)}",
+              file=sys.stderr, flush=True)
+        out["package"] = side_package(fg, torch, stream, not args.no_cpu, off24, col24)
+        print(f"[bench] package done", file=sys.stderr, flush=True)
+        out["batched_c4"] = side_batched(fg, torch, stream)
+        print(f"[bench] batched done", file=sys.stderr, flush=True)
+        out["serving"] = side_serving(fg, torch, {"rmat22": (off, col), "grid4096": (goff, gcol),
+                                                  "rmat24": (off24, col24)})
+        print(f"[bench] serving done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
