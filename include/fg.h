@@ -201,6 +201,12 @@ typedef struct {
   int32_t big_degree;     /* vertices of at least this degree are relaxed by
                              the whole grid (0 = default)                     */
   int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
+  uint32_t delta;         /* near-far threshold step: only vertices closer
+                             than the threshold are relaxed; it grows by delta
+                             when none is left (0 = default: 64 x mean weight
+                             / mean degree; UINT32_MAX = no threshold, plain
+                             frontier Bellman-Ford).  Results do not depend
+                             on it.                                          */
 } fg_sssp_opts;
 
 void fg_sssp_opts_default(fg_sssp_opts* opts);
@@ -208,8 +214,10 @@ void fg_sssp_opts_default(fg_sssp_opts* opts);
 /*
  * Single-source shortest paths with the graph's uint32 weights (Table I's
  * SSSP primitive; weights are non-negative integers, Sec. VII-A).  A
- * frontier traversal whose advance relaxes every out-edge of the frontier
- * (Bellman-Ford frontier form); converges when no distance improves.
+ * frontier traversal whose advance relaxes every out-edge of the frontier;
+ * the frontier holds the improved vertices closer than a threshold that
+ * grows in steps of opts->delta (near-far ordering), and the traversal
+ * converges when no distance improves.
  * dist: device uint32[n], receives the shortest-path weight from src or
  * UINT32_MAX if unreachable.  parent: device int32[n] or NULL; receives the
  * smallest-id u with an edge u->v and dist[u] + w(u,v) == dist[v]

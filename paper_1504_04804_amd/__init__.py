@@ -79,6 +79,7 @@ class SsspOpts(ctypes.Structure):
         ("small_edges", ctypes.c_int32),
         ("big_degree", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
+        ("delta", ctypes.c_uint32),
     ]
 
 
@@ -312,11 +313,15 @@ def bfs(g, src, mode=FG_MODE_DO, parents=True, opts=None, **kw):
     return depth, parent, st
 
 
-def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0):
+SSSP_NO_THRESHOLD = 0xFFFFFFFF  # delta: plain frontier Bellman-Ford
+
+
+def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0, delta=0):
     o = SsspOpts()
     lib().fg_sssp_opts_default(ctypes.byref(o))
     o.small_frontier, o.small_edges = small_frontier, small_edges
     o.big_degree, o.blocks_per_cu = big_degree, blocks_per_cu
+    o.delta = delta
     return o
 
 

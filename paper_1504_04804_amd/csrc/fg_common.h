@@ -33,6 +33,8 @@ struct fg_graph {
   int32_t symmetric = 0;
   int32_t max_degree = 0;
   int32_t nonzero_degree = 0;
+  uint64_t w_sum = 0;   // sum of the weights (0 without weights)
+  uint32_t w_max = 0;   // largest weight
   int32_t device = 0;
   int64_t resident_bytes = 0;
 };

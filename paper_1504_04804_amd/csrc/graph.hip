@@ -115,6 +115,30 @@ __global__ void degree_summary_kernel(int32_t n, int32_t nwords,
   }
 }
 
+// Sum and maximum of the edge weights (the SSSP kernel's default near-far
+// step uses the mean).
+__global__ void weight_summary_kernel(int64_t m, const uint32_t* __restrict__ w,
+                                      unsigned long long* __restrict__ sum,
+                                      uint32_t* __restrict__ mx) {
+  unsigned long long s = 0;
+  uint32_t x = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = w[i];
+    s += v;
+    x = v > x ? v : x;
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    s += __shfl_xor(s, d, 64);
+    const uint32_t o = __shfl_xor(x, d, 64);
+    x = o > x ? o : x;
+  }
+  if (fg_lane() == 0) {
+    atomicAdd(sum, s);
+    atomicMax(mx, x);
+  }
+}
+
 const char* describe(uint32_t f) {
   if (f & VAL_OFF0) return "row_offsets[0] != 0";
   if (f & VAL_LAST) return "row_offsets[n] != m";
@@ -216,7 +240,7 @@ extern "C" fg_status fg_graph_create_csr(int32_t n, int64_t m, const int32_t* ro
   int32_t* dsum = (int32_t*)((char*)aux + fg_align(nzb));  // maxdeg, nzcount, flags
   g->head = (int4*)((char*)aux + fg_align(nzb) + 256);
   g->resident_bytes += (int64_t)(fg_align(nzb) + 256 + fg_align(hb));
-  if (hipMemsetAsync(dsum, 0, 16, s) != hipSuccess) return fail(fg_set_error(FG_EDEVICE, "memset"));
+  if (hipMemsetAsync(dsum, 0, 32, s) != hipSuccess) return fail(fg_set_error(FG_EDEVICE, "memset"));
 
   if (flags & FG_VALIDATE) {
     if (dev) {
@@ -245,12 +269,20 @@ extern "C" fg_status fg_graph_create_csr(int32_t n, int64_t m, const int32_t* ro
   if (blocks < 1) blocks = 1;
   degree_summary_kernel<<<blocks, 256, 0, s>>>(n, g->nwords, g->off, g->col, g->nzmask, g->head,
                                                dsum, dsum + 1);
-  int32_t hs[2] = {0, 0};
-  if (hipMemcpyAsync(hs, dsum, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (g->w && m > 0) {
+    int wb = (int)((m + 1023) / 1024);
+    if (wb > 4096) wb = 4096;
+    weight_summary_kernel<<<wb, 256, 0, s>>>(m, g->w, (unsigned long long*)(dsum + 4),
+                                             (uint32_t*)(dsum + 6));
+  }
+  int32_t hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (hipMemcpyAsync(hs, dsum, 32, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(fg_set_error(FG_EDEVICE, "degree summary failed"));
   g->max_degree = hs[0];
   g->nonzero_degree = hs[1];
+  memcpy(&g->w_sum, &hs[4], 8);
+  g->w_max = (uint32_t)hs[6];
   *out = g;
   return FG_OK;
 }

@@ -7,10 +7,12 @@
 // frontier empties.
 //
 // Per iteration, on the device, one of two directions (as in Sec. VI-A):
-//   push: for every active vertex u and edge u->v, next[v] |= F[u] & ~visit[v]
-//         (64-bit atomicOr); a vertex whose next word was 0 joins the next
-//         active list; a finalise pass keeps only unvisited lanes, marks them
-//         visited and writes their depths.
+//   push: for every active vertex u and edge u->v, the lanes of F[u] not yet
+//         in visit[v] are claimed with a 64-bit atomicOr on visit[v]; the
+//         lanes this thread claimed get their depth and go into next[v]
+//         (atomicOr); a vertex whose next word was 0 joins the next active
+//         list.  Each active vertex clears its own current word, so one grid
+//         barrier ends a push iteration.
 //   pull: every vertex with unvisited live lanes ORs F[u] over its neighbours
 //         in CSR order and stops as soon as every wanted lane is covered;
 //         whole-word writes, no atomics.
@@ -20,7 +22,7 @@
 //           iterations (persists across steps)
 //   visit, F[0], F[1]   uint64[n]
 //   queue   2 x int32[n]        active vertices (push)
-//   desc    int2[m/CH + n + 64]
+//   desc    int4[m/CH + n + 64]  {vertex, first edge, lanes (lo, hi)}
 //   depth   int32[lanes][n]     lane-major, so each lane's result is contiguous
 //   control barrier and counters of one launch (cleared on exit)
 #include <string.h>
@@ -34,7 +36,7 @@ constexpr int PB = 1024;
 constexpr int PWAVES = PB / FG_WAVE;
 constexpr int CH = 256;
 constexpr int STAGE = 512;
-constexpr int DSTAGE = 128;
+constexpr int DSTAGE = 64;
 constexpr int MAXL = 64;
 // Pull: vertices with more than LONG_PULL unresolved entries are not scanned
 // by their own wave (the hubs of an R-MAT graph sit in the first bitmap
@@ -84,7 +86,7 @@ struct MsParams {
   ull* visit;
   ull* F[2];
   int32_t* q[2];
-  int2* desc;
+  int4* desc;
   int32_t* depth;  // [lanes][n]
   MsState* state;
   MsCtl* ctl;
@@ -99,7 +101,8 @@ struct MsParams {
 
 struct Lds {
   int32_t stage[PWAVES][STAGE];
-  int2 dstage[PWAVES][DSTAGE];
+  int4 dstage[PWAVES][DSTAGE];
+  ull w_f[PWAVES][FG_WAVE];
   int32_t w_sc[PWAVES][FG_WAVE];
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
@@ -133,31 +136,62 @@ __device__ __forceinline__ void write_depths(const MsParams& P, int32_t v, ull b
   }
 }
 
+__device__ __forceinline__ int4 make_desc(int32_t u, int32_t e0, ull f) {
+  return make_int4(u, e0, (int32_t)(uint32_t)f, (int32_t)(uint32_t)(f >> 32));
+}
+__device__ __forceinline__ ull desc_lanes(const int4& d) {
+  return (ull)(uint32_t)d.z | ((ull)(uint32_t)d.w << 32);
+}
+
+// Claim the lanes `fu` for v: the ones not yet visited get depth it1 and go
+// into next[v]; returns true when v's next word was 0 (v joins the list).
+// `got` accumulates the lanes claimed.
+__device__ __forceinline__ bool claim(const MsParams& P, ull* Fn, int32_t v, ull fu, int32_t it1,
+                                      const int32_t* start, ull& got) {
+  const ull nb = fu & ~P.visit[v];
+  if (!nb) return false;
+  const ull nw = nb & ~atomicOr(&P.visit[v], nb);
+  if (!nw) return false;
+  got |= nw;
+  ull bits = nw;
+  while (bits) {
+    const int l = __builtin_ctzll(bits);
+    bits &= bits - 1;
+    P.depth[(int64_t)l * P.n + v] = it1 - start[l];
+  }
+  return atomicOr(&Fn[v], nw) == 0ull;
+}
+
 // ---- push expansion (scan-gather for low degree, descriptors for high)
 __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int64_t qlen,
-                            ull qbase, ull dbase, Lds& L) {
+                            ull qbase, ull dbase, Lds& L, ull& got) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int32_t* Qin = P.q[S.qsel];
   int32_t* Qout = P.q[S.qsel ^ 1];
-  const ull* Fc = P.F[S.fsel];
+  ull* Fc = P.F[S.fsel];
   ull* Fn = P.F[S.fsel ^ 1];
   int32_t* sc = L.w_sc[wid];
   int32_t* su = L.w_u[wid];
   int32_t* sb = L.w_b[wid];
+  ull* sf = L.w_f[wid];
+  const int32_t it1 = S.it + 1;
   CtrSlot& C = P.ctl->slot[k & 1];
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  WaveStage<int4, DSTAGE> dst{L.dstage[wid], 0};
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
   for (int64_t base = gw * FG_WAVE; base < qlen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
     int32_t u = 0, b = 0, deg = 0;
+    ull fu = 0;
     if (i < qlen) {
       u = Qin[i];
       b = P.off[u];
       deg = P.off[u + 1] - b;
-      if (Fc[u] == 0ull) deg = 0;  // listed but without lanes
+      fu = Fc[u];
+      Fc[u] = 0ull;  // only this thread reads u's word in this iteration
+      if (fu == 0ull) deg = 0;  // listed but without lanes
     }
     const bool big = deg >= P.big_deg;
     const int32_t nd = big ? (deg + CH - 1) / CH : 0;
@@ -168,13 +202,14 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
       sc[lane] = ndi - nd;
       su[lane] = u;
       sb[lane] = b;
+      sf[lane] = fu;
       wave_lds_fence();
       for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
         const int32_t t = t0 + lane;
-        int2 dsc = make_int2(0, 0);
+        int4 dsc = make_int4(0, 0, 0, 0);
         if (t < ND) {
           const int32_t j = upper_idx(sc, FG_WAVE, t);
-          dsc = make_int2(su[j], sb[j] + (t - sc[j]) * CH);
+          dsc = make_desc(su[j], sb[j] + (t - sc[j]) * CH, sf[j]);
         }
         dst.push(t < ND, dsc, &C.desc.v, dbase, P.desc);
       }
@@ -187,6 +222,7 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
     sc[lane] = inc - d;
     su[lane] = u;
     sb[lane] = b;
+    sf[lane] = fu;
     wave_lds_fence();
     for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
       const int32_t t = t0 + lane;
@@ -195,8 +231,7 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
       if (t < T) {
         const int32_t j = upper_idx(sc, FG_WAVE, t);
         v = P.col[sb[j] + (t - sc[j])];
-        const ull nb = Fc[su[j]] & ~P.visit[v];
-        if (nb && (Fn[v] & nb) != nb) first = atomicOr(&Fn[v], nb) == 0ull;
+        first = claim(P, Fn, v, sf[j], it1, L.start, got);
       }
       st.push(first, v, &C.q.v, qbase, Qout);
     }
@@ -206,22 +241,22 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
 }
 
 __device__ void push_desc(const MsParams& P, const MsState& S, int32_t k, int64_t ndesc,
-                          ull qbase, Lds& L) {
+                          ull qbase, Lds& L, ull& got) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
   int32_t* Qout = P.q[S.qsel ^ 1];
-  const ull* Fc = P.F[S.fsel];
   ull* Fn = P.F[S.fsel ^ 1];
+  const int32_t it1 = S.it + 1;
   CtrSlot& C = P.ctl->slot[k & 1];
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
   for (int64_t i = gw; i < ndesc; i += W) {
-    const int2 dsc = P.desc[i];
+    const int4 dsc = P.desc[i];
     const int32_t u = dsc.x;
     const int32_t e_end = P.off[u + 1];
     const int32_t e1 = dsc.y + CH < e_end ? dsc.y + CH : e_end;
-    const ull fu = Fc[u];
+    const ull fu = desc_lanes(dsc);
     int32_t vv[CH / FG_WAVE];
 #pragma unroll
     for (int r = 0; r < CH / FG_WAVE; ++r) {
@@ -231,11 +266,7 @@ __device__ void push_desc(const MsParams& P, const MsState& S, int32_t k, int64_
 #pragma unroll
     for (int r = 0; r < CH / FG_WAVE; ++r) {
       const int32_t v = vv[r];
-      bool first = false;
-      if (v >= 0) {
-        const ull nb = fu & ~P.visit[v];
-        if (nb && (Fn[v] & nb) != nb) first = atomicOr(&Fn[v], nb) == 0ull;
-      }
+      const bool first = v >= 0 && claim(P, Fn, v, fu, it1, L.start, got);
       st.push(first, v, &C.q.v, qbase, Qout);
     }
   }
@@ -379,7 +410,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           const int32_t nch = (e - b - 4 + CH - 1) / CH;
           Qlong[atomicAdd(&C.q.v, 1ull) - qbp] = (int32_t)v;
           const int64_t d0 = (int64_t)(atomicAdd(&C.desc.v, (ull)nch) - dbp);
-          for (int32_t c = 0; c < nch; ++c) P.desc[d0 + c] = make_int2((int32_t)v, b + 4 + c * CH);
+          for (int32_t c = 0; c < nch; ++c) P.desc[d0 + c] = make_int4((int32_t)v, b + 4 + c * CH, 0, 0);
         }
         uint64_t pend = __ballot(want && nw != want && e - b > 32 && !lng);
         while (pend) {
@@ -431,7 +462,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         dbp = dt;
         if (nch > 0) {
           for (int64_t i = gw; i < nch; i += W) {
-            const int2 dsc = P.desc[i];
+            const int4 dsc = P.desc[i];
             const int32_t v = dsc.x;
             const ull want = S.live & ~P.visit[v];
             const ull cur = fg_uni(__hip_atomic_load(&Fn[v], __ATOMIC_RELAXED,
@@ -480,40 +511,26 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
       S.mode = 1;
     } else {
       // ---- push
-      push_expand(P, S, k, S.qlen, qbp, dbp, L);
+      ull got = 0;
+      push_expand(P, S, k, S.qlen, qbp, dbp, L, got);
+      {
+        const ull bor = block_or(got, L.redu);
+        if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
+      }
       if (!(ok = gs.sync(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - dbp);
       if (ndesc > 0) {
-        push_desc(P, S, k, ndesc, qbp, L);
+        ull got2 = 0;
+        push_desc(P, S, k, ndesc, qbp, L, got2);
+        const ull bor = block_or(got2, L.redu);
+        if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
         if (!(ok = gs.sync(&L.flag))) break;
       }
       dbp = dt;
       const ull qt = fg_atomic_load_u64(&C.q.v);
       const int64_t qn = (int64_t)(qt - qbp);
       qbp = qt;
-      // finalise: keep unvisited lanes, mark them, write depths; clear the
-      // current frontier words so the array is zero again outside the list
-      const int32_t* Qn = P.q[S.qsel ^ 1];
-      ull* Fn = P.F[S.fsel ^ 1];
-      ull lor = 0;
-      for (int64_t i = tid; i < qn; i += nth) {
-        const int32_t v = Qn[i];
-        const ull vis = P.visit[v];
-        const ull nw = Fn[v] & ~vis;
-        Fn[v] = nw;
-        if (nw) {
-          P.visit[v] = vis | nw;
-          write_depths(P, v, nw, it1);
-        }
-        lor |= nw;
-      }
-      const int32_t* Qc = P.q[S.qsel];
-      ull* Fc = P.F[S.fsel];
-      for (int64_t i = tid; i < S.qlen; i += nth) Fc[Qc[i]] = 0ull;
-      const ull bor = block_or(lor, L.redu);
-      if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
-      if (!(ok = gs.sync(&L.flag))) break;
       S.live = fg_atomic_load_u64(livew);
       S.qlen = qn;
       S.qsel ^= 1;
@@ -557,7 +574,7 @@ struct MsLayout {
   ull* visit;
   ull* F[2];
   int32_t* q[2];
-  int2* desc;
+  int4* desc;
   int32_t* depth;
   size_t bytes;
 };
@@ -572,7 +589,7 @@ MsLayout ms_layout(const fg_graph* g, int32_t lanes, void* ws) {
   L.F[1] = c.take<ull>(g->n);
   L.q[0] = c.take<int32_t>(g->n);
   L.q[1] = c.take<int32_t>(g->n);
-  L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
+  L.desc = c.take<int4>((size_t)(g->m / CH) + (size_t)g->n + 64);
   L.depth = c.take<int32_t>((size_t)lanes * (size_t)g->n);
   L.bytes = c.used;
   return L;

@@ -1,19 +1,34 @@
 // Single-source shortest paths with non-negative integer weights (Table I:
 // SSSP is a frontier traversal whose advance relaxes edges, W in O(b|E_i|)).
 //
-// Frontier Bellman-Ford on one GPU in one cooperative launch.  Each vertex
+// Frontier relaxation on one GPU in one cooperative launch.  Each vertex
 // keeps a packed 64-bit key (distance << 32 | predecessor); a relaxation is
 // one 64-bit atomicMin, so at convergence the key holds the shortest
 // distance and the smallest-id tight predecessor (every tight predecessor
-// relaxes the vertex with its final distance once, and only tight ones can
-// produce the final distance).  A vertex whose distance strictly improved
-// joins the next frontier once, through a test-and-set membership bitmap.
+// relaxes the vertex with its final distance at least once, and only tight
+// ones can produce the final distance).
+//
+// Work ordering (near-far): only vertices whose distance is below a
+// threshold T are relaxed ("near").  A vertex whose distance strictly
+// improved to d < T joins the next frontier once (test-and-set membership
+// bitmap); one improved to d >= T is appended once to the far pile
+// (test-and-set membership bitmap of its own).  When the near frontier
+// empties, T grows by delta and the pile is split: entries now below T form
+// the next frontier, entries below the old T are stale (their vertex was
+// relaxed as a near vertex since) and are dropped, the rest stay.  Every
+// vertex is relaxed after its last improvement, so distances and parents are
+// those of any other correct order; delta = UINT32_MAX never splits and
+// gives plain frontier Bellman-Ford.  A smaller delta trades iterations for
+// fewer re-relaxations (on a grid with weights in [1, 64] Bellman-Ford
+// relaxes every edge about a hundred times).
 //
 // Load balance, small-frontier mode and the barrier follow the BFS push
 // kernel.  Data layout in HBM (caller workspace, 256-B aligned):
 //   key     uint64[n]                 packed distance / predecessor
 //   inq     2 x uint32[ceil(n/32)]    membership of the next frontier
+//   infar   uint32[ceil(n/32)]        membership of the far pile
 //   queue   2 x int32[n]              input / output frontier
+//   far     2 x int32[n]              far pile (entries are unique)
 //   desc    int2[m/CH + n + 64]       edge-chunk descriptors
 //   control barrier, counters, small-frontier hand-back state
 #include <string.h>
@@ -32,6 +47,9 @@ constexpr int32_t DEF_SMALL_Q = 1024;
 constexpr int64_t DEF_SMALL_E = 4096;
 constexpr int32_t DEF_BIG_DEG = 64;
 constexpr ull KEY_INF = ~0ull;
+constexpr uint32_t DIST_INF = 0xFFFFFFFFu;
+constexpr int FSTAGE = 256;
+constexpr int64_t SMALL_FAR = 4 * PB;  // piles workgroup 0 splits alone
 
 struct CtrSlot {
   Line64 q;
@@ -50,9 +68,17 @@ struct alignas(256) SsspCtl {
   uint32_t overflow;
   uint32_t pad2[63];
   Line64 reached;
+  Line64 farc;    // appends to the far piles (monotone within a launch)
+  Line64 splitq;  // entries moved to the frontier by full-grid splits
   CtrSlot slot[2];
-  int32_t pub_k, pub_qsel, pub_force;
-  int64_t pub_qlen, pub_insp_sum;
+  // smallest distance among the entries a full-grid split keeps, in slot
+  // (split number % 3); a split clears the slot of the next one
+  uint32_t fmin[3];
+  uint32_t pad3[61];
+  int32_t pub_k, pub_qsel, pub_force, pub_fsel;
+  int64_t pub_qlen, pub_insp_sum, pub_flen;
+  ull pub_fbase;
+  uint32_t pub_T, pub_Tnext;
 };
 
 struct SsspParams {
@@ -66,9 +92,12 @@ struct SsspParams {
   int32_t* parent;
   ull* key;
   uint32_t* inq[2];
+  uint32_t* infar;
   int32_t* q[2];
+  int32_t* far[2];
   int2* desc;
   SsspCtl* ctl;
+  uint32_t delta;
   fg_run_stats* stats;
   int32_t small_q;
   int64_t small_e;
@@ -83,7 +112,19 @@ struct St {
   int64_t insp_sum;
   ull b0q, b0desc, b0insp;
   ull b1q, b1desc, b1insp;
+  uint32_t T;      // near threshold: distances below it are relaxed
+  uint32_t Tnext;  // threshold of the next split
+  int32_t fsel;    // pile holding the far entries
+  int32_t nfs;     // full-grid splits so far
+  ull fbase;       // farc value at which the current pile starts
+  int64_t flen;    // entries in the current pile
+  ull sqbase;      // splitq value after the last full-grid split
 };
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const ull s = (ull)a + (ull)b;
+  return s >= (ull)DIST_INF ? DIST_INF : (uint32_t)s;
+}
 
 struct Bases {
   ull q, desc, insp;
@@ -114,6 +155,8 @@ struct Lds {
   int32_t w_u[PWAVES][FG_WAVE];
   int32_t w_b[PWAVES][FG_WAVE];
   uint32_t w_d[PWAVES][FG_WAVE];
+  int32_t fstage[PWAVES][FSTAGE];
+  uint32_t redm[PWAVES];
   int32_t b_sc[PB];
   int32_t b_u[PB];
   int32_t b_b[PB];
@@ -123,6 +166,7 @@ struct Lds {
   int32_t newcnt;
   int32_t flag;
   int64_t bcast[8];
+  uint32_t bcast2[2];
 };
 
 __device__ __forceinline__ void trace_iter(const St& S, const SsspParams& P) {
@@ -139,24 +183,49 @@ __device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const SsspPa
   }
 }
 
-// Relax v through u with candidate distance du + wt.  Returns true when v's
-// distance strictly improved and v was not yet in the next frontier.
-__device__ __forceinline__ bool relax(int32_t v, int32_t u, uint32_t du, uint32_t wt,
-                                      uint32_t* inq_next, const SsspParams& P) {
+// Block-wide minimum (every thread of the block calls it).
+__device__ __forceinline__ uint32_t block_min(uint32_t x, uint32_t* scratch) {
+#pragma unroll
+  for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_xor(x, d, FG_WAVE);
+    x = o < x ? o : x;
+  }
+  const int wid = threadIdx.x / FG_WAVE;
+  __syncthreads();
+  if (fg_lane() == 0) scratch[wid] = x;
+  __syncthreads();
+  uint32_t m = DIST_INF;
+#pragma unroll
+  for (int i = 0; i < PWAVES; ++i) m = scratch[i] < m ? scratch[i] : m;
+  return m;
+}
+
+enum { R_NONE = 0, R_NEAR = 1, R_FAR = 2 };
+
+// Relax v through u with candidate distance du + wt.  Returns R_NEAR when
+// v's distance strictly improved to below T and v was not yet in the next
+// frontier, R_FAR when it improved to T or more and v was not yet in the far
+// pile, R_NONE otherwise.
+__device__ __forceinline__ int relax(int32_t v, int32_t u, uint32_t du, uint32_t wt, uint32_t T,
+                                     uint32_t* inq_next, const SsspParams& P) {
   const ull nd = (ull)du + (ull)wt;
   if (nd >= 0xFFFFFFFFull) {
     P.ctl->overflow = 1u;  // distance does not fit the uint32 output
-    return false;
+    return R_NONE;
   }
   const ull nk = (nd << 32) | (ull)(uint32_t)u;
   // the source keeps (0, src): with zero-weight edges a neighbour at
   // distance 0 would otherwise replace its predecessor
-  if (v == P.src || nk >= P.key[v]) return false;  // plain pre-check; keys only decrease
+  if (v == P.src || nk >= P.key[v]) return R_NONE;  // plain pre-check; keys only decrease
   const ull old = atomicMin(&P.key[v], nk);
-  if (nd >= (old >> 32)) return false;  // no distance improvement (maybe a better parent)
+  if (nd >= (old >> 32)) return R_NONE;  // no distance improvement (maybe a better parent)
   const uint32_t bit = 1u << (v & 31);
-  const uint32_t o = atomicOr(&inq_next[v >> 5], bit);
-  return !(o & bit);
+  if (nd < (ull)T) {
+    const uint32_t o = atomicOr(&inq_next[v >> 5], bit);
+    return (o & bit) ? R_NONE : R_NEAR;
+  }
+  const uint32_t o = atomicOr(&P.infar[v >> 5], bit);
+  return (o & bit) ? R_NONE : R_FAR;
 }
 
 // Full grid, phase A: 64-entry frontier chunks per wave; low-degree vertices
@@ -178,7 +247,9 @@ __device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
   WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
+  int32_t* pile = P.far[S.fsel];
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
   int64_t insp = 0;
@@ -226,18 +297,20 @@ __device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
     wave_lds_fence();
     for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
       const int32_t t = t0 + lane;
-      bool won = false;
+      int r = R_NONE;
       int32_t v = 0;
       if (t < T) {
         const int32_t j = upper_idx(sc, FG_WAVE, t);
         const int32_t e = sb[j] + (t - sc[j]);
         v = P.col[e];
-        won = relax(v, su[j], sd[j], P.w[e], inq_nxt, P);
+        r = relax(v, su[j], sd[j], P.w[e], S.T, inq_nxt, P);
       }
-      st.push(won, v, &C.q.v, B.q, Qout);
+      st.push(r == R_NEAR, v, &C.q.v, B.q, Qout);
+      fst.push(r == R_FAR, v, &P.ctl->farc.v, S.fbase, pile);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
+  fst.flush(&P.ctl->farc.v, S.fbase, pile);
   dst.flush(&C.desc.v, B.desc, P.desc);
   const int64_t tot = fg_block_sum<PB>(insp, L.red);
   if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
@@ -254,6 +327,8 @@ __device__ void phase_b(const SsspParams& P, const St& S, int64_t ndesc, Lds& L)
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
+  int32_t* pile = P.far[S.fsel];
   for (int64_t i = gw; i < ndesc; i += W) {
     const int2 dsc = P.desc[i];
     const int32_t u = dsc.x;
@@ -271,11 +346,108 @@ __device__ void phase_b(const SsspParams& P, const St& S, int64_t ndesc, Lds& L)
 #pragma unroll
     for (int r = 0; r < CH / FG_WAVE; ++r) {
       const int32_t v = vv[r];
-      const bool won = v >= 0 && relax(v, u, du, ww[r], inq_nxt, P);
-      st.push(won, v, &C.q.v, B.q, Qout);
+      const int rr = v >= 0 ? relax(v, u, du, ww[r], S.T, inq_nxt, P) : R_NONE;
+      st.push(rr == R_NEAR, v, &C.q.v, B.q, Qout);
+      fst.push(rr == R_FAR, v, &P.ctl->farc.v, S.fbase, pile);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
+  fst.flush(&P.ctl->farc.v, S.fbase, pile);
+}
+
+// Split of the far pile by the whole grid (the current frontier is empty):
+// entries with T <= dist < Tnew go to the current queue, stale ones (dist <
+// T) are dropped, the rest move to the other pile.  Their smallest distance
+// goes to fmin[nfs % 3].
+__device__ void split_full(const SsspParams& P, const St& S, uint32_t Tnew, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int32_t* pile = P.far[S.fsel];
+  int32_t* keep = P.far[S.fsel ^ 1];
+  int32_t* Q = P.q[S.qsel];
+  const ull kbase = S.fbase + (ull)S.flen;
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&P.ctl->fmin[(S.nfs + 1) % 3], DIST_INF, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t mn = DIST_INF;
+  for (int64_t base = gw * FG_WAVE; base < S.flen; base += W * FG_WAVE) {
+    const int64_t i = base + lane;
+    int r = R_NONE;
+    int32_t v = 0;
+    if (i < S.flen) {
+      v = pile[i];
+      const uint32_t d = (uint32_t)(P.key[v] >> 32);
+      if (d >= Tnew) {
+        r = R_FAR;
+        mn = d < mn ? d : mn;
+      } else {
+        atomicAnd(&P.infar[v >> 5], ~(1u << (v & 31)));
+        r = d >= S.T ? R_NEAR : R_NONE;
+      }
+    }
+    st.push(r == R_NEAR, v, &P.ctl->splitq.v, S.sqbase, Q);
+    fst.push(r == R_FAR, v, &P.ctl->farc.v, kbase, keep);
+  }
+  st.flush(&P.ctl->splitq.v, S.sqbase, Q);
+  fst.flush(&P.ctl->farc.v, kbase, keep);
+  const uint32_t bm = block_min(mn, L.redm);
+  if (threadIdx.x == 0 && bm != DIST_INF) atomicMin(&P.ctl->fmin[S.nfs % 3], bm);
+}
+
+// The same split by workgroup 0 alone (small piles, inside small mode).
+__device__ void split_small(const SsspParams& P, St& S, Lds& L) {
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  const uint32_t Tnew = S.Tnext;
+  const int32_t* pile = P.far[S.fsel];
+  int32_t* keep = P.far[S.fsel ^ 1];
+  int32_t* Q = P.q[S.qsel];
+  const ull kbase = S.fbase + (ull)S.flen;
+  if (tid == 0) L.newcnt = 0;
+  __syncthreads();
+  uint32_t mn = DIST_INF;
+  for (int64_t c0 = 0; c0 < S.flen; c0 += PB) {
+    const int64_t i = c0 + tid;
+    int r = R_NONE;
+    int32_t v = 0;
+    if (i < S.flen) {
+      v = pile[i];
+      const uint32_t d = (uint32_t)(P.key[v] >> 32);
+      if (d >= Tnew) {
+        r = R_FAR;
+        mn = d < mn ? d : mn;
+      } else {
+        atomicAnd(&P.infar[v >> 5], ~(1u << (v & 31)));
+        r = d >= S.T ? R_NEAR : R_NONE;
+      }
+    }
+    const uint64_t nm = __ballot(r == R_NEAR);
+    if (nm) {
+      int32_t pos = 0;
+      if (lane == 0) pos = atomicAdd(&L.newcnt, __popcll(nm));
+      pos = __shfl(pos, 0, FG_WAVE);
+      if (r == R_NEAR) Q[pos + fg_mbcnt(nm)] = v;
+    }
+    const uint64_t fm = __ballot(r == R_FAR);
+    if (fm) {
+      ull pos = 0;
+      if (lane == 0) pos = atomicAdd(&P.ctl->farc.v, (ull)__popcll(fm));
+      pos = __shfl(pos, 0, FG_WAVE) - kbase;
+      if (r == R_FAR) keep[pos + fg_mbcnt(fm)] = v;
+    }
+  }
+  const uint32_t bm = block_min(mn, L.redm);  // has barriers: newcnt and farc are final
+  S.qlen = L.newcnt;
+  S.fbase = kbase;
+  S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farc.v) - kbase);
+  S.fsel ^= 1;
+  S.T = Tnew;
+  S.Tnext = S.qlen > 0 ? sat_add(Tnew, P.delta) : sat_add(bm, P.delta);
+  __syncthreads();
 }
 
 // Workgroup 0 alone while the frontier is small (see the BFS kernel).
@@ -283,6 +455,14 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
   const int tid = threadIdx.x;
   *force_full = 0;
   for (;;) {
+    if (S.qlen == 0) {
+      // near frontier empty: split the pile here if it is small
+      if (S.flen == 0 || S.flen > SMALL_FAR) return;
+      split_small(P, S, L);
+      trace_iter(S, P);
+      if (S.qlen > P.small_q) return;
+      continue;
+    }
     const int32_t* Qin = P.q[S.qsel];
     int32_t* Qout = P.q[S.qsel ^ 1];
     uint32_t* inq_cur = P.inq[S.k & 1];
@@ -319,25 +499,33 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
       const int32_t cnt = (int32_t)((S.qlen - c0) < PB ? (S.qlen - c0) : PB);
       for (int32_t t0 = 0; t0 < T; t0 += PB) {
         const int32_t t = t0 + tid;
-        bool won = false;
+        int r = R_NONE;
         int32_t v = 0;
         if (t < T) {
           const int32_t j = upper_idx(L.b_sc, cnt, t);
           const int32_t e = L.b_b[j] + (t - L.b_sc[j]);
           v = P.col[e];
-          won = relax(v, L.b_u[j], L.b_d[j], P.w[e], inq_nxt, P);
+          r = relax(v, L.b_u[j], L.b_d[j], P.w[e], S.T, inq_nxt, P);
         }
-        const uint64_t mask = __ballot(won);
+        const uint64_t mask = __ballot(r == R_NEAR);
         if (mask) {
           int32_t pos = 0;
           if (fg_lane() == 0) pos = atomicAdd(&L.newcnt, __popcll(mask));
           pos = __shfl(pos, 0, FG_WAVE);
-          if (won) Qout[pos + fg_mbcnt(mask)] = v;
+          if (r == R_NEAR) Qout[pos + fg_mbcnt(mask)] = v;
+        }
+        const uint64_t fm = __ballot(r == R_FAR);
+        if (fm) {
+          ull pos = 0;
+          if (fg_lane() == 0) pos = atomicAdd(&P.ctl->farc.v, (ull)__popcll(fm));
+          pos = __shfl(pos, 0, FG_WAVE) - S.fbase;
+          if (r == R_FAR) P.far[S.fsel][pos + fg_mbcnt(fm)] = v;
         }
       }
       __syncthreads();
     }
     const int64_t nq = L.newcnt;
+    S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farc.v) - S.fbase);
     trace_insp(S.k, sum, P);
     S.insp_sum += sum;
     S.k++;
@@ -345,7 +533,7 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
     S.qlen = nq;
     trace_iter(S, P);
     __syncthreads();
-    if (nq == 0 || nq > P.small_q) return;
+    if (nq > P.small_q) return;
   }
 }
 
@@ -354,6 +542,8 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
   St S = {};
   S.qlen = 1;
+  S.T = P.delta;
+  S.Tnext = sat_add(P.delta, P.delta);
   uint32_t sm_seen = 0;
   int force_full = 0;
   bool ok = true;
@@ -369,16 +559,22 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   for (int64_t i = tid; i < P.nw32; i += nth) {
     P.inq[0][i] = 0u;
     P.inq[1][i] = 0u;
+    P.infar[i] = 0u;
   }
-  if (tid == 0) P.q[0][0] = P.src;
+  if (tid == 0) {
+    P.q[0][0] = P.src;
+    P.ctl->fmin[0] = DIST_INF;
+    P.ctl->fmin[1] = DIST_INF;
+  }
   if (!gs.sync(&L.flag)) ok = false;
   if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
     P.stats->t_start = (int64_t)wall_clock64();
     P.stats->clock_khz = P.clock_khz;
   }
   trace_iter(S, P);
-  while (ok && S.qlen > 0) {
-    if (!force_full && S.qlen <= P.small_q) {
+  while (ok && (S.qlen > 0 || S.flen > 0)) {
+    const bool small = S.qlen == 0 ? S.flen <= SMALL_FAR : (!force_full && S.qlen <= P.small_q);
+    if (small) {
       sm_seen++;
       if (blockIdx.x == 0) {
         int ff = 0;
@@ -390,6 +586,11 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
           c->pub_force = ff;
           c->pub_qlen = S.qlen;
           c->pub_insp_sum = S.insp_sum;
+          c->pub_fsel = S.fsel;
+          c->pub_flen = S.flen;
+          c->pub_fbase = S.fbase;
+          c->pub_T = S.T;
+          c->pub_Tnext = S.Tnext;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         force_full = ff;
@@ -405,6 +606,11 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
             L.bcast[2] = c->pub_force;
             L.bcast[3] = c->pub_qlen;
             L.bcast[4] = c->pub_insp_sum;
+            L.bcast[5] = c->pub_fsel;
+            L.bcast[6] = c->pub_flen;
+            L.bcast[7] = (int64_t)c->pub_fbase;
+            L.bcast2[0] = c->pub_T;
+            L.bcast2[1] = c->pub_Tnext;
           }
         }
         __syncthreads();
@@ -417,8 +623,33 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
         force_full = (int)L.bcast[2];
         S.qlen = L.bcast[3];
         S.insp_sum = L.bcast[4];
+        S.fsel = (int32_t)L.bcast[5];
+        S.flen = L.bcast[6];
+        S.fbase = (ull)L.bcast[7];
+        S.T = L.bcast2[0];
+        S.Tnext = L.bcast2[1];
         __syncthreads();
       }
+      continue;
+    }
+    if (S.qlen == 0) {
+      // full-grid split of a large pile
+      const uint32_t Tnew = S.Tnext;
+      split_full(P, S, Tnew, L);
+      if (!(ok = gs.sync(&L.flag))) break;
+      const ull sq = fg_atomic_load_u64(&P.ctl->splitq.v);
+      const ull fc = fg_atomic_load_u64(&P.ctl->farc.v);
+      const uint32_t mn = __hip_atomic_load(&P.ctl->fmin[S.nfs % 3], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      S.qlen = (int64_t)(sq - S.sqbase);
+      S.sqbase = sq;
+      S.fbase += (ull)S.flen;
+      S.flen = (int64_t)(fc - S.fbase);
+      S.fsel ^= 1;
+      S.nfs++;
+      S.T = Tnew;
+      S.Tnext = S.qlen > 0 ? sat_add(Tnew, P.delta) : sat_add(mn, P.delta);
+      trace_iter(S, P);
       continue;
     }
     force_full = 0;
@@ -435,6 +666,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
     B.desc = dt;
     const ull qt = fg_atomic_load_u64(&C.q.v);
     const ull it = fg_atomic_load_u64(&C.insp.v);
+    const ull fc = fg_atomic_load_u64(&P.ctl->farc.v);
     const int64_t nq = (int64_t)(qt - B.q);
     const int64_t insp = (int64_t)(it - B.insp);
     B.q = qt;
@@ -445,6 +677,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
     S.k++;
     S.qsel ^= 1;
     S.qlen = nq;
+    S.flen = (int64_t)(fc - S.fbase);
     trace_iter(S, P);
   }
   // unpack keys into the outputs, count reached vertices
@@ -487,7 +720,9 @@ struct SsspLayout {
   SsspCtl* ctl;
   ull* key;
   uint32_t* inq[2];
+  uint32_t* infar;
   int32_t* q[2];
+  int32_t* far[2];
   int2* desc;
   size_t bytes;
 };
@@ -500,14 +735,29 @@ SsspLayout sssp_layout(const fg_graph* g, void* ws) {
   const size_t nw32 = ((size_t)g->n + 31) / 32;
   L.inq[0] = c.take<uint32_t>(nw32);
   L.inq[1] = c.take<uint32_t>(nw32);
+  L.infar = c.take<uint32_t>(nw32);
   L.q[0] = c.take<int32_t>(g->n);
   L.q[1] = c.take<int32_t>(g->n);
+  L.far[0] = c.take<int32_t>(g->n);
+  L.far[1] = c.take<int32_t>(g->n);
   L.desc = c.take<int2>((size_t)(g->m / CH) + (size_t)g->n + 64);
   L.bytes = c.used;
   return L;
 }
 
 int g_sssp_occ[64];
+
+// Default near-far step: 64 (the wave width) times the mean edge weight over
+// the mean degree of the vertices with edges, so one step of the threshold
+// admits about a wave's worth of edges per frontier vertex; at least 1.
+uint32_t fg_sssp_default_delta(const fg_graph* g) {
+  if (g->m <= 0 || g->nonzero_degree <= 0) return 1u;
+  const double mean_w = (double)g->w_sum / (double)g->m;
+  const double mean_deg = (double)g->m / (double)g->nonzero_degree;
+  const double d = 64.0 * mean_w / mean_deg;
+  if (d >= 4294967295.0) return DIST_INF;
+  return d < 1.0 ? 1u : (uint32_t)(d + 0.5);
+}
 
 }  // namespace
 
@@ -562,8 +812,11 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   P.key = lay.key;
   P.inq[0] = lay.inq[0];
   P.inq[1] = lay.inq[1];
+  P.infar = lay.infar;
   P.q[0] = lay.q[0];
   P.q[1] = lay.q[1];
+  P.far[0] = lay.far[0];
+  P.far[1] = lay.far[1];
   P.desc = lay.desc;
   P.ctl = lay.ctl;
   P.stats = stats;
@@ -571,6 +824,7 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   if (P.small_q > PB) P.small_q = PB;
   P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
+  P.delta = o.delta > 0 ? o.delta : fg_sssp_default_delta(g);
   P.clock_khz = pr.clock_khz;
   void* args[] = {&P};
   FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)sssp_persistent, dim3(grid), dim3(PB), args,

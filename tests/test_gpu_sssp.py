@@ -41,6 +41,34 @@ def test_rmat_weighted(fg, orc, scale):
         check(fg, orc, g, off, col, w, int(s))
     check(fg, orc, g, off, col, w, 0, small_frontier=1, small_edges=1)
     check(fg, orc, g, off, col, w, 0, big_degree=2)
+    # near-far steps: tiny (many splits, large piles split by the whole
+    # grid), below and above the largest weight, and no threshold at all
+    for delta in (1, 7, 64, 500, fg.SSSP_NO_THRESHOLD):
+        check(fg, orc, g, off, col, w, 0, delta=delta)
+    check(fg, orc, g, off, col, w, 0, delta=3, small_frontier=1, small_edges=1)
+
+
+@pytest.mark.parametrize("delta", [0, 1, 33, 600, 0xFFFFFFFF])
+def test_grid_near_far(fg, orc, delta):
+    off, col = synth.grid_csr(300, 300)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    for s in (0, 300 * 150 + 150, 300 * 300 - 1):
+        st = check(fg, orc, g, off, col, w, s, delta=delta)
+        if delta == 1:
+            assert st.iterations > 500  # about one split per distance value
+
+
+def test_near_far_gaps(fg, orc):
+    # weights far above the step: each split first finds no vertex below the
+    # new threshold and jumps to the smallest distance in the pile
+    n = 50
+    off, col = synth.from_edge_pairs(n, [(i, i + 1) for i in range(n - 1)] + [(0, 25)])
+    w = np.full(len(col), 1000, np.uint32)
+    g = fg.Graph(off, col, weights=w)
+    for delta in (1, 999, 1000, 1001):
+        check(fg, orc, g, off, col, w, 0, delta=delta)
+        check(fg, orc, g, off, col, w, 0, delta=delta, small_frontier=1, small_edges=1)
 
 
 def test_closed_forms(fg, orc):
@@ -54,9 +82,10 @@ def test_closed_forms(fg, orc):
     off, col = synth.grid_csr(R, C)
     w = np.full(len(col), 7, np.uint32)
     g = fg.Graph(off, col, weights=w)
-    dist, parent, st = fg.sssp(g, 0)
-    d = to_np(dist)
-    assert d.tolist() == [7 * (r + c) for r in range(R) for c in range(C)]
+    for delta in (0, 1, 7, 50, fg.SSSP_NO_THRESHOLD):
+        dist, parent, st = fg.sssp(g, 0, delta=delta)
+        d = to_np(dist)
+        assert d.tolist() == [7 * (r + c) for r in range(R) for c in range(C)]
     check(fg, orc, g, off, col, w, R * C // 2 + 7)
 
 
