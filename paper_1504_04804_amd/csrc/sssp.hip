@@ -68,12 +68,15 @@ struct alignas(256) SsspCtl {
   uint32_t overflow;
   uint32_t pad2[63];
   Line64 reached;
-  Line64 farc;    // appends to the far piles (monotone within a launch)
-  Line64 splitq;  // entries moved to the frontier by full-grid splits
+  // Full-grid phases (near iterations and splits) are numbered ph = 0, 1, ..
+  // and count into slot ph % 3, which phase ph - 1 cleared: a slot is read
+  // after its phase's barrier and written again two barriers later, so no
+  // workgroup reads a count that the next phase is already changing.
+  Line64 farpos;    // positions in the far piles (monotone within a launch)
+  Line64 fcnt[3];   // far-pile appends of the phase
+  Line64 sqcnt[3];  // frontier entries made by a split
   CtrSlot slot[2];
-  // smallest distance among the entries a full-grid split keeps, in slot
-  // (split number % 3); a split clears the slot of the next one
-  uint32_t fmin[3];
+  uint32_t fmin[3];  // smallest distance among the entries a split keeps
   uint32_t pad3[61];
   int32_t pub_k, pub_qsel, pub_force, pub_fsel;
   int64_t pub_qlen, pub_insp_sum, pub_flen;
@@ -115,10 +118,41 @@ struct St {
   uint32_t T;      // near threshold: distances below it are relaxed
   uint32_t Tnext;  // threshold of the next split
   int32_t fsel;    // pile holding the far entries
-  int32_t nfs;     // full-grid splits so far
-  ull fbase;       // farc value at which the current pile starts
+  int32_t ph;      // full-grid phases so far
+  ull fbase;       // farpos value at which the current pile starts
   int64_t flen;    // entries in the current pile
-  ull sqbase;      // splitq value after the last full-grid split
+};
+
+// Far-pile appends staged per wave: positions come from one monotone
+// counter, and the number appended is added to the phase's count slot.
+template <int CAP>
+struct PileStage {
+  int32_t* buf;
+  int32_t cnt;
+
+  __device__ __forceinline__ void flush(ull* pos_ctr, ull* count, ull base, int32_t* out) {
+    if (cnt == 0) return;
+    wave_lds_fence();
+    ull pos = 0;
+    if (fg_lane() == 0) {
+      pos = atomicAdd(pos_ctr, (ull)cnt);
+      if (count) atomicAdd(count, (ull)cnt);
+    }
+    pos = __shfl(pos, 0, FG_WAVE) - base;
+    for (int i = fg_lane(); i < cnt; i += FG_WAVE) out[pos + i] = buf[i];
+    wave_lds_fence();
+    cnt = 0;
+  }
+
+  __device__ __forceinline__ void push(bool keep, int32_t x, ull* pos_ctr, ull* count, ull base,
+                                       int32_t* out) {
+    const uint64_t mask = __ballot(keep);
+    if (!mask) return;
+    const int32_t c = __popcll(mask);
+    if (cnt + c > CAP) flush(pos_ctr, count, base, out);
+    if (keep) buf[cnt + fg_mbcnt(mask)] = x;
+    cnt += c;
+  }
 };
 
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
@@ -181,6 +215,13 @@ __device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const SsspPa
     P.stats->inspected[k] = insp;
     P.stats->t_end[k] = (int64_t)wall_clock64();
   }
+}
+
+// Clears the count slot of the next full-grid phase.
+__device__ __forceinline__ void clear_slot(SsspCtl* c, int s) {
+  __hip_atomic_store(&c->fcnt[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&c->sqcnt[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&c->fmin[s], DIST_INF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Block-wide minimum (every thread of the block calls it).
@@ -247,9 +288,11 @@ __device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
+  PileStage<FSTAGE> fst{L.fstage[wid], 0};
   WaveStage<int2, DSTAGE> dst{L.dstage[wid], 0};
   int32_t* pile = P.far[S.fsel];
+  ull* fpos = &P.ctl->farpos.v;
+  ull* fcnt = &P.ctl->fcnt[S.ph % 3].v;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
   int64_t insp = 0;
@@ -306,11 +349,11 @@ __device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
         r = relax(v, su[j], sd[j], P.w[e], S.T, inq_nxt, P);
       }
       st.push(r == R_NEAR, v, &C.q.v, B.q, Qout);
-      fst.push(r == R_FAR, v, &P.ctl->farc.v, S.fbase, pile);
+      fst.push(r == R_FAR, v, fpos, fcnt, S.fbase, pile);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
-  fst.flush(&P.ctl->farc.v, S.fbase, pile);
+  fst.flush(fpos, fcnt, S.fbase, pile);
   dst.flush(&C.desc.v, B.desc, P.desc);
   const int64_t tot = fg_block_sum<PB>(insp, L.red);
   if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
@@ -327,8 +370,10 @@ __device__ void phase_b(const SsspParams& P, const St& S, int64_t ndesc, Lds& L)
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
+  PileStage<FSTAGE> fst{L.fstage[wid], 0};
   int32_t* pile = P.far[S.fsel];
+  ull* fpos = &P.ctl->farpos.v;
+  ull* fcnt = &P.ctl->fcnt[S.ph % 3].v;
   for (int64_t i = gw; i < ndesc; i += W) {
     const int2 dsc = P.desc[i];
     const int32_t u = dsc.x;
@@ -348,17 +393,17 @@ __device__ void phase_b(const SsspParams& P, const St& S, int64_t ndesc, Lds& L)
       const int32_t v = vv[r];
       const int rr = v >= 0 ? relax(v, u, du, ww[r], S.T, inq_nxt, P) : R_NONE;
       st.push(rr == R_NEAR, v, &C.q.v, B.q, Qout);
-      fst.push(rr == R_FAR, v, &P.ctl->farc.v, S.fbase, pile);
+      fst.push(rr == R_FAR, v, fpos, fcnt, S.fbase, pile);
     }
   }
   st.flush(&C.q.v, B.q, Qout);
-  fst.flush(&P.ctl->farc.v, S.fbase, pile);
+  fst.flush(fpos, fcnt, S.fbase, pile);
 }
 
 // Split of the far pile by the whole grid (the current frontier is empty):
 // entries with T <= dist < Tnew go to the current queue, stale ones (dist <
 // T) are dropped, the rest move to the other pile.  Their smallest distance
-// goes to fmin[nfs % 3].
+// goes to fmin[ph % 3].
 __device__ void split_full(const SsspParams& P, const St& S, uint32_t Tnew, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
@@ -367,12 +412,12 @@ __device__ void split_full(const SsspParams& P, const St& S, uint32_t Tnew, Lds&
   int32_t* Q = P.q[S.qsel];
   const ull kbase = S.fbase + (ull)S.flen;
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int32_t, FSTAGE> fst{L.fstage[wid], 0};
+  PileStage<FSTAGE> fst{L.fstage[wid], 0};
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&P.ctl->fmin[(S.nfs + 1) % 3], DIST_INF, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  ull* sq = &P.ctl->sqcnt[S.ph % 3].v;
+  ull* fpos = &P.ctl->farpos.v;
+  ull* fcnt = &P.ctl->fcnt[S.ph % 3].v;
   uint32_t mn = DIST_INF;
   for (int64_t base = gw * FG_WAVE; base < S.flen; base += W * FG_WAVE) {
     const int64_t i = base + lane;
@@ -389,13 +434,13 @@ __device__ void split_full(const SsspParams& P, const St& S, uint32_t Tnew, Lds&
         r = d >= S.T ? R_NEAR : R_NONE;
       }
     }
-    st.push(r == R_NEAR, v, &P.ctl->splitq.v, S.sqbase, Q);
-    fst.push(r == R_FAR, v, &P.ctl->farc.v, kbase, keep);
+    st.push(r == R_NEAR, v, sq, 0ull, Q);
+    fst.push(r == R_FAR, v, fpos, fcnt, kbase, keep);
   }
-  st.flush(&P.ctl->splitq.v, S.sqbase, Q);
-  fst.flush(&P.ctl->farc.v, kbase, keep);
+  st.flush(sq, 0ull, Q);
+  fst.flush(fpos, fcnt, kbase, keep);
   const uint32_t bm = block_min(mn, L.redm);
-  if (threadIdx.x == 0 && bm != DIST_INF) atomicMin(&P.ctl->fmin[S.nfs % 3], bm);
+  if (threadIdx.x == 0 && bm != DIST_INF) atomicMin(&P.ctl->fmin[S.ph % 3], bm);
 }
 
 // The same split by workgroup 0 alone (small piles, inside small mode).
@@ -435,15 +480,17 @@ __device__ void split_small(const SsspParams& P, St& S, Lds& L) {
     const uint64_t fm = __ballot(r == R_FAR);
     if (fm) {
       ull pos = 0;
-      if (lane == 0) pos = atomicAdd(&P.ctl->farc.v, (ull)__popcll(fm));
+      if (lane == 0) pos = atomicAdd(&P.ctl->farpos.v, (ull)__popcll(fm));
       pos = __shfl(pos, 0, FG_WAVE) - kbase;
       if (r == R_FAR) keep[pos + fg_mbcnt(fm)] = v;
     }
   }
-  const uint32_t bm = block_min(mn, L.redm);  // has barriers: newcnt and farc are final
+  // block_min has barriers: newcnt and farpos are final (workgroup 0 is the
+  // only one running)
+  const uint32_t bm = block_min(mn, L.redm);
   S.qlen = L.newcnt;
   S.fbase = kbase;
-  S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farc.v) - kbase);
+  S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farpos.v) - kbase);
   S.fsel ^= 1;
   S.T = Tnew;
   S.Tnext = S.qlen > 0 ? sat_add(Tnew, P.delta) : sat_add(bm, P.delta);
@@ -517,7 +564,7 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
         const uint64_t fm = __ballot(r == R_FAR);
         if (fm) {
           ull pos = 0;
-          if (fg_lane() == 0) pos = atomicAdd(&P.ctl->farc.v, (ull)__popcll(fm));
+          if (fg_lane() == 0) pos = atomicAdd(&P.ctl->farpos.v, (ull)__popcll(fm));
           pos = __shfl(pos, 0, FG_WAVE) - S.fbase;
           if (r == R_FAR) P.far[S.fsel][pos + fg_mbcnt(fm)] = v;
         }
@@ -525,7 +572,7 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
       __syncthreads();
     }
     const int64_t nq = L.newcnt;
-    S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farc.v) - S.fbase);
+    S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farpos.v) - S.fbase);
     trace_insp(S.k, sum, P);
     S.insp_sum += sum;
     S.k++;
@@ -564,7 +611,6 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   if (tid == 0) {
     P.q[0][0] = P.src;
     P.ctl->fmin[0] = DIST_INF;
-    P.ctl->fmin[1] = DIST_INF;
   }
   if (!gs.sync(&L.flag)) ok = false;
   if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
@@ -632,21 +678,22 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
       }
       continue;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) clear_slot(P.ctl, (S.ph + 1) % 3);
     if (S.qlen == 0) {
       // full-grid split of a large pile
       const uint32_t Tnew = S.Tnext;
       split_full(P, S, Tnew, L);
       if (!(ok = gs.sync(&L.flag))) break;
-      const ull sq = fg_atomic_load_u64(&P.ctl->splitq.v);
-      const ull fc = fg_atomic_load_u64(&P.ctl->farc.v);
-      const uint32_t mn = __hip_atomic_load(&P.ctl->fmin[S.nfs % 3], __ATOMIC_RELAXED,
+      const int sl = S.ph % 3;
+      const ull sq = fg_atomic_load_u64(&P.ctl->sqcnt[sl].v);
+      const ull fc = fg_atomic_load_u64(&P.ctl->fcnt[sl].v);
+      const uint32_t mn = __hip_atomic_load(&P.ctl->fmin[sl], __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
-      S.qlen = (int64_t)(sq - S.sqbase);
-      S.sqbase = sq;
+      S.qlen = (int64_t)sq;
       S.fbase += (ull)S.flen;
-      S.flen = (int64_t)(fc - S.fbase);
+      S.flen = (int64_t)fc;
       S.fsel ^= 1;
-      S.nfs++;
+      S.ph++;
       S.T = Tnew;
       S.Tnext = S.qlen > 0 ? sat_add(Tnew, P.delta) : sat_add(mn, P.delta);
       trace_iter(S, P);
@@ -666,7 +713,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
     B.desc = dt;
     const ull qt = fg_atomic_load_u64(&C.q.v);
     const ull it = fg_atomic_load_u64(&C.insp.v);
-    const ull fc = fg_atomic_load_u64(&P.ctl->farc.v);
+    const ull fc = fg_atomic_load_u64(&P.ctl->fcnt[S.ph % 3].v);
     const int64_t nq = (int64_t)(qt - B.q);
     const int64_t insp = (int64_t)(it - B.insp);
     B.q = qt;
@@ -677,7 +724,8 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
     S.k++;
     S.qsel ^= 1;
     S.qlen = nq;
-    S.flen = (int64_t)(fc - S.fbase);
+    S.flen += (int64_t)fc;
+    S.ph++;
     trace_iter(S, P);
   }
   // unpack keys into the outputs, count reached vertices
