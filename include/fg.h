@@ -112,6 +112,7 @@ fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets, const int
 #define FG_PRIM_BFS_UNFUSED 1  /* fg_bfs, mode FG_MODE_PUSH_UNFUSED           */
 #define FG_PRIM_SSSP 2         /* fg_sssp                                      */
 #define FG_PRIM_MSBFS 3        /* fg_msbfs_* with `lanes` <= 64                */
+#define FG_PRIM_MSSSP 4        /* fg_mssp_* (any `lanes` <= 64)                */
 
 /*
  * Bytes of device workspace a call needs (just-enough sizing, Sec. VI-B:
@@ -336,6 +337,71 @@ fg_status fg_msbfs_read(fg_msbfs* b, int32_t lane, int32_t* depth, void* stream)
 
 /* Forget the query held by `lane` (it no longer reports as done). */
 fg_status fg_msbfs_release(fg_msbfs* b, int32_t lane);
+
+/* ----------------------------------------------------- batched SSSP (64 lanes) */
+
+typedef struct fg_mssp fg_mssp;
+
+typedef struct {
+  uint32_t delta;        /* near-far threshold step of every lane (0 = the
+                            fg_sssp default, UINT32_MAX = no threshold)      */
+  int32_t big_degree;    /* vertices of at least this degree are relaxed in
+                            64-edge chunks by many waves (0 = 256)           */
+  int32_t blocks_per_cu; /* persistent launch width (0 = default)            */
+  int32_t dense_lanes;   /* a vertex with at least this many frontier lanes is
+                            relaxed by one wave across its lanes; fewer lanes
+                            are relaxed one (edge, lane) pair per thread
+                            (0 = 16)                                         */
+} fg_mssp_opts;
+
+void fg_mssp_opts_default(fg_mssp_opts* opts);
+
+/*
+ * A batch of up to 64 independent SSSP queries (lanes) over the graph's
+ * uint32 weights (Table I's SSSP, one query per source) sharing one
+ * traversal: each iteration relaxes, for every vertex in some lane's near
+ * frontier, its edges for all of those lanes at once, and each lane orders
+ * its work near-far with its own threshold (see fg_sssp).  Each lane's
+ * distances equal fg_sssp's distances from its source (no parents).  Lanes
+ * are admitted at any step boundary (continuous batching) and are done when
+ * their near frontier and far pile are empty.  ws: device workspace of
+ * fg_workspace_bytes(g, FG_PRIM_MSSSP, 64) bytes (distances for 64 lanes:
+ * 256 bytes per vertex), owned by the caller, used exclusively by this batch
+ * until fg_mssp_close.  fg_mssp_open clears the batch state (asynchronously
+ * on `stream`).  Errors: FG_EINVAL (no weights, lanes outside [1, 64], NULL
+ * arguments), FG_ENOMEM (workspace too small).
+ */
+fg_status fg_mssp_open(const fg_graph* g, int32_t lanes, void* ws, size_t ws_bytes,
+                       const fg_mssp_opts* opts, void* stream, fg_mssp** out);
+fg_status fg_mssp_close(fg_mssp* b);
+
+/* Queue query `src` for lane `lane`; it starts at the next fg_mssp_step.
+ * The lane's previous result is discarded.  FG_EINVAL for a bad lane / src
+ * or a lane already pending. */
+fg_status fg_mssp_admit(fg_mssp* b, int32_t lane, int32_t src);
+
+/* Run at most k_iters iterations for every live lane (fewer if all lanes
+ * finish), asynchronously on `stream`. */
+fg_status fg_mssp_step(fg_mssp* b, int32_t k_iters, void* stream);
+
+/* Synchronise `stream`; *done_lanes = admitted lanes whose query has
+ * finished; *iterations = iterations run since fg_mssp_open.  Either pointer
+ * may be NULL.  Returns FG_EOVERFLOW once a distance would reach 2^32 - 1
+ * (the affected lane's result is then incomplete), FG_EDEVICE if a step
+ * stopped early. */
+fg_status fg_mssp_poll(fg_mssp* b, uint64_t* done_lanes, int32_t* iterations, void* stream);
+
+/* Synchronise `stream`; work done since fg_mssp_open: *edges = edge visits
+ * (an edge relaxed for all of a vertex's lanes counts once), *edge_lanes =
+ * relaxations attempted (per lane).  Either pointer may be NULL. */
+fg_status fg_mssp_counts(fg_mssp* b, uint64_t* edges, uint64_t* edge_lanes, void* stream);
+
+/* Copy lane's distances (uint32[n], UINT32_MAX = unreachable) to device
+ * memory `dist` (asynchronous on `stream`). */
+fg_status fg_mssp_read(fg_mssp* b, int32_t lane, uint32_t* dist, void* stream);
+
+/* Forget the query held by `lane` (it no longer reports as done). */
+fg_status fg_mssp_release(fg_mssp* b, int32_t lane);
 
 /* ----------------------------------------------------- partition + package */
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libfg.so")
 
 FG_OK, FG_EINVAL, FG_ENOMEM, FG_EDEVICE, FG_EOVERFLOW, FG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FG_DEVICE_PTRS, FG_BORROW, FG_VALIDATE, FG_SYMMETRIC = 1, 2, 4, 8
-FG_PRIM_BFS, FG_PRIM_BFS_UNFUSED, FG_PRIM_SSSP, FG_PRIM_MSBFS = 0, 1, 2, 3
+FG_PRIM_BFS, FG_PRIM_BFS_UNFUSED, FG_PRIM_SSSP, FG_PRIM_MSBFS, FG_PRIM_MSSSP = 0, 1, 2, 3, 4
 FG_MODE_DO, FG_MODE_PUSH, FG_MODE_PUSH_UNFUSED = 0, 1, 2
 FG_TRACE_MAX = 64
 PUSH, PULL = 0, 1
@@ -92,6 +92,15 @@ class MsOpts(ctypes.Structure):
     ]
 
 
+class MpOpts(ctypes.Structure):
+    _fields_ = [
+        ("delta", ctypes.c_uint32),
+        ("big_degree", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+        ("dense_lanes", ctypes.c_int32),
+    ]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -154,6 +163,15 @@ SIGNATURES = {
     "fg_msbfs_poll": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I32), _P]),
     "fg_msbfs_read": (_I32, [_P, _I32, _P, _P]),
     "fg_msbfs_release": (_I32, [_P, _I32]),
+    "fg_mssp_opts_default": (None, [ctypes.POINTER(MpOpts)]),
+    "fg_mssp_open": (_I32, [_P, _I32, _P, _SZ, ctypes.POINTER(MpOpts), _P, ctypes.POINTER(_P)]),
+    "fg_mssp_close": (_I32, [_P]),
+    "fg_mssp_admit": (_I32, [_P, _I32, _I32]),
+    "fg_mssp_step": (_I32, [_P, _I32, _P]),
+    "fg_mssp_poll": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I32), _P]),
+    "fg_mssp_counts": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), _P]),
+    "fg_mssp_read": (_I32, [_P, _I32, _P, _P]),
+    "fg_mssp_release": (_I32, [_P, _I32]),
     "fg_graph_csr": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "fg_share_create": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I32, _P, ctypes.POINTER(_P)]),
     "fg_share_destroy": (_I32, [_P]),
@@ -534,6 +552,82 @@ class MsBatch:
     def close(self):
         if getattr(self, "handle", None):
             lib().fg_msbfs_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mssp_opts(delta=0, big_degree=0, blocks_per_cu=0, dense_lanes=0):
+    o = MpOpts()
+    lib().fg_mssp_opts_default(ctypes.byref(o))
+    o.delta, o.big_degree, o.blocks_per_cu = delta, big_degree, blocks_per_cu
+    o.dense_lanes = dense_lanes
+    return o
+
+
+class MsspBatch:
+    """Up to 64 SSSP queries sharing one traversal (fg_mssp_*)."""
+
+    def __init__(self, g, lanes=64, opts=None, stream=None):
+        self.g = g
+        self.lanes = lanes
+        nb = g.workspace_bytes(FG_PRIM_MSSSP, lanes)
+        self.ws = torch.zeros(max(nb, 256), dtype=torch.uint8, device=g.off.device)
+        h = ctypes.c_void_p()
+        o = opts if opts is not None else mssp_opts()
+        _check(lib().fg_mssp_open(g.handle, lanes, _ptr(self.ws), self.ws.numel(),
+                                  ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.admitted = 0
+
+    def admit(self, lane, src):
+        _check(lib().fg_mssp_admit(self.handle, int(lane), int(src)))
+        self.admitted |= 1 << int(lane)
+
+    def step(self, k_iters, stream=None):
+        _check(lib().fg_mssp_step(self.handle, int(k_iters), _stream(stream)))
+
+    def poll(self, stream=None):
+        done = ctypes.c_uint64()
+        it = ctypes.c_int32()
+        _check(lib().fg_mssp_poll(self.handle, ctypes.byref(done), ctypes.byref(it),
+                                  _stream(stream)))
+        return int(done.value), int(it.value)
+
+    def counts(self, stream=None):
+        e = ctypes.c_uint64()
+        el = ctypes.c_uint64()
+        _check(lib().fg_mssp_counts(self.handle, ctypes.byref(e), ctypes.byref(el),
+                                    _stream(stream)))
+        return int(e.value), int(el.value)
+
+    def read(self, lane, out=None, stream=None):
+        """Lane's distances as an int32 tensor holding the uint32 bits."""
+        out = out if out is not None else torch.empty(self.g.n, dtype=torch.int32,
+                                                      device=self.g.off.device)
+        _check(lib().fg_mssp_read(self.handle, int(lane), _ptr(out), _stream(stream)))
+        return out
+
+    def release(self, lane):
+        _check(lib().fg_mssp_release(self.handle, int(lane)))
+        self.admitted &= ~(1 << int(lane))
+
+    def run(self, k_iters=64, max_steps=1 << 20):
+        """Step until every admitted lane is done; returns the done mask."""
+        for _ in range(max_steps):
+            self.step(k_iters)
+            done, _ = self.poll()
+            if done & self.admitted == self.admitted:
+                return done
+        raise RuntimeError("batched SSSP did not finish")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fg_mssp_close(self.handle)
             self.handle = None
 
     def __del__(self):

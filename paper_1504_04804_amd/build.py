@@ -8,7 +8,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfg.so")
 
-SOURCES = ["abi.cpp", "graph.hip", "bfs.hip", "ops.hip", "sssp.hip", "package.hip", "msbfs.hip"]
+SOURCES = ["abi.cpp", "graph.hip", "bfs.hip", "ops.hip", "sssp.hip", "package.hip", "msbfs.hip",
+           "mssp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

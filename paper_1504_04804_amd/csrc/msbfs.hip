@@ -587,8 +587,10 @@ MsLayout ms_layout(const fg_graph* g, int32_t lanes, void* ws) {
   L.visit = c.take<ull>(g->n);
   L.F[0] = c.take<ull>(g->n);
   L.F[1] = c.take<ull>(g->n);
-  L.q[0] = c.take<int32_t>(g->n);
-  L.q[1] = c.take<int32_t>(g->n);
+  // + 64: admissions list their sources even when a reused lane's cleared
+  // bits leave listed vertices without lanes
+  L.q[0] = c.take<int32_t>((size_t)g->n + MAXL);
+  L.q[1] = c.take<int32_t>((size_t)g->n + MAXL);
   L.desc = c.take<int4>((size_t)(g->m / CH) + (size_t)g->n + 64);
   L.depth = c.take<int32_t>((size_t)lanes * (size_t)g->n);
   L.bytes = c.used;

@@ -340,6 +340,9 @@ extern "C" size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32
     case FG_PRIM_MSBFS:
       if (lanes < 1 || lanes > 64) return 0;
       return fg_msbfs_workspace_bytes(g, lanes);
+    case FG_PRIM_MSSSP:
+      if (lanes < 1 || lanes > 64) return 0;
+      return fg_mssp_workspace_bytes(g);
     default: return 0;
   }
 }
