@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-sources", type=int, default=8)
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the per-config side measurements (SSSP, package, batched, serving)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving sweep (the other side measurements still run)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 512 MiB device copy three times (for the "
                          "rocprof FETCH_SIZE / WRITE_SIZE scale factor)")
@@ -357,13 +359,73 @@ def side_batched(fg, torch, stream):
     return res
 
 
-def side_serving(fg, torch, cpu_graphs):
-    """C5: Poisson stream of BFS / SSSP queries over 8 resident graphs of
-    mixed size, HBM-budget admission and continuous batching, against the
-    one-at-a-time path at the same offered load."""
+def side_batched_sssp(fg, torch, stream, rmat22):
+    """64 SSSP queries per launch (fg_mssp_*) on R-MAT 22 and a 2048 x 2048
+    grid (weights in [1, 64]) against fg_sssp one source at a time."""
     import synth
-    from paper_1504_04804_amd import serve
-    graphs, specs = {}, {}
+    res = {}
+    for name in ("rmat22", "grid2048"):
+        off, col = rmat22 if name == "rmat22" else synth.grid_csr(2048, 2048)
+        w = synth.weights(off, col)
+        g = fg.Graph(off, col, weights=w, symmetric=True, validate=False)
+        srcs = [int(x) for x in synth.sources(off, 64, seed=31)]
+        b = fg.MsspBatch(g, 64, stream=stream)
+        bt, byts = [], []
+        for rep in range(2):
+            for lane, s_ in enumerate(srcs):
+                if rep:
+                    b.release(lane)
+                b.admit(lane, s_)
+            e_0, el_0 = b.counts(stream=stream)
+            e0, e1 = _ev(), _ev()
+            e0.record(stream)
+            b.step(1 << 30, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            bt.append(e0.elapsed_time(e1))
+            e_1, el_1 = b.counts(stream=stream)
+            # per edge visit: column + weight; per (edge, lane): distance read
+            # + atomic; per (vertex, lane) relaxed: its own distance (in el)
+            byts.append(8.0 * (e_1 - e_0) + 8.0 * (el_1 - el_0))
+        done, _ = b.poll(stream=stream)
+        b.close()
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        ws = g.workspace(fg.FG_PRIM_SSSP)
+        fg.sssp_into(g, srcs[0], d, None, ws=ws, stream=stream)
+        st = []
+        for s_ in srcs[:8]:
+            e0, e1 = _ev(), _ev()
+            e0.record(stream)
+            fg.sssp_into(g, s_, d, None, ws=ws, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st.append(e0.elapsed_time(e1))
+        ms_b = float(min(bt))
+        t1 = float(np.mean(st))
+        gbs = byts[int(np.argmin(bt))] / (ms_b * 1e-3) / 1e9
+        res[name] = {
+            "n": g.n, "m": int(g.m), "queries": 64, "all_done": done == (1 << 64) - 1,
+            "batched_ms": round(ms_b, 3), "batched_queries_per_s": round(64 / (ms_b * 1e-3), 1),
+            "single_ms": round(t1, 3), "single_queries_per_s": round(1000.0 / t1, 1),
+            "qps_ratio": round((64 / (ms_b * 1e-3)) / (1000.0 / t1), 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                         "note": "8 B per edge visit + 8 B per (edge, lane) relaxation"},
+        }
+        g.close()
+    return res
+
+
+SERVE_QPS = (25, 50, 75, 100, 150, 200, 300, 400)
+SERVE_NREQ = 200
+SERVE_BUDGET = 16 << 30
+SERVE_P99_TARGETS_MS = (250, 500, 1000)
+
+
+def serving_graphs(fg, cpu_graphs):
+    """The 8 resident graphs of the serving workload, with weights."""
+    import synth
+    graphs, specs, srcs = {}, {}, {}
     for name, maker in (("rmat16", lambda: synth.rmat_csr(16, EDGE_FACTOR)),
                         ("rmat18", lambda: synth.rmat_csr(18, EDGE_FACTOR)),
                         ("rmat20", lambda: synth.rmat_csr(20, EDGE_FACTOR)),
@@ -376,22 +438,67 @@ def side_serving(fg, torch, cpu_graphs):
         w = synth.weights(off, col)
         graphs[name] = fg.Graph(off, col, weights=w, symmetric=True, validate=False)
         specs[name] = (off, True)
-    nreq, qps = 240, 400.0
-    reqs = serve.make_requests(specs, nreq, qps=qps, bfs_frac=0.8, seed=11)
-    srv = serve.Server(graphs, hbm_budget=32 << 30, k_iters=4, keep_results=False)
-    done = serve.serve_stream(srv, reqs, time_limit=300)
-    served = serve.latency_stats(done)
-    reqs2 = serve.make_requests(specs, nreq, qps=qps, bfs_frac=0.8, seed=11)
-    ws = {n: g.workspace(fg.FG_PRIM_SSSP) for n, g in graphs.items()}
-    done2 = serve.serve_fifo(graphs, reqs2, ws, time_limit=300)
-    fifo = serve.latency_stats(done2)
+        srcs[name] = synth.sources(off, 8, seed=77)
+    return graphs, specs, srcs
+
+
+def max_qps_at(sweep, path, target):
+    ok = [row["qps_offered"] for row in sweep if row[path]["p99_ms"] <= target]
+    return max(ok) if ok else None
+
+
+def side_serving(fg, torch, cpu_graphs):
+    """C5: Poisson streams of BFS / SSSP queries over 8 resident graphs of
+    mixed size at a sweep of offered loads, served with HBM-budget admission
+    and continuous batching, against the one-at-a-time path at the same
+    offered load; the highest swept load each sustains under a p99 target."""
+    from paper_1504_04804_amd import serve
+    graphs, specs, srcs = serving_graphs(fg, cpu_graphs)
+    t0 = time.time()
+    costs = serve.calibrate(graphs, srcs)
+    cal_s = time.time() - t0
+    print(f"[bench] serving cost model calibrated in {cal_s:.1f}s", file=sys.stderr, flush=True)
+    bfs_ws = {n: g.workspace(fg.FG_PRIM_BFS) for n, g in graphs.items()}
+    sssp_ws = {n: g.workspace(fg.FG_PRIM_SSSP) for n, g in graphs.items()}
+    sweep = []
+    for qps in SERVE_QPS:
+        reqs = serve.make_requests(specs, SERVE_NREQ, qps=float(qps), bfs_frac=0.8, seed=11)
+        srv = serve.Server(graphs, hbm_budget=SERVE_BUDGET, policy="auto", costs=costs,
+                           keep_results=False)
+        done = serve.serve_stream(srv, reqs, time_limit=300)
+        served = serve.latency_stats(done)
+        nb = sum(1 for r in done if r.path == "batch")
+        reqs2 = serve.make_requests(specs, SERVE_NREQ, qps=float(qps), bfs_frac=0.8, seed=11)
+        done2 = serve.serve_fifo(graphs, reqs2, sssp_ws, bfs_ws=bfs_ws, time_limit=300)
+        fifo = serve.latency_stats(done2)
+        row = {"qps_offered": qps,
+               "served": {k: round(v, 3) for k, v in served.items()},
+               "fifo": {k: round(v, 3) for k, v in fifo.items()},
+               "served_batched_frac": round(nb / len(done), 3),
+               "served_steps": srv.counts["steps"], "served_singles": srv.counts["singles"],
+               "served_evictions": srv.counts["evictions"]}
+        sweep.append(row)
+        print(f"[bench] serving qps={qps}: served p50={served['p50_ms']:.1f} p99={served['p99_ms']:.1f} "
+              f"qps={served['qps']:.1f} | fifo p50={fifo['p50_ms']:.1f} p99={fifo['p99_ms']:.1f} "
+              f"qps={fifo['qps']:.1f}", file=sys.stderr, flush=True)
+        del srv
+    at = {}
+    for tgt in SERVE_P99_TARGETS_MS:
+        s_q, f_q = max_qps_at(sweep, "served", tgt), max_qps_at(sweep, "fifo", tgt)
+        at[f"p99<={tgt}ms"] = {"served_qps": s_q, "fifo_qps": f_q,
+                               "ratio": round(s_q / f_q, 2) if s_q and f_q else None}
     return {
-        "workload": f"{nreq} queries, Poisson {qps:.0f}/s, 80% BFS / 20% SSSP, uniform over 8 resident "
-                    "graphs (rmat16-24 ef16, grids 1024^2-4096^2, weights in [1,64]), "
-                    "HBM budget 32 GiB, 4 levels per batched step",
-        "served": {k: round(v, 3) for k, v in served.items()},
-        "fifo": {k: round(v, 3) for k, v in fifo.items()},
-        "p99_ratio_fifo_over_served": round(fifo["p99_ms"] / served["p99_ms"], 2),
+        "workload": f"{SERVE_NREQ} queries per load, Poisson arrivals, 80% BFS / 20% SSSP, uniform "
+                    "over 8 resident graphs (rmat16/18/20/22/24 ef16, grids 1024^2/2048^2/4096^2, "
+                    f"weights in [1,64]), HBM budget {SERVE_BUDGET >> 30} GiB for workspaces",
+        "policy": "64-lane BFS and SSSP batches per graph with continuous admission; a cost "
+                  "model (single run vs 1- and 8-lane batches, measured per graph and kind) "
+                  "picks batch or single run when a batch is idle; oldest request first",
+        "calibration_s": round(cal_s, 1),
+        "cost_model_ms": {f"{n}/{'bfs' if k == serve.BFS else 'sssp'}": c.as_dict()
+                          for (n, k), c in costs.items()},
+        "sweep": sweep,
+        "max_offered_qps_at_p99": at,
     }
 
 
@@ -614,9 +721,13 @@ def main():
         print(f"[bench] package done", file=sys.stderr, flush=True)
         out["batched_c4"] = side_batched(fg, torch, stream)
         print(f"[bench] batched done", file=sys.stderr, flush=True)
-        out["serving"] = side_serving(fg, torch, {"rmat22": (off, col), "grid4096": (goff, gcol),
-                                                  "rmat24": (off24, col24)})
-        print(f"[bench] serving done", file=sys.stderr, flush=True)
+        out["batched_sssp"] = side_batched_sssp(fg, torch, stream, (off, col))
+        print(f"[bench] batched sssp done", file=sys.stderr, flush=True)
+        if not args.no_serving:
+            out["serving"] = side_serving(fg, torch, {"rmat22": (off, col),
+                                                      "grid4096": (goff, gcol),
+                                                      "rmat24": (off24, col24)})
+            print(f"[bench] serving done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

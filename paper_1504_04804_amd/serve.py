@@ -1,17 +1,22 @@
 """Query server: continuous batching of BFS / SSSP queries over resident graphs.
 
-Requests (graph, kind, source) arrive over time.  BFS requests are admitted
-into free lanes of a 64-lane batched traversal of their graph (fg_msbfs_*)
-at step boundaries, so queries that arrive while others run join the same
-device launches; a lane retires as soon as its frontier empties and its
-depths are copied out.  SSSP requests run as single-query launches between
-batched steps.  Memory for batches and SSSP workspaces is admitted against an
-explicit HBM budget: a request waits while its graph's batch or an SSSP
-workspace does not fit.
+Requests (graph, kind, source) arrive over time.  Per graph and kind the
+server keeps a 64-lane batch (fg_msbfs_* for BFS, fg_mssp_* for SSSP):
+requests are admitted into free lanes at step boundaries, so queries that
+arrive while others run join the same device launches, and a lane retires
+as soon as its query is done and its result is copied out.  A batch over a
+few lanes costs more device time than one single-source run (fg_bfs /
+fg_sssp) but far less than many, so when a batch is idle a cost model
+measured per graph and kind decides whether the waiting requests start a
+batch or the oldest one runs alone.  Batch and single-run workspaces are
+admitted against an explicit HBM budget: idle batches are closed, least
+recently used first, to make room, and requests wait while nothing fits.
 
-All device work is issued on one stream: every traversal is a cooperative
-persistent launch that expects the whole device, so two of them must not
-run concurrently; the overlap between queries comes from sharing launches.
+The device runs one traversal at a time (each is a cooperative persistent
+launch over the whole device).  The next unit of work -- a step of a running
+batch, the start of a batch, or a single run -- is the one holding the
+oldest request, and steps are sized from the measured time per iteration so
+the device changes hands every few milliseconds.
 """
 import collections
 import time
@@ -22,138 +27,286 @@ import torch
 import paper_1504_04804_amd as fg
 
 BFS, SSSP = 0, 1
+LANES = 64
 
 
 class Request:
-    __slots__ = ("rid", "graph", "kind", "src", "arrival", "start", "done", "result")
+    __slots__ = ("rid", "graph", "kind", "src", "arrival", "start", "done", "result", "path")
 
     def __init__(self, rid, graph, kind, src, arrival):
         self.rid, self.graph, self.kind, self.src, self.arrival = rid, graph, kind, src, arrival
         self.start = None
         self.done = None
         self.result = None
+        self.path = None  # "batch" or "single" once served
 
 
-class _GraphSlot:
-    def __init__(self, name, g):
-        self.name = name
-        self.g = g
-        self.batch = None          # fg.MsBatch, allocated on first BFS request
-        self.lane_req = {}         # lane -> Request
-        self.free = list(range(63, -1, -1))
-        self.sssp_ws = None
+class Cost:
+    """Device time of one graph and kind, in ms: `single` per single-source
+    run; a batch of L lanes run to the end takes batch(L), linear between
+    the measured 1-lane and 8-lane batches; `it_ms` per batched iteration."""
+
+    def __init__(self, single, batch1, batch8, it_ms):
+        self.single, self.batch1, self.batch8, self.it_ms = single, batch1, batch8, it_ms
+
+    def batch(self, lanes):
+        return self.batch1 + (self.batch8 - self.batch1) * (lanes - 1) / 7.0
+
+    def prefer_batch(self, lanes):
+        return lanes > 1 and self.batch(lanes) < lanes * self.single
+
+    def as_dict(self):
+        return dict(single_ms=round(self.single, 3), batch1_ms=round(self.batch1, 3),
+                    batch8_ms=round(self.batch8, 3), it_ms=round(self.it_ms, 4))
+
+
+class _Kind:
+    """State of one (graph, kind): waiting requests, the batch and its lanes."""
+
+    def __init__(self, name, g, kind):
+        self.name, self.g, self.kind = name, g, kind
+        self.waiting = collections.deque()
+        self.batch = None
+        self.batch_bytes = 0
+        self.lane_req = {}
+        self.free = list(range(LANES - 1, -1, -1))
+        self.single_ws = None
+        self.single_bytes = 0
+        self.cost = None
+        self.it_ms = None  # running estimate of the batch's time per iteration
+        self.it_seen = 0   # the batch's iteration count after its last step
+        self.last_used = 0.0
+
+    def oldest(self):
+        t = self.waiting[0].arrival if self.waiting else float("inf")
+        for r in self.lane_req.values():
+            t = min(t, r.arrival)
+        return t
+
+    def prim(self):
+        return fg.FG_PRIM_MSBFS if self.kind == BFS else fg.FG_PRIM_MSSSP
+
+    def open_batch(self):
+        return fg.MsBatch(self.g, LANES) if self.kind == BFS else fg.MsspBatch(self.g, LANES)
 
 
 class Server:
     """Continuous-batching query server over resident graphs.
 
-    graphs: dict name -> fg.Graph (SSSP needs weights).  hbm_budget: bytes the
-    server may allocate for batch workspaces, SSSP workspaces and results.
-    k_iters: BFS levels per batched step (the admission granularity).
+    graphs: dict name -> fg.Graph (SSSP needs weights).  hbm_budget: bytes
+    the server may hold in workspaces.  policy: "auto" (the cost model picks
+    batch or single when a batch is idle), "batch" (always batch) or
+    "single" (always single runs, oldest first).  costs: dict (name, kind) ->
+    Cost, e.g. from calibrate(); missing entries default to batching.
+    step_ms: target device time of one batched step.
     """
 
-    def __init__(self, graphs, hbm_budget=32 << 30, k_iters=4, keep_results=True):
-        self.slots = {name: _GraphSlot(name, g) for name, g in graphs.items()}
+    def __init__(self, graphs, hbm_budget=32 << 30, policy="auto", costs=None, step_ms=4.0,
+                 keep_results=True, stream=None):
+        self.kinds = {}
+        for name, g in graphs.items():
+            self.kinds[(name, BFS)] = _Kind(name, g, BFS)
+            if g.w is not None:
+                self.kinds[(name, SSSP)] = _Kind(name, g, SSSP)
+        for key, c in (costs or {}).items():
+            if key in self.kinds:
+                self.kinds[key].cost = c
         self.budget = int(hbm_budget)
         self.used = 0
-        self.k_iters = k_iters
+        self.policy = policy
+        self.step_ms = float(step_ms)
         self.keep = keep_results
-        self.pending = collections.deque()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.finished = []
-        self.stream = torch.cuda.current_stream()
+        self.counts = collections.Counter()
+        self.bfs_opts = fg.bfs_opts(mode=fg.FG_MODE_DO)
 
     # ---------------------------------------------------------- memory
-    def _reserve(self, nbytes):
-        if self.used + nbytes > self.budget:
-            return False
-        self.used += nbytes
+    def _reserve(self, nbytes, keep=None):
+        """Reserve nbytes, closing idle batches (least recently used first)."""
+        if self.used + nbytes <= self.budget:
+            self.used += nbytes
+            return True
+        idle = sorted((k for k in self.kinds.values()
+                       if k.batch is not None and not k.lane_req and k is not keep),
+                      key=lambda k: k.last_used)
+        for k in idle:
+            self._close_batch(k)
+            self.counts["evictions"] += 1
+            if self.used + nbytes <= self.budget:
+                self.used += nbytes
+                return True
+        return False
+
+    def _close_batch(self, k):
+        k.batch.close()
+        k.batch = None
+        self.used -= k.batch_bytes
+        k.batch_bytes = 0
+        k.free = list(range(LANES - 1, -1, -1))
+
+    def _ensure_batch(self, k):
+        if k.batch is None:
+            nb = k.g.workspace_bytes(k.prim(), LANES)
+            if not self._reserve(nb, keep=k):
+                return False
+            k.batch = k.open_batch()
+            k.batch_bytes = nb
+            k.it_seen = 0
         return True
 
-    def _batch(self, slot):
-        if slot.batch is None:
-            nb = slot.g.workspace_bytes(fg.FG_PRIM_MSBFS, 64)
-            if not self._reserve(nb):
-                return None
-            slot.batch = fg.MsBatch(slot.g, 64)
-        return slot.batch
-
-    def _sssp_ws(self, slot):
-        if slot.sssp_ws is None:
-            nb = slot.g.workspace_bytes(fg.FG_PRIM_SSSP)
-            if not self._reserve(nb):
-                return None
-            slot.sssp_ws = torch.zeros(max(nb, 256), dtype=torch.uint8, device="cuda")
-        return slot.sssp_ws
+    def _ensure_single(self, k):
+        if k.single_ws is None:
+            prim = fg.FG_PRIM_BFS if k.kind == BFS else fg.FG_PRIM_SSSP
+            nb = k.g.workspace_bytes(prim)
+            if not self._reserve(nb, keep=k):
+                return False
+            k.single_ws = k.g.workspace(prim)
+            k.single_bytes = nb
+        return True
 
     # ---------------------------------------------------------- scheduling
     def submit(self, req):
-        self.pending.append(req)
-
-    def _admit(self, now):
-        """Admit pending requests whose resources are available (FIFO per kind)."""
-        sssp_now = []
-        keep = collections.deque()
-        while self.pending:
-            r = self.pending.popleft()
-            slot = self.slots[r.graph]
-            if r.kind == BFS:
-                b = self._batch(slot)
-                if b is None or not slot.free:
-                    keep.append(r)
-                    continue
-                lane = slot.free.pop()
-                b.admit(lane, r.src)
-                slot.lane_req[lane] = r
-                r.start = now
-            else:
-                if self._sssp_ws(slot) is None:
-                    keep.append(r)
-                    continue
-                r.start = now
-                sssp_now.append(r)
-        self.pending = keep
-        return sssp_now
-
-    def _run_sssp(self, r):
-        slot = self.slots[r.graph]
-        g = slot.g
-        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        fg.sssp_into(g, r.src, dist, None, ws=slot.sssp_ws, stream=self.stream)
-        return dist
-
-    def tick(self, now_fn):
-        """One scheduling round: admit, run SSSP queries, one batched step per
-        graph with live lanes, then retire finished lanes."""
-        sssp_now = self._admit(now_fn())
-        outs = [(r, self._run_sssp(r)) for r in sssp_now]
-        stepped = []
-        for slot in self.slots.values():
-            if slot.lane_req:
-                slot.batch.step(self.k_iters, stream=self.stream)
-                stepped.append(slot)
-        if outs:
-            self.stream.synchronize()
-            t = now_fn()
-            for r, dist in outs:
-                r.done = t
-                if self.keep:
-                    r.result = dist
-                self.finished.append(r)
-        for slot in stepped:
-            done, _ = slot.batch.poll(stream=self.stream)
-            t = now_fn()
-            for lane in [l for l in slot.lane_req if (done >> l) & 1]:
-                r = slot.lane_req.pop(lane)
-                if self.keep:
-                    r.result = slot.batch.read(lane, stream=self.stream).clone()
-                slot.batch.release(lane)
-                slot.free.append(lane)
-                r.done = t
-                self.finished.append(r)
-        return bool(sssp_now or stepped)
+        self.kinds[(req.graph, req.kind)].waiting.append(req)
 
     def busy(self):
-        return bool(self.pending) or any(s.lane_req for s in self.slots.values())
+        return any(k.waiting or k.lane_req for k in self.kinds.values())
+
+    def _want_batch(self, k):
+        if self.policy == "batch":
+            return True
+        if self.policy == "single":
+            return False
+        c = k.cost
+        return c is None or c.prefer_batch(min(len(k.waiting), LANES))
+
+    def _admit(self, k, now):
+        while k.waiting and k.free:
+            r = k.waiting.popleft()
+            lane = k.free.pop()
+            k.batch.admit(lane, r.src)
+            k.lane_req[lane] = r
+            r.start = now
+            r.path = "batch"
+
+    def _step(self, k, now_fn):
+        it_ms = k.it_ms or (k.cost.it_ms if k.cost else 0.05)
+        iters = int(max(1, min(1 << 20, round(self.step_ms / max(it_ms, 1e-4)))))
+        it0 = k.it_seen
+        t0 = time.perf_counter()
+        k.batch.step(iters, stream=self.stream)
+        done, it1 = k.batch.poll(stream=self.stream)
+        dt = (time.perf_counter() - t0) * 1e3
+        ran = it1 - it0
+        k.it_seen = it1
+        if ran > 0:
+            est = dt / ran
+            k.it_ms = est if k.it_ms is None else 0.5 * k.it_ms + 0.5 * est
+        self.counts["steps"] += 1
+        t = now_fn()
+        for lane in [l for l in k.lane_req if (done >> l) & 1]:
+            r = k.lane_req.pop(lane)
+            if self.keep:
+                r.result = k.batch.read(lane, stream=self.stream).clone()
+            k.batch.release(lane)
+            k.free.append(lane)
+            r.done = t
+            self.finished.append(r)
+        if self.keep:
+            self.stream.synchronize()
+
+    def _single(self, k, now_fn):
+        r = k.waiting.popleft()
+        r.start = now_fn()
+        r.path = "single"
+        g = k.g
+        out = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+        if k.kind == BFS:
+            o = self.bfs_opts if g.symmetric else fg.bfs_opts(mode=fg.FG_MODE_PUSH)
+            fg.bfs_into(g, r.src, out, None, o, ws=k.single_ws, stream=self.stream)
+        else:
+            fg.sssp_into(g, r.src, out, None, ws=k.single_ws, stream=self.stream)
+        self.stream.synchronize()
+        self.counts["singles"] += 1
+        r.done = now_fn()
+        if self.keep:
+            r.result = out
+        self.finished.append(r)
+
+    def tick(self, now_fn):
+        """Run the unit of work that holds the oldest request; False when
+        there is nothing to run."""
+        live = [k for k in self.kinds.values() if k.waiting or k.lane_req]
+        if not live:
+            return False
+        live.sort(key=lambda k: k.oldest())
+        for k in live:
+            k.last_used = time.perf_counter()
+            if k.lane_req:
+                self._admit(k, now_fn())
+                self._step(k, now_fn)
+                return True
+            if self._want_batch(k) and self._ensure_batch(k):
+                k.it_ms = None
+                self._admit(k, now_fn())
+                self._step(k, now_fn)
+                return True
+            if self._ensure_single(k):
+                self._single(k, now_fn)
+                return True
+            # nothing of this kind fits the budget now; try the next one
+        raise RuntimeError("no waiting request fits the HBM budget")
+
+
+def calibrate(graphs, sources_per_graph, stream=None):
+    """Measure the cost model of every graph and kind: single-source runs
+    (one warm-up, two timed) and batches of 1 and 8 lanes run to the end.
+    sources_per_graph: dict name -> at least 8 source vertices."""
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    costs = {}
+
+    def timed(fn):
+        stream.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        stream.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    for name, g in graphs.items():
+        srcs = [int(s) for s in sources_per_graph[name][:8]]
+        kinds = [BFS] + ([SSSP] if g.w is not None else [])
+        for kind in kinds:
+            out = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+            if kind == BFS:
+                ws = g.workspace(fg.FG_PRIM_BFS)
+                o = fg.bfs_opts(mode=fg.FG_MODE_DO if g.symmetric else fg.FG_MODE_PUSH)
+                run1 = lambda s: fg.bfs_into(g, s, out, None, o, ws=ws, stream=stream)
+                b = fg.MsBatch(g, LANES, stream=stream)
+            else:
+                ws = g.workspace(fg.FG_PRIM_SSSP)
+                run1 = lambda s: fg.sssp_into(g, s, out, None, ws=ws, stream=stream)
+                b = fg.MsspBatch(g, LANES, stream=stream)
+            run1(srcs[0])
+            single = (timed(lambda: run1(srcs[1])) + timed(lambda: run1(srcs[2]))) / 2
+
+            def batch_run(lanes_srcs):
+                for lane in range(LANES):
+                    if (b.admitted >> lane) & 1:
+                        b.release(lane)
+                for lane, s in enumerate(lanes_srcs):
+                    b.admit(lane, s)
+                _, it0 = b.poll(stream=stream)
+                t = timed(lambda: b.step(1 << 30, stream=stream))
+                _, it1 = b.poll(stream=stream)
+                return t, it1 - it0
+
+            batch_run(srcs[:1])
+            t1, _ = batch_run(srcs[1:2])
+            t8, it8 = batch_run(srcs[:8])
+            b.close()
+            del ws
+            costs[(name, kind)] = Cost(single, t1, t8, t8 / max(it8, 1))
+    return costs
 
 
 def poisson_arrivals(n, qps, seed):
@@ -201,7 +354,7 @@ def serve_stream(server, reqs, time_limit=600.0):
     return server.finished
 
 
-def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0):
+def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None):
     """The one-at-a-time plain path: each request runs alone (fg_bfs /
     fg_sssp) in arrival order, on the same stream and device."""
     t0 = time.perf_counter()
@@ -213,15 +366,17 @@ def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0):
             time.sleep(min(r.arrival - now(), 0.002))
         r.start = now()
         g = graphs[r.graph]
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
         if r.kind == BFS:
-            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
-            fg.bfs_into(g, r.src, d, None, o if g.symmetric else fg.bfs_opts(mode=fg.FG_MODE_PUSH))
+            ws = bfs_ws[r.graph] if bfs_ws else None
+            fg.bfs_into(g, r.src, d, None, o if g.symmetric else fg.bfs_opts(mode=fg.FG_MODE_PUSH),
+                        ws=ws)
         else:
-            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
             fg.sssp_into(g, r.src, d, None, ws=sssp_ws[r.graph])
         torch.cuda.current_stream().synchronize()
         r.done = now()
         r.result = d
+        r.path = "single"
         out.append(r)
         if now() > time_limit:
             raise RuntimeError("FIFO replay exceeded its time limit")

@@ -40,19 +40,43 @@ def check_results(orc, csr, done, serve):
             assert np.array_equal(got.astype(np.uint32), want), (r.rid, r.graph, r.src)
 
 
-@pytest.mark.parametrize("budget,k", [(32 << 30, 4), (1 << 22, 1)])
-def test_served_mix_equals_alone(env, orc, budget, k):
+@pytest.mark.parametrize("budget,policy,step_ms", [(32 << 30, "batch", 4.0), (1 << 22, "batch", 0.05),
+                                                    (32 << 30, "auto", 1.0), (64 << 20, "auto", 0.2),
+                                                    (32 << 30, "single", 1.0)])
+def test_served_mix_equals_alone(env, orc, budget, policy, step_ms):
     fg, serve, specs, graphs, csr = env
     reqs = serve.make_requests(specs, 160, qps=20000.0, seed=budget & 0xFFFF)
-    announce(f"serve 160 requests budget={budget} k={k}")
-    srv = serve.Server(graphs, hbm_budget=budget, k_iters=k)
+    announce(f"serve 160 requests budget={budget} policy={policy} step_ms={step_ms}")
+    costs = None
+    if policy == "auto":
+        srcs = {n: synth.sources(csr[n][0], 8, seed=4) for n in graphs}
+        costs = serve.calibrate(graphs, srcs)
+    srv = serve.Server(graphs, hbm_budget=budget, policy=policy, costs=costs, step_ms=step_ms)
     done = serve.serve_stream(srv, reqs, time_limit=120)
     assert len(done) == len(reqs)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
     assert all(r.done >= r.arrival for r in done)
     check_results(orc, csr, done, serve)
-    # lanes really were shared: some batched steps ran with several queries
+    if policy == "batch":
+        assert srv.counts["steps"] > 0
+        if budget < (1 << 24):
+            # idle batches were closed to make room for others; a request
+            # whose batch does not fit while the others are busy runs alone
+            assert srv.counts["evictions"] > 0
+        else:
+            assert all(r.path == "batch" for r in done)
+    if policy == "single":
+        assert srv.counts["steps"] == 0 and srv.counts["singles"] == len(reqs)
     st = serve.latency_stats(done)
     assert st["n"] == len(reqs)
+
+
+def test_budget_too_small_is_reported(env):
+    fg, serve, specs, graphs, csr = env
+    reqs = serve.make_requests(specs, 4, qps=20000.0, seed=1)
+    srv = serve.Server(graphs, hbm_budget=1024, policy="batch")
+    with pytest.raises(RuntimeError):
+        serve.serve_stream(srv, reqs, time_limit=60)
 
 
 def test_fifo_path_same_answers(env, orc):
