@@ -37,8 +37,8 @@ GRID = 4096
 # rmat22x64_grid4096.md).  They hold only for the kernel sources they were
 # taken with: `traffic` is null when these files hash differently.
 TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
-TRAFFIC_SHA256 = "5efa90092dc1a3241a1e82820d8235f6eab94be540c5186db02d45a2edfdb3ab"
-TRAFFIC_BYTES = {"bfs_persistent<DO>": 244264550, "bfs_persistent<PUSH>": 2923487539}
+TRAFFIC_SHA256 = "4ef8c8f36c85a03d7ebf130d4fbb00020f6a6c86b797b015524d46d082acd8d0"
+TRAFFIC_BYTES = {"bfs_persistent<DO>": 244281941, "bfs_persistent<PUSH>": 2920845800}
 
 # direction-switch thresholds of the DO runs (Sec. VI-A do_a, do_b), as
 # chosen for this workload by paper_1504_04804_amd.autotune (stage-1 sweep
@@ -315,19 +315,23 @@ def side_batched(fg, torch, stream):
             n_single = 8
         g = fg.Graph(off, col, symmetric=True, validate=False)
         b = fg.MsBatch(g, 64)
-        bt = []
+        bt, work = [], []
         for rep in range(3):
             for lane, s in enumerate(srcs):
                 if rep:
                     b.release(lane)
                 b.admit(lane, s)
+            c0 = b.counts(stream=stream)
             e0, e1 = _ev(), _ev()
             e0.record(stream)
             b.step(1 << 30, stream=stream)
             e1.record(stream)
             torch.cuda.synchronize()
             bt.append(e0.elapsed_time(e1))
+            c1 = b.counts(stream=stream)
+            work.append((c1[0] - c0[0], c1[1] - c0[1]))
         done, _ = b.poll()
+        reached = sum(int((b.read(lane, stream=stream) >= 0).sum().item()) for lane in range(64))
         b.close()
         d = torch.empty(g.n, dtype=torch.int32, device="cuda")
         ws = g.workspace(fg.FG_PRIM_BFS)
@@ -342,6 +346,12 @@ def side_batched(fg, torch, stream):
             st.append(e0.elapsed_time(e1))
         ms_b = float(min(bt))
         t1 = float(np.mean(st))
+        ed, vv = work[int(np.argmin(bt))]
+        # per adjacency entry read: column + the neighbour's lane word; per
+        # vertex visit: visit + two frontier words; per lane: the depth row
+        # filled at admission, plus one depth store per reached vertex
+        alg = 12.0 * ed + 24.0 * vv + 4.0 * 64 * g.n + 4.0 * reached
+        gbs = alg / (ms_b * 1e-3) / 1e9
         # 64 queries arriving together: batched, all finish at the batch end;
         # one at a time, query i finishes after i + 1 traversals
         fifo_lat = [t1 * (i + 1) for i in range(64)]
@@ -354,6 +364,11 @@ def side_batched(fg, torch, stream):
             "single_fifo_latency_ms_p99": round(float(np.percentile(fifo_lat, 99)), 3),
             "qps_ratio": round((64 / (ms_b * 1e-3)) / (1000.0 / t1), 2),
             "single_path": "DOBFS (autotuned thresholds)" if name == "rmat23" else "push BFS",
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                         "alg_bytes_per_launch": round(alg),
+                         "note": "12 B per adjacency entry read + 24 B per vertex visit + "
+                                 "4 B per (lane, vertex) depth fill + 4 B per depth found"},
         }
         g.close()
     return res

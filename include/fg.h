@@ -202,6 +202,9 @@ typedef struct {
   int32_t big_degree;     /* vertices of at least this degree are relaxed by
                              the whole grid (0 = default)                     */
   int32_t blocks_per_cu;  /* persistent launch width (0 = default)            */
+  int32_t grid_blocks;    /* workgroups of the persistent launch (0 = every
+                             CU x blocks_per_cu); fewer make each grid barrier
+                             cheaper when frontiers are small              */
   uint32_t delta;         /* near-far threshold step: only vertices closer
                              than the threshold are relaxed; it grows by delta
                              when none is left (0 = default: 64 x mean weight
@@ -300,6 +303,8 @@ typedef struct {
   int32_t pull_div;      /* push -> pull when active vertices > n / pull_div (0 = 64) */
   int32_t push_div;      /* pull -> push when active vertices < n / push_div (0 = 512) */
   int32_t blocks_per_cu; /* persistent launch width (0 = default)                     */
+  int32_t grid_blocks;   /* workgroups of the persistent launch (0 = every CU x
+                            blocks_per_cu)                                          */
 } fg_msbfs_opts;
 
 void fg_msbfs_opts_default(fg_msbfs_opts* opts);
@@ -335,6 +340,12 @@ fg_status fg_msbfs_poll(fg_msbfs* b, uint64_t* done_lanes, int32_t* iterations, 
  * (asynchronous on `stream`). */
 fg_status fg_msbfs_read(fg_msbfs* b, int32_t lane, int32_t* depth, void* stream);
 
+/* Synchronise `stream`; work done since fg_msbfs_open: *edges = adjacency
+ * entries read (push: whole lists of active vertices; pull: up to the early
+ * exit), *verts = vertex visits (push: active vertices; pull: every vertex
+ * of the graph per pull level).  Either pointer may be NULL. */
+fg_status fg_msbfs_counts(fg_msbfs* b, uint64_t* edges, uint64_t* verts, void* stream);
+
 /* Forget the query held by `lane` (it no longer reports as done). */
 fg_status fg_msbfs_release(fg_msbfs* b, int32_t lane);
 
@@ -348,10 +359,16 @@ typedef struct {
   int32_t big_degree;    /* vertices of at least this degree are relaxed in
                             64-edge chunks by many waves (0 = 256)           */
   int32_t blocks_per_cu; /* persistent launch width (0 = default)            */
+  int32_t grid_blocks;   /* workgroups of the persistent launch (0 = every CU
+                            x blocks_per_cu)                                 */
   int32_t dense_lanes;   /* a vertex with at least this many frontier lanes is
                             relaxed by one wave across its lanes; fewer lanes
                             are relaxed one (edge, lane) pair per thread
                             (0 = 16)                                         */
+  int32_t split_lanes;   /* lanes whose near frontier is empty wait until this
+                            many can split in one scan of the far list (0 = 8) */
+  int32_t split_wait;    /* ... or until they have waited this many
+                            iterations (0 = 8); 1 = split at once             */
 } fg_mssp_opts;
 
 void fg_mssp_opts_default(fg_mssp_opts* opts);

@@ -79,6 +79,7 @@ class SsspOpts(ctypes.Structure):
         ("small_edges", ctypes.c_int32),
         ("big_degree", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
         ("delta", ctypes.c_uint32),
     ]
 
@@ -89,6 +90,7 @@ class MsOpts(ctypes.Structure):
         ("pull_div", ctypes.c_int32),
         ("push_div", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -97,7 +99,10 @@ class MpOpts(ctypes.Structure):
         ("delta", ctypes.c_uint32),
         ("big_degree", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
         ("dense_lanes", ctypes.c_int32),
+        ("split_lanes", ctypes.c_int32),
+        ("split_wait", ctypes.c_int32),
     ]
 
 
@@ -163,6 +168,7 @@ SIGNATURES = {
     "fg_msbfs_poll": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I32), _P]),
     "fg_msbfs_read": (_I32, [_P, _I32, _P, _P]),
     "fg_msbfs_release": (_I32, [_P, _I32]),
+    "fg_msbfs_counts": (_I32, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), _P]),
     "fg_mssp_opts_default": (None, [ctypes.POINTER(MpOpts)]),
     "fg_mssp_open": (_I32, [_P, _I32, _P, _SZ, ctypes.POINTER(MpOpts), _P, ctypes.POINTER(_P)]),
     "fg_mssp_close": (_I32, [_P]),
@@ -334,12 +340,13 @@ def bfs(g, src, mode=FG_MODE_DO, parents=True, opts=None, **kw):
 SSSP_NO_THRESHOLD = 0xFFFFFFFF  # delta: plain frontier Bellman-Ford
 
 
-def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0, delta=0):
+def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0, delta=0,
+              grid_blocks=0):
     o = SsspOpts()
     lib().fg_sssp_opts_default(ctypes.byref(o))
     o.small_frontier, o.small_edges = small_frontier, small_edges
     o.big_degree, o.blocks_per_cu = big_degree, blocks_per_cu
-    o.delta = delta
+    o.delta, o.grid_blocks = delta, grid_blocks
     return o
 
 
@@ -494,10 +501,11 @@ def graph_csr(handle, n, m):
     return off, col
 
 
-def msbfs_opts(big_degree=0, pull_div=0, push_div=0, blocks_per_cu=0):
+def msbfs_opts(big_degree=0, pull_div=0, push_div=0, blocks_per_cu=0, grid_blocks=0):
     o = MsOpts()
     lib().fg_msbfs_opts_default(ctypes.byref(o))
     o.big_degree, o.pull_div, o.push_div, o.blocks_per_cu = big_degree, pull_div, push_div, blocks_per_cu
+    o.grid_blocks = grid_blocks
     return o
 
 
@@ -540,6 +548,14 @@ class MsBatch:
         _check(lib().fg_msbfs_release(self.handle, int(lane)))
         self.admitted &= ~(1 << int(lane))
 
+    def counts(self, stream=None):
+        """(adjacency entries read, vertex visits) since open."""
+        e = ctypes.c_uint64()
+        v = ctypes.c_uint64()
+        _check(lib().fg_msbfs_counts(self.handle, ctypes.byref(e), ctypes.byref(v),
+                                     _stream(stream)))
+        return int(e.value), int(v.value)
+
     def run(self, k_iters=16, max_steps=1 << 20):
         """Step until every admitted lane is done; returns the done mask."""
         for _ in range(max_steps):
@@ -561,11 +577,13 @@ class MsBatch:
             pass
 
 
-def mssp_opts(delta=0, big_degree=0, blocks_per_cu=0, dense_lanes=0):
+def mssp_opts(delta=0, big_degree=0, blocks_per_cu=0, dense_lanes=0, grid_blocks=0,
+              split_lanes=0, split_wait=0):
     o = MpOpts()
     lib().fg_mssp_opts_default(ctypes.byref(o))
     o.delta, o.big_degree, o.blocks_per_cu = delta, big_degree, blocks_per_cu
-    o.dense_lanes = dense_lanes
+    o.dense_lanes, o.grid_blocks = dense_lanes, grid_blocks
+    o.split_lanes, o.split_wait = split_lanes, split_wait
     return o
 
 

@@ -53,7 +53,10 @@ struct MsState {
   ull live;        // lanes with a non-empty current frontier
   ull used;        // lanes admitted at least once
   int32_t start[MAXL];
-  int32_t pad[16];
+  ull edges;  // adjacency entries read since open (push: whole lists; pull:
+              // up to the early exit)
+  ull verts;  // vertex visits since open (push: active; pull: every vertex)
+  int32_t pad[12];
 };
 
 // Monotone counters of one iteration parity (see the BFS kernel).
@@ -164,7 +167,7 @@ __device__ __forceinline__ bool claim(const MsParams& P, ull* Fn, int32_t v, ull
 
 // ---- push expansion (scan-gather for low degree, descriptors for high)
 __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int64_t qlen,
-                            ull qbase, ull dbase, Lds& L, ull& got) {
+                            ull qbase, ull dbase, Lds& L, ull& got, uint32_t& ecnt, uint32_t& vcnt) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int32_t* Qin = P.q[S.qsel];
@@ -192,6 +195,8 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
       fu = Fc[u];
       Fc[u] = 0ull;  // only this thread reads u's word in this iteration
       if (fu == 0ull) deg = 0;  // listed but without lanes
+      ecnt += (uint32_t)deg;
+      vcnt += fu != 0ull;
     }
     const bool big = deg >= P.big_deg;
     const int32_t nd = big ? (deg + CH - 1) / CH : 0;
@@ -332,6 +337,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
 
   if (threadIdx.x < MAXL) L.start[threadIdx.x] = P.state->start[threadIdx.x];
   __syncthreads();
+  uint32_t ecnt = 0, vcnt = 0;  // per-thread counts stay far below 2^32
   for (int32_t k = 0; ok && k < P.k_iters && S.live != 0ull; ++k) {
     const int32_t it1 = S.it + 1;
     const bool want_pull = S.mode == 0 ? S.qlen > P.n / P.pull_div : S.qlen >= P.n / P.push_div;
@@ -388,8 +394,10 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           hd = P.head[v];
         }
         const ull want = S.live & ~vis;
+        vcnt += v < P.n;
         if (want && e > b) {
           const int32_t d = e - b;
+          ecnt += (uint32_t)(d < 4 ? d : 4);
           const ull f0 = Fc[hd.x], f1 = Fc[hd.y], f2 = Fc[hd.z], f3 = Fc[hd.w];
           nw = (f0 | (d > 1 ? f1 : 0ull) | (d > 2 ? f2 : 0ull) | (d > 3 ? f3 : 0ull)) & want;
         }
@@ -400,6 +408,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             const int32_t u0 = P.col[i], u1 = P.col[i + 1 < l ? i + 1 : l],
                           u2 = P.col[i + 2 < l ? i + 2 : l], u3 = P.col[i + 3 < l ? i + 3 : l];
             const ull g = Fc[u0] | Fc[u1] | Fc[u2] | Fc[u3];
+            ecnt += (uint32_t)(e - i < 4 ? e - i : 4);
             nw |= g & want;
             if (nw == want || i + 4 >= e) shortl = false;
           }
@@ -424,6 +433,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             const int32_t i = i0 + lane;
             ull x = 0;
             if (i < le) x = Fc[P.col[i]] & lw;
+            if (lane == 0) ecnt += (uint32_t)(le - i0 < FG_WAVE ? le - i0 : FG_WAVE);
             acc |= fg_wave_or64(x);
           }
           if (lane == l) nw = acc & lw;
@@ -469,6 +479,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
                                                      __HIP_MEMORY_SCOPE_AGENT));
             if ((cur & want) == want) continue;  // every wanted lane already found
             const int32_t e1 = min(dsc.y + CH, P.off[v + 1]);
+            if (lane == 0) ecnt += (uint32_t)(e1 - dsc.y);
             ull x = 0;
 #pragma unroll
             for (int r = 0; r < CH / FG_WAVE; ++r) {
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
     } else {
       // ---- push
       ull got = 0;
-      push_expand(P, S, k, S.qlen, qbp, dbp, L, got);
+      push_expand(P, S, k, S.qlen, qbp, dbp, L, got, ecnt, vcnt);
       {
         const ull bor = block_or(got, L.redu);
         if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
@@ -544,6 +555,16 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
     cb1 = (cbp & msk) | (cb1 & ~msk);
     cb0 = (cb0 & msk) | (cbp & ~msk);
     S.it = it1;
+  }
+  {
+    // work counters: every workgroup adds its own (the host reads them after
+    // the launch)
+    const int64_t be = fg_block_sum<PB>((int64_t)ecnt, L.red);
+    const int64_t bv = fg_block_sum<PB>((int64_t)vcnt, L.red);
+    if (threadIdx.x == 0) {
+      if (be) atomicAdd(&P.state->edges, (ull)be);
+      if (bv) atomicAdd(&P.state->verts, (ull)bv);
+    }
   }
   if (tid == 0) {
     MsState* st = P.state;
@@ -714,7 +735,9 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   P.pull_div = b->opts.pull_div > 0 ? b->opts.pull_div : 64;
   P.push_div = b->opts.push_div > 0 ? b->opts.push_div : 512;
   void* args[] = {&P};
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)msbfs_persistent, dim3(pr.cus * bpc),
+  int grid = pr.cus * bpc;
+  if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)msbfs_persistent, dim3(grid),
                                         dim3(PB), args, 0, (hipStream_t)stream));
   b->npend = 0;
   return FG_OK;
@@ -731,6 +754,17 @@ extern "C" fg_status fg_msbfs_poll(fg_msbfs* b, uint64_t* done_lanes, int32_t* i
   for (int i = 0; i < b->npend; ++i) pend |= 1ull << b->pend_lane[i];
   if (done_lanes) *done_lanes = b->admitted & ~hs.live & ~pend;
   if (iterations) *iterations = hs.it;
+  return FG_OK;
+}
+
+extern "C" fg_status fg_msbfs_counts(fg_msbfs* b, uint64_t* edges, uint64_t* verts, void* stream) {
+  if (!b) return fg_set_error(FG_EINVAL, "fg_msbfs_counts: batch is NULL");
+  MsState hs;
+  hipStream_t s = (hipStream_t)stream;
+  FG_HIP_TRY(hipMemcpyAsync(&hs, b->lay.state, sizeof(MsState), hipMemcpyDeviceToHost, s));
+  FG_HIP_TRY(hipStreamSynchronize(s));
+  if (edges) *edges = hs.edges;
+  if (verts) *verts = hs.verts;
   return FG_OK;
 }
 

@@ -20,7 +20,9 @@
 // iteration splits instead of relaxing: T grows to the lane's next
 // threshold, and a scan of the far list moves its entries now below T into
 // the next frontier, drops the stale ones (below the old T: relaxed as near
-// since) and keeps the rest.  A split that finds nothing ends the lane; one
+// since) and keeps the rest.  The scan reads the whole far list whatever
+// the number of lanes splitting, so idle lanes wait (a few iterations at
+// most) until several of them can split in one scan.  A split that finds nothing ends the lane; one
 // that only keeps entries sets the next threshold from their smallest
 // distance.  Splits of some lanes run in the same iteration as the
 // relaxations of the others, so an iteration ends with one grid barrier (two
@@ -64,7 +66,7 @@ struct MpState {
   ull edges;       // edge visits (one per edge and wave, all lanes at once)
   ull edge_lanes;  // edge relaxations attempted (per lane)
   uint32_t overflow;
-  int32_t pad;
+  int32_t swait;   // iterations idle lanes have waited for a split
   uint32_t T[MAXL];
   uint32_t Tnext[MAXL];
 };
@@ -109,7 +111,9 @@ struct MpParams {
   int32_t pend_src[MAXL];
   uint32_t delta;
   int32_t big_deg;
-  int32_t dense;  // lanes from which a vertex is relaxed lane-parallel
+  int32_t dense;        // lanes from which a vertex is relaxed lane-parallel
+  int32_t split_lanes;  // idle lanes that trigger a split of the far list
+  int32_t split_wait;   // ... or iterations the idle lanes have waited
 };
 
 struct Lds {
@@ -284,6 +288,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   MpCtl* C = P.ctl;
   // every workgroup reads the state before anyone writes it
   int32_t it = P.state->it, qsel = P.state->qsel, fsel = P.state->fsel, psel = P.state->psel;
+  int32_t swait = P.state->swait;
   int64_t qlen = P.state->qlen, plen = P.state->plen;
   ull live = P.state->live, used = P.state->used, nearl = P.state->nearl;
   if (threadIdx.x < MAXL) {
@@ -356,11 +361,20 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   ull edges = 0, edge_lanes = 0;
   for (int32_t k = 0; ok && k < P.k_iters && live != 0ull; ++k) {
     const int s = k % 3;
-    ull sl = live & ~nearl;  // lanes that split in this iteration
-    if (sl && plen == 0) {
-      live &= ~sl;  // empty near frontier and nothing far: finished
-      sl = 0;
+    ull idle = live & ~nearl;  // lanes with an empty near frontier
+    if (idle && plen == 0) {
+      live &= ~idle;  // empty near frontier and nothing far: finished
+      idle = 0;
       if (!live) break;
+    }
+    ull sl = 0;  // lanes that split in this iteration
+    if (idle) {
+      if (__popcll(idle) >= P.split_lanes || (live & nearl) == 0 || swait + 1 >= P.split_wait) {
+        sl = idle;
+        swait = 0;
+      } else {
+        swait++;
+      }
     }
     if (tid == 0) {
       const int s1 = (k + 1) % 3;
@@ -618,6 +632,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
       S->live = (ok && ok2) ? live : 0ull;
       S->used = used;
       S->nearl = nearl;
+      S->swait = swait;
       S->edges += fg_atomic_load_u64(&C->edges.v);
       S->edge_lanes += fg_atomic_load_u64(&C->edge_lanes.v);
       const uint32_t o = __hip_atomic_load(&C->pub_ovf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -804,8 +819,12 @@ extern "C" fg_status fg_mssp_step(fg_mssp* b, int32_t k_iters, void* stream) {
   P.big_deg = b->opts.big_degree > 0 ? b->opts.big_degree : 4 * CHS;
   if (P.big_deg > 65536) P.big_deg = 65536;  // keeps a wave's (edge, lane) count in int32
   P.dense = b->opts.dense_lanes > 0 ? b->opts.dense_lanes : 16;
+  P.split_lanes = b->opts.split_lanes > 0 ? b->opts.split_lanes : 8;
+  P.split_wait = b->opts.split_wait > 0 ? b->opts.split_wait : 8;
   void* args[] = {&P};
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)mssp_persistent, dim3(pr.cus * bpc),
+  int grid = pr.cus * bpc;
+  if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)mssp_persistent, dim3(grid),
                                         dim3(PB), args, 0, (hipStream_t)stream));
   b->npend = 0;
   return FG_OK;

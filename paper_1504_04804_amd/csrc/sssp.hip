@@ -845,7 +845,8 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   int bpc = (dev >= 0 && dev < 64) ? g_sssp_occ[dev] : 1;
   if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
   if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
-  const int grid = pr.cus * bpc;
+  int grid = pr.cus * bpc;
+  if (o.grid_blocks > 0 && o.grid_blocks < grid) grid = o.grid_blocks;
 
   SsspParams P;
   memset(&P, 0, sizeof(P));

@@ -40,7 +40,9 @@ def run_batch(fg, g, srcs, opts=None, lanes=64, k_iters=16):
 @pytest.mark.parametrize("opts", [dict(), dict(delta=1), dict(delta=40), dict(delta=0xFFFFFFFF),
                                   dict(big_degree=2), dict(delta=3, big_degree=8),
                                   dict(dense_lanes=1), dict(dense_lanes=65),
-                                  dict(dense_lanes=65, big_degree=2), dict(dense_lanes=4, big_degree=30)])
+                                  dict(dense_lanes=65, big_degree=2), dict(dense_lanes=4, big_degree=30),
+                                  dict(split_wait=1), dict(split_lanes=64, split_wait=1000),
+                                  dict(delta=2, split_lanes=3, split_wait=2)])
 def test_rmat12_64_lanes(fg, orc, opts):
     off, col = synth.rmat_csr(12)
     w = synth.weights(off, col)
@@ -53,16 +55,18 @@ def test_rmat12_64_lanes(fg, orc, opts):
     assert 0 < e <= el
 
 
-@pytest.mark.parametrize("delta,dense", [(0, 0), (1, 0), (500, 0), (0, 1)])
-def test_grid_lanes(fg, orc, delta, dense):
+@pytest.mark.parametrize("delta,dense,split", [(0, 0, 0), (1, 0, 0), (500, 0, 0), (0, 1, 0), (0, 0, 1),
+                                               (7, 0, 100)])
+def test_grid_lanes(fg, orc, delta, dense, split):
     off, col = synth.grid_csr(120, 130)
     w = synth.weights(off, col)
     g = fg.Graph(off, col, weights=w)
     rng = np.random.default_rng(4)
     srcs = {int(l): int(s) for l, s in zip(rng.choice(64, 9, replace=False),
                                            rng.choice(len(off) - 1, 9, replace=False))}
-    announce(f"mssp grid 120x130 lanes {sorted(srcs)} delta={delta} dense={dense}")
-    b = run_batch(fg, g, srcs, fg.mssp_opts(delta=delta, dense_lanes=dense), k_iters=100)
+    announce(f"mssp grid 120x130 lanes {sorted(srcs)} delta={delta} dense={dense} split={split}")
+    b = run_batch(fg, g, srcs, fg.mssp_opts(delta=delta, dense_lanes=dense, split_wait=split,
+                                            split_lanes=split), k_iters=100)
     check_lanes(orc, b, off, col, w, srcs)
 
 
