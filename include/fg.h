@@ -211,6 +211,10 @@ typedef struct {
                              / mean degree; UINT32_MAX = no threshold, plain
                              frontier Bellman-Ford).  Results do not depend
                              on it.                                          */
+  int32_t team_blocks;    /* workgroups that run medium frontiers from LDS
+                             queues as a team (0 = 32, -1 = no team)         */
+  int32_t team_edges;     /* ... while the frontier's degree sum is at most
+                             this (0 = 65536)                                */
 } fg_sssp_opts;
 
 void fg_sssp_opts_default(fg_sssp_opts* opts);

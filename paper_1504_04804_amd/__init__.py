@@ -81,6 +81,8 @@ class SsspOpts(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
         ("delta", ctypes.c_uint32),
+        ("team_blocks", ctypes.c_int32),
+        ("team_edges", ctypes.c_int32),
     ]
 
 
@@ -341,12 +343,13 @@ SSSP_NO_THRESHOLD = 0xFFFFFFFF  # delta: plain frontier Bellman-Ford
 
 
 def sssp_opts(small_frontier=0, small_edges=0, big_degree=0, blocks_per_cu=0, delta=0,
-              grid_blocks=0):
+              grid_blocks=0, team_blocks=0, team_edges=0):
     o = SsspOpts()
     lib().fg_sssp_opts_default(ctypes.byref(o))
     o.small_frontier, o.small_edges = small_frontier, small_edges
     o.big_degree, o.blocks_per_cu = big_degree, blocks_per_cu
     o.delta, o.grid_blocks = delta, grid_blocks
+    o.team_blocks, o.team_edges = team_blocks, team_edges
     return o
 
 

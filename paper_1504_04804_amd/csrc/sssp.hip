@@ -50,6 +50,16 @@ constexpr ull KEY_INF = ~0ull;
 constexpr uint32_t DIST_INF = 0xFFFFFFFFu;
 constexpr int FSTAGE = 256;
 constexpr int64_t SMALL_FAR = 4 * PB;  // piles workgroup 0 splits alone
+// Team mode (medium frontiers; see team_mode): LDS queue entries per member,
+// widest team, packed team word fields, and the frontier shape it takes.
+constexpr int QCAP = 2048;
+constexpr int TEAM_MAX = 64;
+constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
+constexpr int64_t TW_CAP = (1 << 19) - 1;
+constexpr int LDS_MEAN_DEG = 64;
+constexpr int TPV = 4;
+constexpr int32_t DEF_TEAM = 32;
+constexpr int64_t DEF_TEAM_E = 65536;
 
 struct CtrSlot {
   Line64 q;
@@ -78,6 +88,13 @@ struct alignas(256) SsspCtl {
   CtrSlot slot[2];
   uint32_t fmin[3];  // smallest distance among the entries a split keeps
   uint32_t pad3[61];
+  // team mode: arrivals of the team barrier, per-member records, the
+  // level words, and the overflow counter of the global queue
+  uint32_t team_arrive;
+  uint32_t pad4[63];
+  ull team_rec[2][TEAM_MAX][2];
+  Line64 team_word[3];
+  Line64 team_ovf;
   int32_t pub_k, pub_qsel, pub_force, pub_fsel;
   int64_t pub_qlen, pub_insp_sum, pub_flen;
   ull pub_fbase;
@@ -106,6 +123,8 @@ struct SsspParams {
   int64_t small_e;
   int32_t big_deg;
   int32_t clock_khz;
+  int32_t team;     // workgroups of a team (<= 1: no team mode)
+  int64_t team_e;   // largest frontier degree sum a team takes
 };
 
 struct St {
@@ -201,6 +220,16 @@ struct Lds {
   int32_t flag;
   int64_t bcast[8];
   uint32_t bcast2[2];
+  // team mode: this member's share of the frontier, (vertex, first edge,
+  // end edge), for the current and the next level; counters rotate over
+  // three slots (input, output, cleared for the level after)
+  int32_t lq_v[2][QCAP];
+  int32_t lq_b[2][QCAP];
+  int32_t lq_e[2][QCAP];
+  int32_t lq_cnt[3];
+  int32_t lq_deg[3];
+  int32_t lq_big[3];
+  int32_t tsum[6];
 };
 
 __device__ __forceinline__ void trace_iter(const St& S, const SsspParams& P) {
@@ -584,6 +613,412 @@ __device__ void small_mode(const SsspParams& P, St& S, Lds& L, int* force_full) 
   }
 }
 
+
+// ---------------------------------------------------------------- team mode
+//
+// A team of T workgroups runs near iterations back to back while the
+// frontier is of medium size (more than one workgroup's worth, at most
+// QCAP * T / 2 vertices, mean degree <= LDS_MEAN_DEG, degree sum <= team_e).
+// Each member keeps its share of the frontier in LDS as (vertex, first edge,
+// end edge); a vertex it moves into the next frontier goes to its own next
+// LDS queue with the offsets loaded alongside the relaxation.  Far-pile
+// appends go to the global pile as elsewhere.  Per iteration the members
+// add one packed word (arrival | overflow flag | count | capped degree sum)
+// to the level's team word and poll it.  Members share the keys and the
+// membership bitmaps, touched only by atomics here: a vertex's own distance
+// is read with an agent-scope atomic load (another member may just have
+// lowered it) and membership words are cleared with agent-scope atomic
+// stores.  Exact per-member counts (tagged records) are read when the
+// episode ends or a member's share is uneven; the shares are then evened
+// out through the global queue.  The other workgroups sleep meanwhile.
+struct TeamSync {
+  uint32_t* arrive;
+  uint32_t* abort_flag;
+  uint32_t T;
+  uint32_t count;
+
+  __device__ bool sync(int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+};
+
+struct TeamBases {
+  ull ovf;          // team_ovf value at which the current global queue starts
+  uint32_t levels;  // team word exchanges so far
+};
+
+// Workgroup 0 clears the team word of exchange `level + 1` (its last
+// readers have all arrived at this exchange).
+__device__ __forceinline__ ull team_clear_next(const SsspParams& P, uint32_t level) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    return __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+// One exchange: add this member's word, wait for all T.  L.tsum: [0] count,
+// [1] degree sum, [2] members that flagged themselves (count > lim).
+__device__ bool team_fast(const SsspParams& P, Lds& L, uint32_t T, uint32_t level, int32_t bcnt,
+                          int32_t bdeg, int32_t lim, ull cleared) {
+  if (threadIdx.x == 0) {
+    ull* w = &P.ctl->team_word[level % 3].v;
+    const ull g = bdeg < TW_CAP ? (ull)bdeg : (ull)TW_CAP;
+    const ull add = (1ull << TW_ARR) | ((ull)(bcnt > lim) << TW_FLAG) | ((ull)bcnt << TW_CNT) | g;
+    // the clear's old value is consumed before the arrival is issued
+    asm volatile("" ::"v"(cleared) : "memory");
+    __hip_atomic_fetch_add(w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    uint32_t spins = 0;
+    int bad = 0;
+    ull x;
+    for (;;) {
+      x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((x >> TW_ARR) >= T) break;
+      if ((++spins & 31u) == 0 &&
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+      if (spins > FG_SPIN_LIMIT) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    L.tsum[0] = (int32_t)((x >> TW_CNT) & ((1ull << (TW_FLAG - TW_CNT)) - 1));
+    L.tsum[1] = (int32_t)(x & ((1ull << TW_CNT) - 1));
+    L.tsum[2] = (int32_t)((x >> TW_FLAG) & ((1ull << (TW_ARR - TW_FLAG)) - 1));
+    L.flag = bad;
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+// Exact per-member counts (records tagged with the level; re-read until
+// current).  L.tsum: [2] members over QCAP, [3] overflow entries in all,
+// [4] entries kept in LDS by the members before this one, [5] largest count.
+__device__ bool team_records(const SsspParams& P, Lds& L, uint32_t T, uint32_t seq, int odd) {
+  const int tid = threadIdx.x;
+  if (tid < FG_WAVE) {
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    int32_t c = 0, bad = 0;
+    if ((uint32_t)tid < T) {
+      const ull* r = P.ctl->team_rec[odd][tid];
+      uint32_t spins = 0;
+      for (;;) {
+        const ull a = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(a >> 32) == seq) {
+          c = (int32_t)(uint32_t)a;
+          break;
+        }
+        if (++spins > FG_SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const int32_t keep = c < QCAP ? c : QCAP;
+    const int32_t keep_incl = fg_wave_incl_scan(keep);
+    const int32_t before = __builtin_amdgcn_readlane(keep_incl - keep, blockIdx.x);
+    const int32_t tof = fg_wave_sum(c > QCAP ? 1 : 0);
+    const int32_t tov = fg_wave_sum(c - keep);
+    int32_t mx = c;
+#pragma unroll
+    for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+      const int32_t y = __shfl_xor(mx, d, FG_WAVE);
+      mx = y > mx ? y : mx;
+    }
+    bad = fg_wave_sum(bad);
+    if (tid == 0) {
+      L.tsum[2] = tof;
+      L.tsum[3] = tov;
+      L.tsum[4] = before;
+      L.tsum[5] = mx;
+      L.flag = bad;
+    }
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+// `w` consecutive slots per lane behind the LDS counter, one atomic per
+// wave; returns this lane's first slot.  Every lane of the wave takes part.
+__device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
+  const int32_t incl = fg_wave_incl_scan(w);
+  const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+  int32_t base = 0;
+  if (tot) {
+    if (fg_lane() == 0) base = atomicAdd(counter, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+  }
+  return base + incl - w;
+}
+
+// Stores a won vertex at slot `pos` of the next LDS queue; slots past QCAP
+// go to the global queue, one atomic per wave.  Every lane takes part.
+__device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos, int32_t v,
+                                         int32_t vb, int32_t ve, int32_t* Qo, ull* ovf,
+                                         ull ovf_base) {
+  const bool over = won && pos >= QCAP;
+  if (won && !over) {
+    L.lq_v[nxt][pos] = v;
+    L.lq_b[nxt][pos] = vb;
+    L.lq_e[nxt][pos] = ve;
+  }
+  const uint64_t om = __ballot(over);
+  if (om) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
+    base = fg_uni(base);
+    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
+  }
+}
+
+// Far-pile append of a wave's far vertices (one atomic per wave).
+__device__ __forceinline__ void far_put(const SsspParams& P, bool put, int32_t v, int32_t* pile,
+                                        ull fbase) {
+  const uint64_t m = __ballot(put);
+  if (m) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(&P.ctl->farpos.v, (ull)__popcll(m));
+    base = fg_uni(base);
+    if (put) pile[base - fbase + fg_mbcnt(m)] = v;
+  }
+}
+
+// The relaxation of team mode: no pre-check load (latency matters more than
+// atomic traffic at these frontier sizes).
+__device__ __forceinline__ int relax_team(int32_t v, int32_t u, uint32_t du, uint32_t wt, uint32_t T,
+                                          uint32_t* inq_next, const SsspParams& P) {
+  const ull nd = (ull)du + (ull)wt;
+  if (nd >= 0xFFFFFFFFull) {
+    __hip_atomic_store(&P.ctl->overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return R_NONE;
+  }
+  if (v == P.src) return R_NONE;
+  const ull nk = (nd << 32) | (ull)(uint32_t)u;
+  const ull old = atomicMin(&P.key[v], nk);
+  if (nd >= (old >> 32)) return R_NONE;
+  const uint32_t bit = 1u << (v & 31);
+  if (nd < (ull)T) {
+    const uint32_t o = atomicOr(&inq_next[v >> 5], bit);
+    return (o & bit) ? R_NONE : R_NEAR;
+  }
+  const uint32_t o = atomicOr(&P.infar[v >> 5], bit);
+  return (o & bit) ? R_NONE : R_FAR;
+}
+
+// Runs near iterations as a team of T members (blockIdx.x < T).  Returns
+// false on a device error.  *handback = 1 when the frontier met on entry
+// does not suit the mode (the caller runs the next iteration on the full
+// grid).  On return S describes the frontier in the global queue Q[qsel].
+__device__ bool team_mode(const SsspParams& P, St& S, Lds& L, uint32_t T, TeamSync& ts,
+                          TeamBases& tb, int* handback) {
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  ull* ovf = &P.ctl->team_ovf.v;
+  ull ovf_base = tb.ovf;
+  int cur = 0, ci = 0, ni = 1, ri = 2;
+  bool load = true;
+  int64_t lvl_deg = 0;  // degree sum of the current level's frontier
+  *handback = 0;
+  for (;;) {
+    const int32_t* Qg = P.q[S.qsel];
+    int32_t* Qo = P.q[S.qsel ^ 1];
+    if (load) {
+      // my even slice of the global frontier -> LDS queue `cur`
+      load = false;
+      const int64_t lo = S.qlen * blockIdx.x / T, hi = S.qlen * (blockIdx.x + 1) / T;
+      const int32_t cnt = (int32_t)(hi - lo);
+      int32_t sd = 0;
+      for (int32_t i = tid; i < cnt; i += PB) {
+        const int32_t u = Qg[lo + i];
+        const int32_t b = P.off[u], e = P.off[u + 1];
+        L.lq_v[cur][i] = u;
+        L.lq_b[cur][i] = b;
+        L.lq_e[cur][i] = e;
+        sd += e - b;
+      }
+      if (tid == 0) {
+        L.lq_cnt[ci] = cnt;
+        L.lq_cnt[ni] = 0;
+        L.lq_deg[ni] = 0;
+        L.lq_big[ni] = 0;
+      }
+      const int32_t bsd = fg_block_sum<PB>(sd, L.red32);
+      if (!team_fast(P, L, T, tb.levels, cnt, bsd, QCAP, team_clear_next(P, tb.levels)))
+        return false;
+      tb.levels++;
+      lvl_deg = fg_uni(L.tsum[1]);
+      if (lvl_deg > LDS_MEAN_DEG * S.qlen || lvl_deg > P.team_e) {
+        *handback = 1;  // the global queue is untouched
+        return true;
+      }
+      __syncthreads();
+    }
+    const int nxt = cur ^ 1;
+    const int32_t cnt = L.lq_cnt[ci];
+    // issued now, so that it is done by the time this level's exchange
+    // needs it
+    const ull cleared = team_clear_next(P, tb.levels);
+    if (tid == 0) {
+      L.lq_cnt[ri] = 0;
+      L.lq_deg[ri] = 0;
+      L.lq_big[ri] = 0;
+    }
+    uint32_t* inq_cur = P.inq[S.k & 1];
+    uint32_t* inq_nxt = P.inq[(S.k + 1) & 1];
+    int32_t* pile = P.far[S.fsel];
+    bool big = false;
+    // vertices of degree <= TPV: TPV consecutive lanes per vertex, one edge
+    // each; every vertex clears its word of the current membership bitmap
+    for (int32_t c0 = 0; c0 < cnt; c0 += PB / TPV) {
+      const int32_t i = c0 + tid / TPV;
+      const int32_t j = tid % TPV;
+      int32_t u = 0, b = 0, d = 0;
+      if (i < cnt) {
+        u = L.lq_v[cur][i];
+        b = L.lq_b[cur][i];
+        d = L.lq_e[cur][i] - b;
+        if (j == 0)
+          __hip_atomic_store(&inq_cur[u >> 5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      big |= d > TPV;
+      int r = R_NONE;
+      int32_t v = 0, vb = 0, ve = 0;
+      if (d <= TPV && j < d) {
+        const int32_t e = b + j;
+        v = P.col[e];
+        const uint32_t wt = P.w[e];
+        vb = P.off[v];
+        ve = P.off[v + 1];
+        const uint32_t du = (uint32_t)(__hip_atomic_load(&P.key[u], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT) >> 32);
+        r = relax_team(v, u, du, wt, S.T, inq_nxt, P);
+      }
+      const bool won = r == R_NEAR;
+      const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+      const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+      if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+      wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+      far_put(P, r == R_FAR, v, pile, S.fbase);
+    }
+    if (big) L.lq_big[ni] = 1;
+    __syncthreads();
+    if (L.lq_big[ni]) {
+      // vertices of degree > TPV: block scan-gather over their edges
+      for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
+        const int32_t i = c0 + tid;
+        int32_t u = 0, b = 0, d = 0;
+        uint32_t du = 0;
+        if (i < cnt) {
+          u = L.lq_v[cur][i];
+          b = L.lq_b[cur][i];
+          d = L.lq_e[cur][i] - b;
+        }
+        if (d <= TPV) d = 0;
+        if (d)
+          du = (uint32_t)(__hip_atomic_load(&P.key[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
+                          32);
+        int32_t Tn = 0;
+        const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &Tn);
+        L.b_sc[tid] = ex;
+        L.b_u[tid] = u;
+        L.b_b[tid] = b;
+        L.b_d[tid] = du;
+        __syncthreads();
+        const int32_t nc = cnt - c0 < PB ? cnt - c0 : PB;
+        for (int32_t t0 = 0; t0 < Tn; t0 += PB) {
+          const int32_t t = t0 + tid;
+          int r = R_NONE;
+          int32_t v = 0, vb = 0, ve = 0;
+          if (t < Tn) {
+            const int32_t jj = upper_idx(L.b_sc, nc, t);
+            const int32_t e = L.b_b[jj] + (t - L.b_sc[jj]);
+            v = P.col[e];
+            const uint32_t wt = P.w[e];
+            vb = P.off[v];
+            ve = P.off[v + 1];
+            r = relax_team(v, L.b_u[jj], L.b_d[jj], wt, S.T, inq_nxt, P);
+          }
+          const bool won = r == R_NEAR;
+          const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+          const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+          if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+          wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+          far_put(P, r == R_FAR, v, pile, S.fbase);
+        }
+        __syncthreads();
+      }
+    }
+    const int32_t bcnt = L.lq_cnt[ni];
+    const int32_t bdeg = L.lq_deg[ni];
+    if (tid == 0) {
+      // the record behind the word, read only on the slow path
+      ull* rr = P.ctl->team_rec[S.k & 1][blockIdx.x];
+      const ull tag = (ull)((uint32_t)S.k + 1u) << 32;
+      __hip_atomic_store(rr, tag | (uint32_t)bcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t lim = (5 * S.qlen / T + 64) / 4;
+    if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP), cleared))
+      return false;
+    tb.levels++;
+    const int64_t nq = fg_uni(L.tsum[0]);
+    const int64_t nqdeg = fg_uni(L.tsum[1]);
+    const int64_t nflag = fg_uni(L.tsum[2]);
+    trace_insp(S.k, lvl_deg, P);
+    S.insp_sum += lvl_deg;
+    S.k++;
+    S.qlen = nq;
+    lvl_deg = nqdeg;
+    trace_iter(S, P);
+    bool stay = nq > 0 && nqdeg <= LDS_MEAN_DEG * nq && nqdeg <= P.team_e &&
+                nq <= (int64_t)QCAP * T / 2 && !(nq <= P.small_q && nqdeg <= P.small_e);
+    int64_t nover = bcnt > QCAP ? bcnt - QCAP : 0, before = 0;
+    bool rebalance = false;
+    if (!stay || nflag) {
+      if (!team_records(P, L, T, (uint32_t)S.k, (S.k - 1) & 1)) return false;
+      nover = fg_uni(L.tsum[3]);
+      before = fg_uni(L.tsum[4]);
+      stay = stay && fg_uni(L.tsum[2]) == 0;
+      rebalance = stay && 4 * fg_uni(L.tsum[5]) * (int64_t)T > 5 * nq + 64 * (int64_t)T;
+    }
+    if (!stay || rebalance) {
+      // global queue: the overflow entries, then every member's LDS queue
+      // in member order
+      const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
+      int32_t* dst = Qo + nover + before;
+      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      ovf_base += (ull)nover;
+      tb.ovf = ovf_base;
+      if (!ts.sync(&L.flag)) return false;
+      S.qsel ^= 1;
+      if (!stay) {
+        // the far pile grew by the members' appends (all done before the
+        // barrier above)
+        S.flen = (int64_t)(fg_atomic_load_u64(&P.ctl->farpos.v) - S.fbase);
+        return true;
+      }
+      load = true;
+    }
+    cur = nxt;
+    const int t3 = ci;
+    ci = ni;
+    ni = ri;
+    ri = t3;
+  }
+}
+
 __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -594,6 +1029,9 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   uint32_t sm_seen = 0;
   int force_full = 0;
   bool ok = true;
+  TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)(P.team > 1 ? P.team : 1),
+              0u};
+  TeamBases tb = {};
   const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * PB;
   // init: every key infinite except the source, membership bitmaps clear
@@ -620,12 +1058,19 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   trace_iter(S, P);
   while (ok && (S.qlen > 0 || S.flen > 0)) {
     const bool small = S.qlen == 0 ? S.flen <= SMALL_FAR : (!force_full && S.qlen <= P.small_q);
-    if (small) {
+    const bool team = !small && S.qlen > 0 && !force_full && P.team > 1 &&
+                      S.qlen <= (int64_t)QCAP * P.team / 2;
+    if (small || team) {
       sm_seen++;
-      if (blockIdx.x == 0) {
+      const bool member = small ? blockIdx.x == 0 : blockIdx.x < (uint32_t)P.team;
+      if (member) {
         int ff = 0;
-        small_mode(P, S, L, &ff);
-        if (threadIdx.x == 0) {
+        if (small) {
+          small_mode(P, S, L, &ff);
+        } else if (!team_mode(P, S, L, (uint32_t)P.team, ts, tb, &ff)) {
+          ok = false;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
           SsspCtl* c = P.ctl;
           c->pub_k = S.k;
           c->pub_qsel = S.qsel;
@@ -641,6 +1086,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
         }
         force_full = ff;
         __syncthreads();
+        if (!ok) break;
       } else {
         if (threadIdx.x == 0) {
           const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
@@ -874,6 +1320,11 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
   P.delta = o.delta > 0 ? o.delta : fg_sssp_default_delta(g);
+  P.team = o.team_blocks > 0 ? o.team_blocks : (o.team_blocks < 0 ? 1 : DEF_TEAM);
+  if (P.team > TEAM_MAX) P.team = TEAM_MAX;
+  if (P.team > grid) P.team = grid;
+  P.team_e = o.team_edges > 0 ? o.team_edges : DEF_TEAM_E;
+  if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
   P.clock_khz = pr.clock_khz;
   void* args[] = {&P};
   FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)sssp_persistent, dim3(grid), dim3(PB), args,

@@ -59,6 +59,25 @@ def test_grid_near_far(fg, orc, delta):
             assert st.iterations > 500  # about one split per distance value
 
 
+@pytest.mark.parametrize("team,team_e,delta", [(2, 0, 0), (5, 0, 1), (32, 0, 0), (64, 0, 600),
+                                               (32, 40, 0), (-1, 0, 0), (3, 0, 0xFFFFFFFF)])
+def test_team_mode(fg, orc, team, team_e, delta):
+    # small_frontier=1 sends every frontier of more than one vertex to the
+    # team (or the full grid when its mean degree is too high)
+    off, col = synth.grid_csr(200, 220)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    for s in (0, 200 * 110 + 37):
+        check(fg, orc, g, off, col, w, s, small_frontier=1, small_edges=1, team_blocks=team,
+              team_edges=team_e, delta=delta)
+    off, col = synth.rmat_csr(13)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    check(fg, orc, g, off, col, w, 0, small_frontier=1, small_edges=1, team_blocks=team,
+          team_edges=team_e, delta=delta)
+    check(fg, orc, g, off, col, w, 77, team_blocks=team, team_edges=team_e, delta=delta)
+
+
 def test_near_far_gaps(fg, orc):
     # weights far above the step: each split first finds no vertex below the
     # new threshold and jumps to the smallest distance in the pile
