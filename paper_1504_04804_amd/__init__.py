@@ -93,6 +93,8 @@ class MsOpts(ctypes.Structure):
         ("push_div", ctypes.c_int32),
         ("blocks_per_cu", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("team_blocks", ctypes.c_int32),
+        ("team_edges", ctypes.c_int32),
     ]
 
 
@@ -504,11 +506,12 @@ def graph_csr(handle, n, m):
     return off, col
 
 
-def msbfs_opts(big_degree=0, pull_div=0, push_div=0, blocks_per_cu=0, grid_blocks=0):
+def msbfs_opts(big_degree=0, pull_div=0, push_div=0, blocks_per_cu=0, grid_blocks=0,
+               team_blocks=0, team_edges=0):
     o = MsOpts()
     lib().fg_msbfs_opts_default(ctypes.byref(o))
     o.big_degree, o.pull_div, o.push_div, o.blocks_per_cu = big_degree, pull_div, push_div, blocks_per_cu
-    o.grid_blocks = grid_blocks
+    o.grid_blocks, o.team_blocks, o.team_edges = grid_blocks, team_blocks, team_edges
     return o
 
 

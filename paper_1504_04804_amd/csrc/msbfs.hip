@@ -43,6 +43,17 @@ constexpr int MAXL = 64;
 // words, so one wave would scan them all); they are listed and their lists
 // cut into CH-entry chunks that every wave takes in turn.
 constexpr int32_t LONG_PULL = 64;
+// Team mode (push levels of medium frontiers; see team_levels): LDS queue
+// entries per member, widest team, packed team word fields, frontier shape.
+constexpr int QCAP = 2048;
+constexpr int TEAM_MAX = 64;
+constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
+constexpr int64_t TW_CAP = (1 << 19) - 1;
+constexpr int LDS_MEAN_DEG = 64;
+constexpr int TPV = 4;
+constexpr int32_t DEF_TEAM = 32;
+constexpr int64_t DEF_TEAM_E = 65536;
+constexpr int32_t TEAM_MIN_Q = 1;
 
 struct MsState {
   int32_t it;      // global iteration counter
@@ -77,6 +88,18 @@ struct alignas(256) MsCtl {
   Line64 livew[3];
   int64_t pub_qlen;
   ull pub_live;
+  // team mode: hand-back signal to the waiting workgroups, team barrier,
+  // per-member records, level words, overflow counter, episode live words
+  uint32_t sm_signal;
+  uint32_t pad1[63];
+  uint32_t team_arrive;
+  uint32_t pad2[63];
+  ull team_rec[2][TEAM_MAX][2];
+  Line64 team_word[3];
+  Line64 team_ovf;
+  int32_t pub_it, pub_qsel, pub_fsel, pub_levels, pub_force;
+  int64_t pub_tqlen;
+  ull pub_tlive;
 };
 
 struct MsParams {
@@ -100,6 +123,8 @@ struct MsParams {
   int32_t big_deg;
   int32_t pull_div;  // push -> pull when active vertices > n / pull_div
   int32_t push_div;  // pull -> push when active vertices < n / push_div
+  int32_t team;      // workgroups of a team (<= 1: no team mode)
+  int64_t team_e;    // largest frontier degree sum a team takes
 };
 
 struct Lds {
@@ -115,7 +140,21 @@ struct Lds {
   int32_t flag;
   int64_t bcast[4];
   int32_t start[MAXL];  // iteration at which each lane was admitted
+  // team mode: this member's share of the frontier (vertex, first edge, end
+  // edge) for the current and the next level; counters over three slots
+  int32_t lq_v[2][QCAP];
+  int32_t lq_b[2][QCAP];
+  int32_t lq_e[2][QCAP];
+  int32_t lq_cnt[3];
+  int32_t lq_deg[3];
+  int32_t lq_big[3];
+  int32_t tsum[6];
+  int32_t b_sc[PB];
+  int32_t b_u[PB];
+  int32_t b_b[PB];
+  ull b_f[PB];
 };
+
 
 __device__ __forceinline__ ull block_or(ull x, ull* scratch) {
 #pragma unroll
@@ -278,6 +317,398 @@ __device__ void push_desc(const MsParams& P, const MsState& S, int32_t k, int64_
   st.flush(&C.q.v, qbase, Qout);
 }
 
+
+// ---------------------------------------------------------------- team mode
+//
+// Push levels of medium frontiers (at least TEAM_MIN_Q and at most
+// QCAP * T / 2 vertices, mean degree <= LDS_MEAN_DEG, degree sum <= team_e)
+// run as a team of T workgroups from LDS queues, as in the single-source
+// kernels: each member keeps its share of the active vertices as (vertex,
+// first edge, end edge) in LDS, takes a vertex's lanes with an agent-scope
+// exchange of its current word (the word is complete: all claims of the
+// previous level came before the team exchange), claims the lanes of each
+// neighbour with atomicOr on visit (writing their depths), and appends a
+// neighbour whose next word was 0 (offsets loaded alongside) to its next
+// LDS queue.  Members share only visit and the frontier words, touched by
+// atomics.  Per level the members add one packed word to the level's team
+// word and poll it; exact per-member counts (tagged records) are read when
+// the episode ends or a share is uneven.  On exit the members write their
+// LDS queues to the global queue and meet at a team barrier; the live lanes
+// are taken as before the episode (lanes only finish; the next full-grid
+// level recomputes them) unless the frontier emptied.  The other
+// workgroups sleep.
+struct TeamSync {
+  uint32_t* arrive;
+  uint32_t* abort_flag;
+  uint32_t T;
+  uint32_t count;
+
+  __device__ bool sync(int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+};
+
+struct TeamBases {
+  ull ovf;          // team_ovf value at which the current global queue starts
+  uint32_t levels;  // team word exchanges so far
+};
+
+__device__ __forceinline__ ull team_clear_next(const MsParams& P, uint32_t level) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    return __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+__device__ bool team_fast(const MsParams& P, Lds& L, uint32_t T, uint32_t level, int32_t bcnt,
+                          int32_t bdeg, int32_t lim, ull cleared) {
+  if (threadIdx.x == 0) {
+    ull* w = &P.ctl->team_word[level % 3].v;
+    const ull g = bdeg < TW_CAP ? (ull)bdeg : (ull)TW_CAP;
+    const ull add = (1ull << TW_ARR) | ((ull)(bcnt > lim) << TW_FLAG) | ((ull)bcnt << TW_CNT) | g;
+    asm volatile("" ::"v"(cleared) : "memory");
+    __hip_atomic_fetch_add(w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    uint32_t spins = 0;
+    int bad = 0;
+    ull x;
+    for (;;) {
+      x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((x >> TW_ARR) >= T) break;
+      if ((++spins & 31u) == 0 &&
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+      if (spins > FG_SPIN_LIMIT) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    L.tsum[0] = (int32_t)((x >> TW_CNT) & ((1ull << (TW_FLAG - TW_CNT)) - 1));
+    L.tsum[1] = (int32_t)(x & ((1ull << TW_CNT) - 1));
+    L.tsum[2] = (int32_t)((x >> TW_FLAG) & ((1ull << (TW_ARR - TW_FLAG)) - 1));
+    L.flag = bad;
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+__device__ bool team_records(const MsParams& P, Lds& L, uint32_t T, uint32_t seq, int odd) {
+  const int tid = threadIdx.x;
+  if (tid < FG_WAVE) {
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    int32_t c = 0, bad = 0;
+    if ((uint32_t)tid < T) {
+      const ull* r = P.ctl->team_rec[odd][tid];
+      uint32_t spins = 0;
+      for (;;) {
+        const ull a = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(a >> 32) == seq) {
+          c = (int32_t)(uint32_t)a;
+          break;
+        }
+        if (++spins > FG_SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const int32_t keep = c < QCAP ? c : QCAP;
+    const int32_t keep_incl = fg_wave_incl_scan(keep);
+    const int32_t before = __builtin_amdgcn_readlane(keep_incl - keep, blockIdx.x);
+    const int32_t tof = fg_wave_sum(c > QCAP ? 1 : 0);
+    const int32_t tov = fg_wave_sum(c - keep);
+    int32_t mx = c;
+#pragma unroll
+    for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+      const int32_t y = __shfl_xor(mx, d, FG_WAVE);
+      mx = y > mx ? y : mx;
+    }
+    bad = fg_wave_sum(bad);
+    if (tid == 0) {
+      L.tsum[2] = tof;
+      L.tsum[3] = tov;
+      L.tsum[4] = before;
+      L.tsum[5] = mx;
+      L.flag = bad;
+    }
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+__device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
+  const int32_t incl = fg_wave_incl_scan(w);
+  const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+  int32_t base = 0;
+  if (tot) {
+    if (fg_lane() == 0) base = atomicAdd(counter, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+  }
+  return base + incl - w;
+}
+
+__device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos, int32_t v,
+                                         int32_t vb, int32_t ve, int32_t* Qo, ull* ovf,
+                                         ull ovf_base) {
+  const bool over = won && pos >= QCAP;
+  if (won && !over) {
+    L.lq_v[nxt][pos] = v;
+    L.lq_b[nxt][pos] = vb;
+    L.lq_e[nxt][pos] = ve;
+  }
+  const uint64_t om = __ballot(over);
+  if (om) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
+    base = fg_uni(base);
+    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
+  }
+}
+
+// Claim of team mode: the lanes of `fu` not yet in visit[v] (agent-scope
+// atomics only).  Returns true when v's next word was 0.
+__device__ __forceinline__ bool claim_team(const MsParams& P, ull* Fn, int32_t v, ull fu,
+                                           int32_t it1, const int32_t* start, ull& got) {
+  const ull nb = fu & ~__hip_atomic_load(&P.visit[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!nb) return false;
+  const ull nw = nb & ~atomicOr(&P.visit[v], nb);
+  if (!nw) return false;
+  got |= nw;
+  ull bits = nw;
+  while (bits) {
+    const int l = __builtin_ctzll(bits);
+    bits &= bits - 1;
+    P.depth[(int64_t)l * P.n + v] = it1 - start[l];
+  }
+  return atomicOr(&Fn[v], nw) == 0ull;
+}
+
+// Runs push levels as a team of T members while the frontier suits the
+// mode, at most `budget` levels.  Returns false on a device error.
+// *levels = levels run; *handback = 1 when the frontier met on entry does
+// not suit the mode.  On return S describes the frontier in Q[qsel] (and
+// S.live the lanes of its words).
+__device__ bool team_levels(const MsParams& P, MsState& S, Lds& L, uint32_t T, TeamSync& ts,
+                            TeamBases& tb, int32_t budget, int32_t kbase, int32_t* levels,
+                            int* handback, uint32_t& ecnt, uint32_t& vcnt) {
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  ull* ovf = &P.ctl->team_ovf.v;
+  ull ovf_base = tb.ovf;
+  int cur = 0, ci = 0, ni = 1, ri = 2;
+  *levels = 0;
+  *handback = 0;
+  // my even slice of the global frontier -> LDS queue `cur`
+  {
+    const int32_t* Qg = P.q[S.qsel];
+    const int64_t lo = S.qlen * blockIdx.x / T, hi = S.qlen * (blockIdx.x + 1) / T;
+    const int32_t cnt = (int32_t)(hi - lo);
+    int32_t sd = 0;
+    for (int32_t i = tid; i < cnt; i += PB) {
+      const int32_t u = Qg[lo + i];
+      const int32_t b = P.off[u], e = P.off[u + 1];
+      L.lq_v[cur][i] = u;
+      L.lq_b[cur][i] = b;
+      L.lq_e[cur][i] = e;
+      sd += e - b;
+    }
+    if (tid == 0) {
+      L.lq_cnt[ci] = cnt;
+      L.lq_cnt[ni] = 0;
+      L.lq_deg[ni] = 0;
+      L.lq_big[ni] = 0;
+    }
+    const int32_t bsd = fg_block_sum<PB>(sd, L.red32);
+    if (!team_fast(P, L, T, tb.levels, cnt, bsd, QCAP, team_clear_next(P, tb.levels)))
+      return false;
+    tb.levels++;
+    const int64_t qd = fg_uni(L.tsum[1]);
+    if (qd > LDS_MEAN_DEG * S.qlen || qd > P.team_e) {
+      *handback = 1;  // nothing changed; the queue and the words are intact
+      return true;
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    int32_t* Qo = P.q[S.qsel ^ 1];
+    const int nxt = cur ^ 1;
+    const int32_t cnt = L.lq_cnt[ci];
+    const ull cleared2 = team_clear_next(P, tb.levels);
+    if (tid == 0) {
+      L.lq_cnt[ri] = 0;
+      L.lq_deg[ri] = 0;
+      L.lq_big[ri] = 0;
+    }
+    ull* Fc = P.F[S.fsel];
+    ull* Fn = P.F[S.fsel ^ 1];
+    const int32_t it1 = S.it + 1;
+    ull got = 0;
+    bool big = false;
+    // vertices of degree <= TPV: TPV lanes per vertex, one edge each; the
+    // first takes (and clears) the vertex's current word
+    for (int32_t c0 = 0; c0 < cnt; c0 += PB / TPV) {
+      const int32_t i = c0 + tid / TPV;
+      const int32_t j = tid % TPV;
+      int32_t u = 0, b = 0, d = 0;
+      ull fu = 0;
+      if (i < cnt) {
+        u = L.lq_v[cur][i];
+        b = L.lq_b[cur][i];
+        d = L.lq_e[cur][i] - b;
+        if (j == 0 && d <= TPV) {
+          // vertices of degree > TPV take their word in the scan-gather below
+          fu = __hip_atomic_exchange(&Fc[u], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ecnt += (uint32_t)d;
+          vcnt += fu != 0ull;
+        }
+      }
+      // the word to the vertex's other lanes (the first lane of the group)
+      fu = __shfl(fu, (int)(threadIdx.x % FG_WAVE) & ~(TPV - 1), FG_WAVE);
+      big |= d > TPV;
+      bool won = false;
+      int32_t v = 0, vb = 0, ve = 0;
+      if (d <= TPV && j < d && fu) {
+        v = P.col[b + j];
+        vb = P.off[v];
+        ve = P.off[v + 1];
+        won = claim_team(P, Fn, v, fu, it1, L.start, got);
+      }
+      const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+      const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+      if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+      wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+    }
+    if (big) L.lq_big[ni] = 1;
+    __syncthreads();
+    if (L.lq_big[ni]) {
+      // vertices of degree > TPV: block scan-gather over their edges
+      for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
+        const int32_t i = c0 + tid;
+        int32_t u = 0, b = 0, d = 0;
+        ull fu = 0;
+        if (i < cnt) {
+          u = L.lq_v[cur][i];
+          b = L.lq_b[cur][i];
+          d = L.lq_e[cur][i] - b;
+          if (d > TPV) {
+            fu = __hip_atomic_exchange(&Fc[u], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ecnt += (uint32_t)d;
+            vcnt += fu != 0ull;
+          }
+        }
+        if (d <= TPV || !fu) d = 0;
+        int32_t Tn = 0;
+        const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &Tn);
+        L.b_sc[tid] = ex;
+        L.b_u[tid] = u;
+        L.b_b[tid] = b;
+        L.b_f[tid] = fu;
+        __syncthreads();
+        const int32_t nc = cnt - c0 < PB ? cnt - c0 : PB;
+        for (int32_t t0 = 0; t0 < Tn; t0 += PB) {
+          const int32_t t = t0 + tid;
+          bool won = false;
+          int32_t v = 0, vb = 0, ve = 0;
+          if (t < Tn) {
+            const int32_t jj = upper_idx(L.b_sc, nc, t);
+            v = P.col[L.b_b[jj] + (t - L.b_sc[jj])];
+            vb = P.off[v];
+            ve = P.off[v + 1];
+            won = claim_team(P, Fn, v, L.b_f[jj], it1, L.start, got);
+          }
+          const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+          const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+          if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+          wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+        }
+        __syncthreads();
+      }
+    }
+    const int32_t bcnt = L.lq_cnt[ni];
+    const int32_t bdeg = L.lq_deg[ni];
+    if (tid == 0) {
+      ull* rr = P.ctl->team_rec[S.it & 1][blockIdx.x];
+      const ull tag = (ull)((uint32_t)S.it + 1u) << 32;
+      __hip_atomic_store(rr, tag | (uint32_t)bcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t lim = (5 * S.qlen / T + 64) / 4;
+    if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP), cleared2))
+      return false;
+    tb.levels++;
+    const int64_t nq = fg_uni(L.tsum[0]);
+    const int64_t nqdeg = fg_uni(L.tsum[1]);
+    const int64_t nflag = fg_uni(L.tsum[2]);
+    S.it = it1;
+    S.qlen = nq;
+    S.fsel ^= 1;
+    (*levels)++;
+    bool stay = nq >= TEAM_MIN_Q && nqdeg <= LDS_MEAN_DEG * nq && nqdeg <= P.team_e &&
+                nq <= (int64_t)QCAP * T / 2 && nq <= P.n / P.pull_div && *levels < budget;
+    int64_t nover = bcnt > QCAP ? bcnt - QCAP : 0, before = 0;
+    bool rebalance = false;
+    if (!stay || nflag) {
+      if (!team_records(P, L, T, (uint32_t)S.it, (S.it - 1) & 1)) return false;
+      nover = fg_uni(L.tsum[3]);
+      before = fg_uni(L.tsum[4]);
+      stay = stay && fg_uni(L.tsum[2]) == 0;
+      rebalance = stay && 4 * fg_uni(L.tsum[5]) * (int64_t)T > 5 * nq + 64 * (int64_t)T;
+    }
+    if (!stay || rebalance) {
+      // global queue: the overflow entries, then every member's LDS queue
+      // in member order
+      const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
+      int32_t* dst = Qo + nover + before;
+      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      ovf_base += (ull)nover;
+      tb.ovf = ovf_base;
+      // the live word of the next full-grid level starts at zero (cleared
+      // before the barrier, which every member passes before using it)
+      if (!stay && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(&P.ctl->livew[(kbase + *levels) % 3].v, 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      if (!ts.sync(&L.flag)) return false;
+      S.qsel ^= 1;
+      if (!stay) {
+        if (nq == 0) S.live = 0ull;
+        return true;
+      }
+      // reload an even share from the global queue
+      {
+        const int32_t* Qg = P.q[S.qsel];
+        const int64_t lo = S.qlen * blockIdx.x / T, hi = S.qlen * (blockIdx.x + 1) / T;
+        const int32_t c2 = (int32_t)(hi - lo);
+        for (int32_t i = tid; i < c2; i += PB) {
+          const int32_t u = Qg[lo + i];
+          L.lq_v[nxt][i] = u;
+          L.lq_b[nxt][i] = P.off[u];
+          L.lq_e[nxt][i] = P.off[u + 1];
+        }
+        __syncthreads();
+        if (tid == 0) L.lq_cnt[ni] = c2;
+        __syncthreads();
+      }
+    }
+    cur = nxt;
+    const int t3 = ci;
+    ci = ni;
+    ni = ri;
+    ri = t3;
+  }
+}
+
 __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -338,9 +769,69 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
   if (threadIdx.x < MAXL) L.start[threadIdx.x] = P.state->start[threadIdx.x];
   __syncthreads();
   uint32_t ecnt = 0, vcnt = 0;  // per-thread counts stay far below 2^32
+  TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)(P.team > 1 ? P.team : 1),
+              0u};
+  TeamBases tb = {};
+  uint32_t sm_seen = 0;
+  int force_full = 0;
   for (int32_t k = 0; ok && k < P.k_iters && S.live != 0ull; ++k) {
     const int32_t it1 = S.it + 1;
     const bool want_pull = S.mode == 0 ? S.qlen > P.n / P.pull_div : S.qlen >= P.n / P.push_div;
+    // ---- push levels of medium frontiers as a team (the others sleep)
+    if (!force_full && S.mode == 0 && !want_pull && P.team > 1 && S.qlen >= TEAM_MIN_Q &&
+        S.qlen <= (int64_t)QCAP * P.team / 2) {
+      sm_seen++;
+      int32_t nl = 0;
+      if (blockIdx.x < (uint32_t)P.team) {
+        int hb = 0;
+        if (!team_levels(P, S, L, (uint32_t)P.team, ts, tb, P.k_iters - k, k, &nl, &hb, ecnt,
+                         vcnt))
+          ok = false;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          MsCtl* c = P.ctl;
+          c->pub_it = S.it;
+          c->pub_qsel = S.qsel;
+          c->pub_fsel = S.fsel;
+          c->pub_levels = nl;
+          c->pub_force = hb;
+          c->pub_tqlen = S.qlen;
+          c->pub_tlive = S.live;
+          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        force_full = hb;
+        __syncthreads();
+        if (!ok) break;
+      } else {
+        if (threadIdx.x == 0) {
+          const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
+          L.flag = bad;
+          if (!bad) {
+            const MsCtl* c = P.ctl;
+            L.bcast[0] = c->pub_it;
+            L.bcast[1] = c->pub_qsel | ((int64_t)c->pub_fsel << 8) | ((int64_t)c->pub_force << 16);
+            L.bcast[2] = c->pub_levels;
+            L.bcast[3] = c->pub_tqlen;
+            L.redu[0] = c->pub_tlive;
+          }
+        }
+        __syncthreads();
+        if (L.flag) {
+          ok = false;
+          break;
+        }
+        S.it = (int32_t)L.bcast[0];
+        S.qsel = (int32_t)(L.bcast[1] & 0xff);
+        S.fsel = (int32_t)((L.bcast[1] >> 8) & 0xff);
+        force_full = (int)((L.bcast[1] >> 16) & 0xff);
+        nl = (int32_t)L.bcast[2];
+        S.qlen = L.bcast[3];
+        S.live = L.redu[0];
+        __syncthreads();
+      }
+      k += nl - 1;  // the loop adds the last one
+      continue;
+    }
+    force_full = 0;
     CtrSlot& C = P.ctl->slot[k & 1];
     const bool odd = k & 1;
     const ull msk = 0ull - (ull)odd;
@@ -737,6 +1228,12 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   void* args[] = {&P};
   int grid = pr.cus * bpc;
   if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
+  P.team = b->opts.team_blocks > 0 ? b->opts.team_blocks : (b->opts.team_blocks < 0 ? 1 : DEF_TEAM);
+  if (P.team > TEAM_MAX) P.team = TEAM_MAX;
+  if (P.team > grid) P.team = grid;
+  P.team_e = b->opts.team_edges > 0 ? b->opts.team_edges : DEF_TEAM_E;
+  if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
+
   FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)msbfs_persistent, dim3(grid),
                                         dim3(PB), args, 0, (hipStream_t)stream));
   b->npend = 0;

@@ -110,6 +110,40 @@ def test_grid_64_sources_closed_form(fg):
         assert np.array_equal(to_np(b.read(lane)), np.abs(rr - r0) + np.abs(cc - c0))
 
 
+@pytest.mark.parametrize("team,team_e,lanes", [(32, 0, 1), (32, 0, 8), (2, 0, 5), (7, 0, 64),
+                                               (64, 0, 3), (32, 300, 8), (-1, 0, 8)])
+def test_team_levels(fg, orc, team, team_e, lanes):
+    # grid levels run as a team; k_iters=3 ends episodes in mid-flight and
+    # the next step resumes them; lanes are admitted between steps
+    R, C = 150, 170
+    off, col = synth.grid_csr(R, C)
+    g = fg.Graph(off, col)
+    rng = np.random.default_rng(abs(team) * 100 + lanes)
+    srcs = {int(l): int(s) for l, s in zip(rng.choice(64, lanes, replace=False),
+                                           rng.choice(R * C, lanes, replace=False))}
+    announce(f"msbfs team={team} team_e={team_e} lanes={lanes}")
+    b = fg.MsBatch(g, 64, fg.msbfs_opts(team_blocks=team, team_edges=team_e))
+    items = list(srcs.items())
+    half = len(items) // 2
+    for lane, s in items[:half]:
+        b.admit(lane, s)
+    if half:
+        b.step(3)
+    for lane, s in items[half:]:
+        b.admit(lane, s)
+    b.run(k_iters=3)
+    check_lanes(fg, orc, b, off, col, srcs)
+    # R-MAT with pull off: push levels of every shape, hubs included
+    off, col = synth.rmat_csr(13)
+    g = fg.Graph(off, col)
+    srcs = {i: int(s) for i, s in enumerate(synth.sources(off, lanes, seed=abs(team) + 50))}
+    b = fg.MsBatch(g, 64, fg.msbfs_opts(team_blocks=team, team_edges=team_e, pull_div=1))
+    for lane, s in srcs.items():
+        b.admit(lane, s)
+    b.run(k_iters=5)
+    check_lanes(fg, orc, b, off, col, srcs)
+
+
 def test_msbfs_argument_errors(fg):
     off, col = synth.from_edge_pairs(4, [(0, 1)])
     g = fg.Graph(off, col)
