@@ -310,9 +310,10 @@ typedef struct {
   int32_t grid_blocks;   /* workgroups of the persistent launch (0 = every CU x
                             blocks_per_cu)                                          */
   int32_t team_blocks;   /* workgroups that run push levels of medium frontiers from
-                            LDS queues as a team (0 = 32, -1 = no team)             */
+                            LDS queues as a team (0 = 32 while fewer than 4 lanes
+                            hold queries, 64 otherwise; -1 = no team)               */
   int32_t team_edges;    /* ... while the frontier's degree sum is at most this
-                            (0 = 65536)                                             */
+                            (0 = 262144)                                            */
 } fg_msbfs_opts;
 
 void fg_msbfs_opts_default(fg_msbfs_opts* opts);

@@ -51,8 +51,11 @@ constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
 constexpr int64_t TW_CAP = (1 << 19) - 1;
 constexpr int LDS_MEAN_DEG = 64;
 constexpr int TPV = 4;
+// default team: 32 workgroups for up to 3 lanes, 64 for more (their union
+// frontier is wider); degree sums up to 2^18 per level
 constexpr int32_t DEF_TEAM = 32;
-constexpr int64_t DEF_TEAM_E = 65536;
+constexpr int32_t DEF_TEAM_WIDE = 64;
+constexpr int64_t DEF_TEAM_E = 1 << 18;
 constexpr int32_t TEAM_MIN_Q = 1;
 
 struct MsState {
@@ -1228,7 +1231,10 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   void* args[] = {&P};
   int grid = pr.cus * bpc;
   if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
-  P.team = b->opts.team_blocks > 0 ? b->opts.team_blocks : (b->opts.team_blocks < 0 ? 1 : DEF_TEAM);
+  const int lanes_in = __builtin_popcountll(b->admitted);
+  P.team = b->opts.team_blocks > 0 ? b->opts.team_blocks
+           : b->opts.team_blocks < 0 ? 1
+           : (lanes_in >= 4 ? DEF_TEAM_WIDE : DEF_TEAM);
   if (P.team > TEAM_MAX) P.team = TEAM_MAX;
   if (P.team > grid) P.team = grid;
   P.team_e = b->opts.team_edges > 0 ? b->opts.team_edges : DEF_TEAM_E;

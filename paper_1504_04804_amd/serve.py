@@ -260,7 +260,8 @@ class Server:
 
 def calibrate(graphs, sources_per_graph, stream=None):
     """Measure the cost model of every graph and kind: single-source runs
-    (one warm-up, two timed) and batches of 1 and 8 lanes run to the end.
+    (one warm-up, two timed) and batches of 1 and 8 lanes run to the end
+    (the faster of two runs each).
     sources_per_graph: dict name -> at least 8 source vertices."""
     stream = stream if stream is not None else torch.cuda.current_stream()
     costs = {}
@@ -301,8 +302,13 @@ def calibrate(graphs, sources_per_graph, stream=None):
                 return t, it1 - it0
 
             batch_run(srcs[:1])
-            t1, _ = batch_run(srcs[1:2])
+            # the faster of two runs: one-off stalls (a first touch of fresh
+            # workspace memory) must not set the model
+            t1 = min(batch_run(srcs[1:2])[0], batch_run(srcs[2:3])[0])
             t8, it8 = batch_run(srcs[:8])
+            t8b, it8b = batch_run(srcs[:8])
+            if t8b < t8:
+                t8, it8 = t8b, it8b
             b.close()
             del ws
             costs[(name, kind)] = Cost(single, t1, t8, t8 / max(it8, 1))
