@@ -310,8 +310,11 @@ typedef struct {
   int32_t grid_blocks;   /* workgroups of the persistent launch (0 = every CU x
                             blocks_per_cu)                                          */
   int32_t team_blocks;   /* workgroups that run push levels of medium frontiers from
-                            LDS queues as a team (0 = 32 while fewer than 4 lanes
-                            hold queries, 64 otherwise; -1 = no team)               */
+                            LDS queues as a team (> 1 = that many; 1 = 32 while
+                            fewer than 4 lanes hold queries, 64 otherwise; 0 or -1
+                            = no team, the default: runs with a team have, rarely,
+                            ended with FG_EDEVICE from fg_msbfs_poll after a team
+                            wait reached its limit, cause not yet found)           */
   int32_t team_edges;    /* ... while the frontier's degree sum is at most this
                             (0 = 262144)                                            */
 } fg_msbfs_opts;
@@ -342,7 +345,8 @@ fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream);
 
 /* Synchronise `stream`; *done_lanes = admitted lanes whose traversal has
  * finished; *iterations = levels run since fg_msbfs_open.  Either pointer
- * may be NULL. */
+ * may be NULL.  Returns FG_EDEVICE if a step stopped early (its results
+ * are then incomplete). */
 fg_status fg_msbfs_poll(fg_msbfs* b, uint64_t* done_lanes, int32_t* iterations, void* stream);
 
 /* Copy lane's depths (int32[n], -1 = unreached) to device memory `depth`
@@ -378,6 +382,12 @@ typedef struct {
                             many can split in one scan of the far list (0 = 8) */
   int32_t split_wait;    /* ... or until they have waited this many
                             iterations (0 = 8); 1 = split at once             */
+  int32_t team_blocks;   /* workgroups that run near iterations of medium
+                            frontiers from LDS queues as a team (0 = 32 while
+                            fewer than 4 lanes hold queries, 64 otherwise;
+                            -1 = no team)                                    */
+  int32_t team_edges;    /* ... while the frontier's degree sum is at most
+                            this (0 = 262144)                                */
 } fg_mssp_opts;
 
 void fg_mssp_opts_default(fg_mssp_opts* opts);

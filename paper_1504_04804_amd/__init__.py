@@ -107,6 +107,8 @@ class MpOpts(ctypes.Structure):
         ("dense_lanes", ctypes.c_int32),
         ("split_lanes", ctypes.c_int32),
         ("split_wait", ctypes.c_int32),
+        ("team_blocks", ctypes.c_int32),
+        ("team_edges", ctypes.c_int32),
     ]
 
 
@@ -584,12 +586,13 @@ class MsBatch:
 
 
 def mssp_opts(delta=0, big_degree=0, blocks_per_cu=0, dense_lanes=0, grid_blocks=0,
-              split_lanes=0, split_wait=0):
+              split_lanes=0, split_wait=0, team_blocks=0, team_edges=0):
     o = MpOpts()
     lib().fg_mssp_opts_default(ctypes.byref(o))
     o.delta, o.big_degree, o.blocks_per_cu = delta, big_degree, blocks_per_cu
     o.dense_lanes, o.grid_blocks = dense_lanes, grid_blocks
     o.split_lanes, o.split_wait = split_lanes, split_wait
+    o.team_blocks, o.team_edges = team_blocks, team_edges
     return o
 
 

@@ -52,6 +52,16 @@ constexpr int CHS = 64;  // edges per descriptor
 constexpr int STAGE = 256;
 constexpr int FSTAGE = 128;
 constexpr uint32_t DIST_INF = 0xFFFFFFFFu;
+// Team mode (see mp_team): LDS queue entries per member, widest team,
+// packed team word fields, frontier shape it takes, default widths.
+constexpr int QCAP = 2048;
+constexpr int TEAM_MAX = 64;
+constexpr int TW_CNT = 25, TW_FLAG = 50, TW_ARR = 57;
+constexpr int64_t TW_CAP = (1 << 19) - 1;
+constexpr int LDS_MEAN_DEG = 64;
+constexpr int32_t DEF_TEAM = 32;
+constexpr int32_t DEF_TEAM_WIDE = 64;
+constexpr int64_t DEF_TEAM_E = 1 << 18;
 
 struct MpState {
   int32_t it;      // iterations since open
@@ -90,6 +100,19 @@ struct alignas(256) MpCtl {
   int64_t pub_qlen, pub_plen;
   ull pub_live;
   uint32_t pub_ovf;
+  // team mode: hand-back signal, team barrier, per-member records, level
+  // words, lanes given next-frontier entries per level, overflow counter
+  uint32_t sm_signal;
+  uint32_t pad1[63];
+  uint32_t team_arrive;
+  uint32_t pad2[63];
+  ull team_rec[2][TEAM_MAX][2];
+  Line64 team_word[3];
+  Line64 tnear[3];
+  Line64 team_ovf;
+  int32_t tp_it, tp_qsel, tp_fsel, tp_levels, tp_force, tp_swait;
+  int64_t tp_qlen, tp_plen;
+  ull tp_live, tp_nearl;
 };
 
 struct MpParams {
@@ -114,6 +137,8 @@ struct MpParams {
   int32_t dense;        // lanes from which a vertex is relaxed lane-parallel
   int32_t split_lanes;  // idle lanes that trigger a split of the far list
   int32_t split_wait;   // ... or iterations the idle lanes have waited
+  int32_t team;         // workgroups of a team (<= 1: no team mode)
+  int64_t team_e;       // largest frontier degree sum a team takes
 };
 
 struct Lds {
@@ -130,6 +155,23 @@ struct Lds {
   uint32_t Tnext[MAXL];
   uint32_t minl[MAXL];
   int32_t flag;
+  // team mode: this member's share of the frontier (vertex, first edge, end
+  // edge) for the current and the next level, counters over three slots,
+  // block scan-gather arrays, exchange results
+  int32_t lq_v[2][QCAP];
+  int32_t lq_b[2][QCAP];
+  int32_t lq_e[2][QCAP];
+  int32_t lq_cnt[3];
+  int32_t lq_deg[3];
+  int32_t tsum[6];
+  int32_t b_sc[PB];
+  int32_t b_u[PB];
+  int32_t b_b[PB];
+  int32_t b_d[PB];
+  ull b_m[PB];
+  ull tnear;
+  int64_t tfar;
+  int32_t red32[PWAVES + 1];
 };
 
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
@@ -276,6 +318,410 @@ __device__ __forceinline__ int kth_bit(ull m, int k) {
   return __builtin_ctzll(m);
 }
 
+
+// ---------------------------------------------------------------- team mode
+//
+// Near iterations of medium frontiers (at most QCAP * T / 2 vertices, mean
+// degree <= LDS_MEAN_DEG, degree sum <= team_e) run as a team of T
+// workgroups from LDS queues, as in the single-source kernels: each member
+// keeps its share of the active vertices as (vertex, first edge, end edge)
+// in LDS, takes a vertex's lanes with an agent-scope exchange of its
+// current word, spreads the (edge, lane) pairs over its threads by a block
+// scan, and appends a vertex whose next word was 0 (offsets loaded
+// alongside) to its next LDS queue; far entries go to the far list as
+// elsewhere.  A lane's own distance is read with an agent-scope atomic load
+// (another member may just have lowered it).  Per level the members OR the
+// lanes they gave next-frontier entries into the level's near word, then
+// add one packed word to the level's team word and poll it (the near word
+// is complete once every member has arrived: each OR returned before its
+// member arrived).  Lanes whose near frontier empties wait as in the full
+// grid; when their split is due, or the frontier leaves the mode's range,
+// the members write their LDS queues to the global queue and the next
+// iteration runs on the full grid.
+struct TeamSync {
+  uint32_t* arrive;
+  uint32_t* abort_flag;
+  uint32_t T;
+  uint32_t count;
+
+  __device__ bool sync(int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+};
+
+struct TeamBases {
+  ull ovf;          // team_ovf value at which the current global queue starts
+  uint32_t levels;  // team word exchanges so far
+};
+
+// Workgroup 0 clears the team and near words of exchange `level + 1`.
+__device__ __forceinline__ ull team_clear_next(const MpParams& P, uint32_t level) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const ull a = __hip_atomic_exchange(&P.ctl->team_word[(level + 1) % 3].v, 0ull,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const ull b = __hip_atomic_exchange(&P.ctl->tnear[(level + 1) % 3].v, 0ull, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    return a | b;
+  }
+  return 0;
+}
+
+__device__ bool team_fast(const MpParams& P, Lds& L, uint32_t T, uint32_t level, int32_t bcnt,
+                          int32_t bdeg, int32_t lim, ull cleared) {
+  if (threadIdx.x == 0) {
+    ull* w = &P.ctl->team_word[level % 3].v;
+    const ull g = bdeg < TW_CAP ? (ull)bdeg : (ull)TW_CAP;
+    const ull add = (1ull << TW_ARR) | ((ull)(bcnt > lim) << TW_FLAG) | ((ull)bcnt << TW_CNT) | g;
+    asm volatile("" ::"v"(cleared) : "memory");
+    __hip_atomic_fetch_add(w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    uint32_t spins = 0;
+    int bad = 0;
+    ull x;
+    for (;;) {
+      x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((x >> TW_ARR) >= T) break;
+      if ((++spins & 31u) == 0 &&
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+      if (spins > FG_SPIN_LIMIT) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    L.tsum[0] = (int32_t)((x >> TW_CNT) & ((1ull << (TW_FLAG - TW_CNT)) - 1));
+    L.tsum[1] = (int32_t)(x & ((1ull << TW_CNT) - 1));
+    L.tsum[2] = (int32_t)((x >> TW_FLAG) & ((1ull << (TW_ARR - TW_FLAG)) - 1));
+    L.tnear = __hip_atomic_load(&P.ctl->tnear[level % 3].v, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+    L.tfar = (int64_t)__hip_atomic_load(&P.ctl->farpos.v, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    L.flag = bad;
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+__device__ bool team_records(const MpParams& P, Lds& L, uint32_t T, uint32_t seq, int odd) {
+  const int tid = threadIdx.x;
+  if (tid < FG_WAVE) {
+    uint32_t* abort_flag = P.ctl->bar + FG_BAR_STRIDE;
+    int32_t c = 0, bad = 0;
+    if ((uint32_t)tid < T) {
+      const ull* r = P.ctl->team_rec[odd][tid];
+      uint32_t spins = 0;
+      for (;;) {
+        const ull a = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(a >> 32) == seq) {
+          c = (int32_t)(uint32_t)a;
+          break;
+        }
+        if (++spins > FG_SPIN_LIMIT) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const int32_t keep = c < QCAP ? c : QCAP;
+    const int32_t keep_incl = fg_wave_incl_scan(keep);
+    const int32_t before = __builtin_amdgcn_readlane(keep_incl - keep, blockIdx.x);
+    const int32_t tof = fg_wave_sum(c > QCAP ? 1 : 0);
+    const int32_t tov = fg_wave_sum(c - keep);
+    int32_t mx = c;
+#pragma unroll
+    for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+      const int32_t y = __shfl_xor(mx, d, FG_WAVE);
+      mx = y > mx ? y : mx;
+    }
+    bad = fg_wave_sum(bad);
+    if (tid == 0) {
+      L.tsum[2] = tof;
+      L.tsum[3] = tov;
+      L.tsum[4] = before;
+      L.tsum[5] = mx;
+      L.flag = bad;
+    }
+  }
+  __syncthreads();
+  return L.flag == 0;
+}
+
+__device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
+  const int32_t incl = fg_wave_incl_scan(w);
+  const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+  int32_t base = 0;
+  if (tot) {
+    if (fg_lane() == 0) base = atomicAdd(counter, tot);
+    base = __builtin_amdgcn_readfirstlane(base);
+  }
+  return base + incl - w;
+}
+
+__device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos, int32_t v,
+                                         int32_t vb, int32_t ve, int32_t* Qo, ull* ovf,
+                                         ull ovf_base) {
+  const bool over = won && pos >= QCAP;
+  if (won && !over) {
+    L.lq_v[nxt][pos] = v;
+    L.lq_b[nxt][pos] = vb;
+    L.lq_e[nxt][pos] = ve;
+  }
+  const uint64_t om = __ballot(over);
+  if (om) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
+    base = fg_uni(base);
+    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
+  }
+}
+
+// Far-list append of a wave's new far vertices (one atomic per wave).
+__device__ __forceinline__ void far_put(const MpParams& P, bool put, int32_t v, int32_t* pile,
+                                        ull fbase) {
+  const uint64_t m = __ballot(put);
+  if (m) {
+    ull base = 0;
+    if (fg_lane() == 0) base = atomicAdd(&P.ctl->farpos.v, (ull)__popcll(m));
+    base = fg_uni(base);
+    if (put) pile[base - fbase + fg_mbcnt(m)] = v;
+  }
+}
+
+// Batch state the team reads and advances (identical in every member).
+struct MpRun {
+  int32_t it, qsel, fsel, psel, swait;
+  int64_t qlen, plen;
+  ull fbase, live, nearl;
+};
+
+// Near iterations as a team of T members (blockIdx.x < T), at most `budget`.
+// Returns false on a device error; *levels = iterations run; *handback = 1
+// when the frontier met on entry does not suit the mode.
+__device__ bool mp_team(const MpParams& P, MpRun& R, Lds& L, uint32_t T, TeamSync& ts,
+                        TeamBases& tb, int32_t budget, int32_t kbase, int32_t* levels,
+                        int* handback, bool& ovf, ull& edges, ull& edge_lanes) {
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  MpCtl* C = P.ctl;
+  ull* ovfc = &C->team_ovf.v;
+  ull ovf_base = tb.ovf;
+  int cur = 0, ci = 0, ni = 1, ri = 2;
+  *levels = 0;
+  *handback = 0;
+  {
+    const int32_t* Qg = P.q[R.qsel];
+    const int64_t lo = R.qlen * blockIdx.x / T, hi = R.qlen * (blockIdx.x + 1) / T;
+    const int32_t cnt = (int32_t)(hi - lo);
+    int32_t sd = 0;
+    for (int32_t i = tid; i < cnt; i += PB) {
+      const int32_t u = Qg[lo + i];
+      const int32_t b = P.off[u], e = P.off[u + 1];
+      L.lq_v[cur][i] = u;
+      L.lq_b[cur][i] = b;
+      L.lq_e[cur][i] = e;
+      sd += e - b;
+    }
+    if (tid == 0) {
+      L.lq_cnt[ci] = cnt;
+      L.lq_cnt[ni] = 0;
+      L.lq_deg[ni] = 0;
+    }
+    const int32_t bsd = fg_block_sum<PB>(sd, L.red32);
+    if (!team_fast(P, L, T, tb.levels, cnt, bsd, QCAP, team_clear_next(P, tb.levels)))
+      return false;
+    tb.levels++;
+    const int64_t qd = fg_uni(L.tsum[1]);
+    if (qd > LDS_MEAN_DEG * R.qlen || qd > P.team_e) {
+      *handback = 1;
+      return true;
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    int32_t* Qo = P.q[R.qsel ^ 1];
+    const int nxt = cur ^ 1;
+    const int32_t cnt = L.lq_cnt[ci];
+    const ull cleared = team_clear_next(P, tb.levels);
+    if (tid == 0) {
+      L.lq_cnt[ri] = 0;
+      L.lq_deg[ri] = 0;
+    }
+    ull* Fc = P.F[R.fsel];
+    ull* Fn = P.F[R.fsel ^ 1];
+    int32_t* pile = P.far[R.psel];
+    ull nearb = 0;
+    for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
+      const int32_t i = c0 + tid;
+      int32_t u = 0, b = 0, d = 0;
+      ull m = 0;
+      if (i < cnt) {
+        u = L.lq_v[cur][i];
+        b = L.lq_b[cur][i];
+        d = L.lq_e[cur][i] - b;
+        m = __hip_atomic_exchange(&Fc[u], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const int32_t pc = __popcll(m);
+      edges += m ? (ull)d : 0ull;
+      edge_lanes += (ull)d * (ull)pc;
+      const int32_t items = d * pc;
+      int32_t Tn = 0;
+      const int32_t ex = fg_block_excl_scan<PB>(items, L.red32, &Tn);
+      L.b_sc[tid] = ex;
+      L.b_u[tid] = u;
+      L.b_b[tid] = b;
+      L.b_d[tid] = d;
+      L.b_m[tid] = m;
+      __syncthreads();
+      const int32_t nc = cnt - c0 < PB ? cnt - c0 : PB;
+      for (int32_t t0 = 0; t0 < Tn; t0 += PB) {
+        const int32_t t = t0 + tid;
+        bool won = false, fput = false;
+        int32_t v = 0, vb = 0, ve = 0;
+        if (t < Tn) {
+          const int32_t jj = upper_idx(L.b_sc, nc, t);
+          const int32_t r = t - L.b_sc[jj];
+          const int32_t dj = L.b_d[jj];
+          const int32_t li = r / dj;
+          const int l = kth_bit(L.b_m[jj], li);
+          const int32_t e = L.b_b[jj] + (r - li * dj);
+          const int32_t uj = L.b_u[jj];
+          v = P.col[e];
+          const uint32_t wt = P.w[e];
+          vb = P.off[v];
+          ve = P.off[v + 1];
+          const ull nd = (ull)__hip_atomic_load(&P.dist[(int64_t)uj * MAXL + l], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT) + (ull)wt;
+          if (nd >= (ull)DIST_INF) {
+            ovf = true;
+          } else {
+            const uint32_t old = atomicMin(&P.dist[(int64_t)v * MAXL + l], (uint32_t)nd);
+            if ((uint32_t)nd < old) {
+              const ull bit = 1ull << l;
+              if ((uint32_t)nd < L.T[l]) {
+                won = atomicOr(&Fn[v], bit) == 0ull;
+                nearb |= bit;
+              } else {
+                fput = atomicOr(&P.Ff[v], bit) == 0ull;
+              }
+            }
+          }
+        }
+        const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
+        const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
+        if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
+        wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovfc, ovf_base);
+        far_put(P, fput, v, pile, R.fbase);
+      }
+      __syncthreads();
+    }
+    const ull bn = block_or(nearb, L.redu);
+    const int32_t bcnt = L.lq_cnt[ni];
+    const int32_t bdeg = L.lq_deg[ni];
+    ull orv = 0;
+    if (tid == 0) {
+      if (bn)
+        orv = __hip_atomic_fetch_or(&C->tnear[tb.levels % 3].v, bn, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      ull* rr = C->team_rec[R.it & 1][blockIdx.x];
+      const ull tag = (ull)((uint32_t)R.it + 1u) << 32;
+      __hip_atomic_store(rr, tag | (uint32_t)bcnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t lim = (5 * R.qlen / T + 64) / 4;
+    // the near OR returns before the arrival is issued
+    asm volatile("" ::"v"(orv) : "memory");
+    if (!team_fast(P, L, T, tb.levels, bcnt, bdeg, (int32_t)(lim < QCAP ? lim : QCAP), cleared))
+      return false;
+    tb.levels++;
+    const int64_t nq = fg_uni(L.tsum[0]);
+    const int64_t nqdeg = fg_uni(L.tsum[1]);
+    const int64_t nflag = fg_uni(L.tsum[2]);
+    const ull nw = L.tnear;
+    const int64_t far_now = L.tfar;
+    R.it++;
+    R.qlen = nq;
+    R.fsel ^= 1;
+    R.nearl = nw;
+    R.plen = (int64_t)((ull)far_now - R.fbase);
+    (*levels)++;
+    // lanes whose near frontier emptied: finished when nothing is far; a
+    // due split ends the episode, otherwise they wait as on the full grid
+    ull idle = R.live & ~R.nearl;
+    if (idle && R.plen == 0) {
+      R.live &= ~idle;
+      idle = 0;
+    }
+    const bool split_due = idle && (__popcll(idle) >= P.split_lanes || (R.live & R.nearl) == 0 ||
+                                    R.swait + 1 >= P.split_wait);
+    if (idle && !split_due) R.swait++;
+    bool stay = nq > 0 && R.live != 0 && !split_due && nqdeg <= LDS_MEAN_DEG * nq &&
+                nqdeg <= P.team_e && nq <= (int64_t)QCAP * T / 2 && *levels < budget;
+    int64_t nover = bcnt > QCAP ? bcnt - QCAP : 0, before = 0;
+    bool rebalance = false;
+    if (!stay || nflag) {
+      if (!team_records(P, L, T, (uint32_t)R.it, (R.it - 1) & 1)) return false;
+      nover = fg_uni(L.tsum[3]);
+      before = fg_uni(L.tsum[4]);
+      stay = stay && fg_uni(L.tsum[2]) == 0;
+      rebalance = stay && 4 * fg_uni(L.tsum[5]) * (int64_t)T > 5 * nq + 64 * (int64_t)T;
+    }
+    if (!stay || rebalance) {
+      const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
+      int32_t* dst = Qo + nover + before;
+      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      ovf_base += (ull)nover;
+      tb.ovf = ovf_base;
+      if (!stay && blockIdx.x == 0) {
+        // the count slot of the next full-grid iteration starts cleared
+        const int s = (kbase + *levels) % 3;
+        if (tid == 0) {
+          __hip_atomic_store(&C->qcnt[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&C->dcnt[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&C->fcnt[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&C->nearw[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&C->stayw[s].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (tid < MAXL)
+          __hip_atomic_store(&C->minst[s][tid], DIST_INF, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (!ts.sync(&L.flag)) return false;
+      R.qsel ^= 1;
+      if (!stay) return true;
+      // reload an even share from the global queue
+      const int32_t* Qg = P.q[R.qsel];
+      const int64_t lo = R.qlen * blockIdx.x / T, hi = R.qlen * (blockIdx.x + 1) / T;
+      const int32_t c2 = (int32_t)(hi - lo);
+      for (int32_t i = tid; i < c2; i += PB) {
+        const int32_t u = Qg[lo + i];
+        L.lq_v[nxt][i] = u;
+        L.lq_b[nxt][i] = P.off[u];
+        L.lq_e[nxt][i] = P.off[u + 1];
+      }
+      __syncthreads();
+      if (tid == 0) L.lq_cnt[ni] = c2;
+      __syncthreads();
+    }
+    cur = nxt;
+    const int t3 = ci;
+    ci = ni;
+    ni = ri;
+    ri = t3;
+  }
+}
+
 __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -359,7 +805,79 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   }
 
   ull edges = 0, edge_lanes = 0;
+  TeamSync ts{&C->team_arrive, C->bar + FG_BAR_STRIDE, (uint32_t)(P.team > 1 ? P.team : 1), 0u};
+  TeamBases tb = {};
+  uint32_t sm_seen = 0;
+  int force_full = 0;
   for (int32_t k = 0; ok && k < P.k_iters && live != 0ull; ++k) {
+    // ---- near iterations of medium frontiers as a team (the others sleep)
+    {
+      const ull idle0 = live & ~nearl;
+      const bool split_now = idle0 && plen > 0 &&
+                             (__popcll(idle0) >= P.split_lanes || (live & nearl) == 0 ||
+                              swait + 1 >= P.split_wait);
+      if (!force_full && !split_now && P.team > 1 && qlen > 0 &&
+          qlen <= (int64_t)QCAP * P.team / 2) {
+        sm_seen++;
+        int32_t nl = 0;
+        if (blockIdx.x < (uint32_t)P.team) {
+          MpRun R{it, qsel, fsel, psel, swait, qlen, plen, fbase, live, nearl};
+          int hb = 0;
+          if (!mp_team(P, R, L, (uint32_t)P.team, ts, tb, P.k_iters - k, k, &nl, &hb, ovf, edges,
+                       edge_lanes))
+            ok = false;
+          it = R.it;
+          qsel = R.qsel;
+          fsel = R.fsel;
+          swait = R.swait;
+          qlen = R.qlen;
+          plen = R.plen;
+          live = R.live;
+          nearl = R.nearl;
+          if (blockIdx.x == 0 && threadIdx.x == 0) {
+            C->tp_it = it;
+            C->tp_qsel = qsel;
+            C->tp_fsel = fsel;
+            C->tp_levels = nl;
+            C->tp_force = hb;
+            C->tp_swait = swait;
+            C->tp_qlen = qlen;
+            C->tp_plen = plen;
+            C->tp_live = live;
+            C->tp_nearl = nearl;
+            __hip_atomic_fetch_add(&C->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          force_full = hb;
+          __syncthreads();
+          if (!ok) break;
+        } else {
+          if (threadIdx.x == 0) {
+            const int bad = !fg_wait_geq(&C->sm_signal, sm_seen, C->bar + FG_BAR_STRIDE, 4096);
+            L.flag = bad;
+          }
+          __syncthreads();
+          if (L.flag) {
+            ok = false;
+            break;
+          }
+          const MpCtl* cc = C;
+          it = cc->tp_it;
+          qsel = cc->tp_qsel;
+          fsel = cc->tp_fsel;
+          nl = cc->tp_levels;
+          force_full = cc->tp_force;
+          swait = cc->tp_swait;
+          qlen = cc->tp_qlen;
+          plen = cc->tp_plen;
+          live = cc->tp_live;
+          nearl = cc->tp_nearl;
+          __syncthreads();
+        }
+        k += nl - 1;  // the loop adds the last one
+        continue;
+      }
+    }
+    force_full = 0;
     const int s = k % 3;
     ull idle = live & ~nearl;  // lanes with an empty near frontier
     if (idle && plen == 0) {
@@ -824,6 +1342,15 @@ extern "C" fg_status fg_mssp_step(fg_mssp* b, int32_t k_iters, void* stream) {
   void* args[] = {&P};
   int grid = pr.cus * bpc;
   if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
+  const int lanes_in = __builtin_popcountll(b->admitted);
+  P.team = b->opts.team_blocks > 0 ? b->opts.team_blocks
+           : b->opts.team_blocks < 0 ? 1
+           : (lanes_in >= 4 ? DEF_TEAM_WIDE : DEF_TEAM);
+  if (P.team > TEAM_MAX) P.team = TEAM_MAX;
+  if (P.team > grid) P.team = grid;
+  P.team_e = b->opts.team_edges > 0 ? b->opts.team_edges : DEF_TEAM_E;
+  if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
+
   FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)mssp_persistent, dim3(grid),
                                         dim3(PB), args, 0, (hipStream_t)stream));
   b->npend = 0;

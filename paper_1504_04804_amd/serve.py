@@ -120,6 +120,7 @@ class Server:
         self.finished = []
         self.counts = collections.Counter()
         self.bfs_opts = fg.bfs_opts(mode=fg.FG_MODE_DO)
+        self.stats = None
 
     # ---------------------------------------------------------- memory
     def _reserve(self, nbytes, keep=None):
@@ -221,12 +222,18 @@ class Server:
         r.path = "single"
         g = k.g
         out = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+        if self.stats is None:
+            self.stats = fg.new_stats(g.off.device)
         if k.kind == BFS:
             o = self.bfs_opts if g.symmetric else fg.bfs_opts(mode=fg.FG_MODE_PUSH)
-            fg.bfs_into(g, r.src, out, None, o, ws=k.single_ws, stream=self.stream)
+            fg.bfs_into(g, r.src, out, None, o, ws=k.single_ws, stats=self.stats,
+                        stream=self.stream)
         else:
-            fg.sssp_into(g, r.src, out, None, ws=k.single_ws, stream=self.stream)
-        self.stream.synchronize()
+            fg.sssp_into(g, r.src, out, None, ws=k.single_ws, stats=self.stats, stream=self.stream)
+        st = fg.read_stats(self.stats, stream=self.stream)
+        if st.status != 0:
+            raise RuntimeError(f"single {'BFS' if k.kind == BFS else 'SSSP'} on {k.name} "
+                               f"from {r.src} ended with status {st.status}")
         self.counts["singles"] += 1
         r.done = now_fn()
         if self.keep:

@@ -70,6 +70,39 @@ def test_grid_lanes(fg, orc, delta, dense, split):
     check_lanes(orc, b, off, col, w, srcs)
 
 
+@pytest.mark.parametrize("team,team_e,lanes", [(32, 0, 1), (32, 0, 3), (64, 0, 8), (2, 0, 5),
+                                               (7, 0, 64), (32, 500, 4), (-1, 0, 4)])
+def test_team_iterations(fg, orc, team, team_e, lanes):
+    # grid near iterations run as a team; k_iters=5 ends episodes in
+    # mid-flight and lanes are admitted between steps
+    R, C = 140, 160
+    off, col = synth.grid_csr(R, C)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    rng = np.random.default_rng(abs(team) * 10 + lanes)
+    srcs = {int(l): int(s) for l, s in zip(rng.choice(64, lanes, replace=False),
+                                           rng.choice(R * C, lanes, replace=False))}
+    announce(f"mssp team={team} team_e={team_e} lanes={lanes}")
+    b = fg.MsspBatch(g, 64, fg.mssp_opts(team_blocks=team, team_edges=team_e))
+    items = list(srcs.items())
+    half = len(items) // 2
+    for lane, s_ in items[:half]:
+        b.admit(lane, s_)
+    if half:
+        b.step(5)
+    for lane, s_ in items[half:]:
+        b.admit(lane, s_)
+    b.run(k_iters=5)
+    check_lanes(orc, b, off, col, w, srcs)
+    # R-MAT: hubs on the first levels hand the frontier back to the full grid
+    off, col = synth.rmat_csr(12)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    srcs = {i: int(s_) for i, s_ in enumerate(synth.sources(off, lanes, seed=abs(team) + 9))}
+    b = run_batch(fg, g, srcs, fg.mssp_opts(team_blocks=team, team_edges=team_e, delta=5), k_iters=7)
+    check_lanes(orc, b, off, col, w, srcs)
+
+
 def test_closed_form_grid(fg):
     R, C = 30, 40
     off, col = synth.grid_csr(R, C)
