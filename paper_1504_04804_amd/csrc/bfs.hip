@@ -261,17 +261,28 @@ struct Lds {
   int32_t lq_cnt[3];   // per level mod 3: entries appended
   int32_t lq_deg[3];   // ... their degree sum
   int32_t lq_big[3];   // ... an input vertex of degree > TPV was seen
-  int32_t stage[PWAVES][STAGE];
-  int4 dstage[PWAVES][DSTAGE];
-  // per-wave scan-gather staging (push, full grid)
-  int32_t w_sc[PWAVES][FG_WAVE];
-  int32_t w_u[PWAVES][FG_WAVE];
-  int32_t w_b[PWAVES][FG_WAVE];
-  int32_t w_e[PWAVES][FG_WAVE];
-  // per-wave pull batch: unvisited vertices of nonzero degree per bitmap
-  // word, and the vertices found per word
-  uint64_t pw_act[PWAVES][FG_WAVE];
-  uint64_t pw_nb[PWAVES][FG_WAVE];
+  // Full-grid phases and LDS-queue episodes never overlap in a workgroup
+  // (each ends behind a block barrier), so their staging shares LDS.
+  union {
+    struct {
+      int32_t stage[PWAVES][STAGE];
+      int4 dstage[PWAVES][DSTAGE];
+      // per-wave scan-gather staging (push, full grid)
+      int32_t w_sc[PWAVES][FG_WAVE];
+      int32_t w_u[PWAVES][FG_WAVE];
+      int32_t w_b[PWAVES][FG_WAVE];
+      int32_t w_e[PWAVES][FG_WAVE];
+      // per-wave pull batch: unvisited vertices of nonzero degree per
+      // bitmap word, and the vertices found per word
+      uint64_t pw_act[PWAVES][FG_WAVE];
+      uint64_t pw_nb[PWAVES][FG_WAVE];
+    };
+    // LDS-queue mode: the head-table entry (first four neighbours) of each
+    // queued vertex, loaded beside its offsets when it is discovered, so a
+    // level of low-degree vertices starts from LDS instead of a dependent
+    // load of the column array
+    int4 lq_h[2][QCAP];
+  };
   // block-level staging (small-frontier mode)
   int32_t b_sc[PB];
   int32_t b_u[PB];
@@ -581,7 +592,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
       }
     }
     wave_lds_fence();
-    if (wj < P.nwords) Vout[wj] = vis | nbw[lane];
+    if (wj < P.nwords) fg_st_shared(&Vout[wj], vis | nbw[lane]);
   }
   const int32_t tot = fg_block_sum<PB>(insp, L.red32);
   const int32_t tdeg = fg_block_sum<PB>(ndeg, L.red32);
@@ -630,7 +641,7 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S, Lds& L) {
     while (diff) {
       const int bit = __builtin_ctzll(diff);
       diff &= diff - 1;
-      Q[pos++] = (int32_t)(w * 64 + bit);
+      fg_st_shared(&Q[pos++], (int32_t)(w * 64 + bit));
     }
     __syncthreads();
   }
@@ -802,13 +813,14 @@ __device__ __forceinline__ int32_t wave_reserve(int32_t w, int32_t* counter) {
 // LDS queue; slots past QCAP go to the global queue, one atomic per wave.
 // Every lane of the wave must take part.
 __device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos, int32_t v,
-                                         int32_t vb, int32_t ve, int32_t* Qo, ull* ovf,
+                                         int32_t vb, int32_t ve, int4 vh, int32_t* Qo, ull* ovf,
                                          ull ovf_base) {
   const bool over = won && pos >= QCAP;
   if (won && !over) {
     L.lq_v[nxt][pos] = v;
     L.lq_b[nxt][pos] = vb;
     L.lq_e[nxt][pos] = ve;
+    L.lq_h[nxt][pos] = vh;
   }
   const uint64_t om = __ballot(over);
   if (om) {
@@ -844,9 +856,11 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       for (int32_t i = tid; i < cnt; i += PB) {
         const int32_t u = Qg[lo + i];
         const int32_t b = P.off[u], e = P.off[u + 1];
+        const int4 h = P.head[u];
         L.lq_v[cur][i] = u;
         L.lq_b[cur][i] = b;
         L.lq_e[cur][i] = e;
+        L.lq_h[cur][i] = h;
         sd += e - b;
       }
       if (tid == 0) {
@@ -885,7 +899,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
     const int32_t d_new = S.k + 1;
     bool big = false;
     // vertices of degree <= TPV: TPV consecutive lanes per vertex, one edge
-    // each (the column loads of a vertex coalesce; one dependent chain)
+    // each, the neighbour taken from the vertex's head entry in LDS
     for (int32_t c0 = 0; c0 < cnt; c0 += PB / TPV) {
       const int32_t i = c0 + tid / TPV;
       const int32_t j = tid % TPV;
@@ -898,21 +912,26 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       big |= d > TPV;
       bool won = false;
       int32_t v = 0, vb = 0, ve = 0;
+      int4 vh = make_int4(0, 0, 0, 0);
       if (d <= TPV && j < d) {
-        v = P.col[b + j];
-        vb = P.off[v];
-        ve = P.off[v + 1];
+        v = ((const int32_t*)&L.lq_h[cur][i])[j];
         const uint32_t bit = 1u << (v & 31);
         won = !(atomicOr(&vis32[v >> 5], bit) & bit);
-        if (won) {
-          P.depth[v] = d_new;
-          if (P.parent) P.parent[v] = u;
-        }
+      }
+      // only the winners fetch what the next level needs: most targets of
+      // a low-degree frontier are already visited, and these random line
+      // reads, not the atomics, bound such a level
+      if (won) {
+        vb = P.off[v];
+        ve = P.off[v + 1];
+        vh = P.head[v];
+        P.depth[v] = d_new;
+        if (P.parent) P.parent[v] = u;
       }
       const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
       const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
       if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
-      wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+      wave_put(L, nxt, won, pos, v, vb, ve, vh, Qo, ovf, ovf_base);
     }
     if (big) L.lq_big[ni] = 1;
     __syncthreads();
@@ -938,23 +957,25 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
           const int32_t t = t0 + tid;
           bool won = false;
           int32_t v = 0, vb = 0, ve = 0, pu = 0;
+          int4 vh = make_int4(0, 0, 0, 0);
           if (t < Tn) {
             const int32_t j = upper_idx(L.b_sc, nc, t);
             pu = L.b_u[j];
             v = P.col[L.b_b[j] + (t - L.b_sc[j])];
             const uint32_t bit = 1u << (v & 31);
+            won = !(atomicOr(&vis32[v >> 5], bit) & bit);
+          }
+          if (won) {
             vb = P.off[v];
             ve = P.off[v + 1];
-            if (!(atomicOr(&vis32[v >> 5], bit) & bit)) {
-              won = true;
-              P.depth[v] = d_new;
-              if (P.parent) P.parent[v] = pu;
-            }
+            vh = P.head[v];
+            P.depth[v] = d_new;
+            if (P.parent) P.parent[v] = pu;
           }
           const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
           const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
           if (lane == 0 && wdeg) atomicAdd(&L.lq_deg[ni], wdeg);
-          wave_put(L, nxt, won, pos, v, vb, ve, Qo, ovf, ovf_base);
+          wave_put(L, nxt, won, pos, v, vb, ve, vh, Qo, ovf, ovf_base);
         }
         __syncthreads();
       }
@@ -1096,7 +1117,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     // backward -> forward: list the last pull's discoveries first
     if (MODE == FG_MODE_DO && S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
       bitmap_diff_to_queue(P, S, L);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       S.auxbase = fg_atomic_load_u64(&P.ctl->aux.v);
       S.prevdir = DIR_PUSH;
     }
@@ -1186,18 +1207,18 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     Bases B = get_bases(S);
     if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
       push_phase_a(P, S, L, gridDim.x);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - B.desc);
       if (ndesc > 0) {
         push_phase_b(P, S, ndesc, L, gridDim.x);
-        if (!(ok = gs.sync(&L.flag))) break;
+        if (!(ok = gs.sync_acquire(&L.flag))) break;
       }
       B.desc = dt;
       S.qsel ^= 1;
     } else {
       pull_phase(P, S, L);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       S.cur ^= 1;
     }
     const ull qt = fg_atomic_load_u64(&C.q.v);

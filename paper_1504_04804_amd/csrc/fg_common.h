@@ -199,6 +199,28 @@ __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
   return true;
 }
 
+// Stores of data that other workgroups read after a barrier which does not
+// write back the L2 (fg_grid_sync::sync_acquire): agent-scope atomic stores
+// write through to the point of coherence, so no dirty copy stays in one
+// XCD's L2.
+__device__ __forceinline__ void fg_st_shared(int32_t* p, int32_t x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fg_st_shared(uint64_t* p, uint64_t x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fg_st_shared(int2* p, const int2& x) {
+  __hip_atomic_store((unsigned long long*)p, ((unsigned long long)(uint32_t)x.y << 32) | (uint32_t)x.x,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fg_st_shared(int4* p, const int4& x) {
+  unsigned long long* q = (unsigned long long*)p;
+  __hip_atomic_store(q, ((unsigned long long)(uint32_t)x.y << 32) | (uint32_t)x.x,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, ((unsigned long long)(uint32_t)x.w << 32) | (uint32_t)x.z,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Device-wide barrier for cooperative (co-resident) launches, two levels:
 // workgroups arrive at their group's counter (groups of FG_BAR_GROUP
 // consecutive workgroups); the last arrival of a group arrives at the global
@@ -240,6 +262,38 @@ struct fg_grid_sync {
         ok = fg_wait_geq(ctl, count * ngroups, abort_flag(), 1);
         if (ok)
           __hip_atomic_store(group_release(g), count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = fg_wait_geq(group_release(g), count, abort_flag(), 1);
+      }
+      *s_flag = !ok;
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
+
+  // The same barrier without the L2 write-back (the costly half of sync()
+  // when lines are dirty): for phases whose outputs read by other
+  // workgroups are atomics or fg_st_shared stores.  Every wave first waits
+  // for its own memory operations, the arrivals are relaxed, and each
+  // workgroup ends with one agent-scope acquire (fg_wait_geq), so plain
+  // loads after the barrier see what the other workgroups wrote.  Plain
+  // stores made before it stay unordered with other workgroups.
+  __device__ bool sync_acquire(int* s_flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      const uint32_t g = blockIdx.x / FG_BAR_GROUP;
+      const uint32_t ngroups = (nblocks + FG_BAR_GROUP - 1) / FG_BAR_GROUP;
+      const uint32_t gsize = (g + 1 < ngroups) ? FG_BAR_GROUP : nblocks - g * FG_BAR_GROUP;
+      int ok = 1;
+      const uint32_t old = __hip_atomic_fetch_add(group_arrive(g), 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if (old == count * gsize - 1) {
+        __hip_atomic_fetch_add(ctl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = fg_wait_geq(ctl, count * ngroups, abort_flag(), 1);
+        if (ok)
+          __hip_atomic_store(group_release(g), count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         ok = fg_wait_geq(group_release(g), count, abort_flag(), 1);
       }

@@ -29,7 +29,8 @@ struct WaveStage {
     ull pos = 0;
     if (fg_lane() == 0) pos = atomicAdd(total, (ull)cnt);
     pos = __shfl(pos, 0, FG_WAVE) - base;
-    for (int i = fg_lane(); i < cnt; i += FG_WAVE) out[pos + i] = buf[i];
+    // written through: read by other workgroups after the next barrier
+    for (int i = fg_lane(); i < cnt; i += FG_WAVE) fg_st_shared(&out[pos + i], buf[i]);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     cnt = 0;
