@@ -206,7 +206,13 @@ __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
 __device__ __forceinline__ void fg_st_shared(int32_t* p, int32_t x) {
   __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void fg_st_shared(uint32_t* p, uint32_t x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void fg_st_shared(uint64_t* p, uint64_t x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fg_st_shared(unsigned long long* p, unsigned long long x) {
   __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void fg_st_shared(int2* p, const int2& x) {

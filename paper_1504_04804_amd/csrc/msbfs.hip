@@ -236,7 +236,7 @@ __device__ void push_expand(const MsParams& P, const MsState& S, int32_t k, int6
       b = P.off[u];
       deg = P.off[u + 1] - b;
       fu = Fc[u];
-      Fc[u] = 0ull;  // only this thread reads u's word in this iteration
+      fg_st_shared(&Fc[u], 0ull);  // only this thread reads u's word in this iteration
       if (fu == 0ull) deg = 0;  // listed but without lanes
       ecnt += (uint32_t)deg;
       vcnt += fu != 0ull;
@@ -856,12 +856,12 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         bool act = false;
         if (v < P.n) {
           act = Fc[v] != 0ull;
-          Fn[v] = 0ull;
+          fg_st_shared(&Fn[v], 0ull);
         }
         st.push(act, (int32_t)v, &C.cnt.v, cbp, P.q[S.qsel]);
       }
       st.flush(&C.cnt.v, cbp, P.q[S.qsel]);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull ct = fg_atomic_load_u64(&C.cnt.v);
       S.qlen = (int64_t)(ct - cbp);
       cbp = ct;
@@ -912,9 +912,10 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         if (lng) {
           // listed for the chunked scan; the lanes found so far stay in Fn
           const int32_t nch = (e - b - 4 + CH - 1) / CH;
-          Qlong[atomicAdd(&C.q.v, 1ull) - qbp] = (int32_t)v;
+          fg_st_shared(&Qlong[atomicAdd(&C.q.v, 1ull) - qbp], (int32_t)v);
           const int64_t d0 = (int64_t)(atomicAdd(&C.desc.v, (ull)nch) - dbp);
-          for (int32_t c = 0; c < nch; ++c) P.desc[d0 + c] = make_int4((int32_t)v, b + 4 + c * CH, 0, 0);
+          for (int32_t c = 0; c < nch; ++c)
+            fg_st_shared(&P.desc[d0 + c], make_int4((int32_t)v, b + 4 + c * CH, 0, 0));
         }
         uint64_t pend = __ballot(want && nw != want && e - b > 32 && !lng);
         while (pend) {
@@ -934,8 +935,8 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           if (lane == l) nw = acc & lw;
         }
         if (v < P.n) {
-          if (nw && !lng) P.visit[v] = vis | nw;
-          Fn[v] = nw;
+          if (nw && !lng) fg_st_shared(&P.visit[v], vis | nw);
+          fg_st_shared(&Fn[v], nw);
         }
         if (lng) nw = 0;  // finished after the chunked scan
         // depths, lane by lane over the wave's union: coalesced row stores
@@ -956,7 +957,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           if (bact) atomicAdd(&C.cnt.v, (ull)bact);
         }
       }
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       // ---- listed long vertices (if any): chunked scan by every wave, then
       // finalise; without them the level costs one grid barrier as before
       {
@@ -984,16 +985,16 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             x = fg_wave_or64(x & want);
             if (lane == 0 && (x & ~cur)) atomicOr(&Fn[v], x);
           }
-          if (!(ok = gs.sync(&L.flag))) break;
+          if (!(ok = gs.sync_acquire(&L.flag))) break;
           ull lor2 = 0;
           int32_t act2 = 0;
           for (int64_t i = tid; i < nlong; i += nth) {
             const int32_t v = Qlong[i];
             const ull vis = P.visit[v];
             const ull nw = Fn[v] & S.live & ~vis;
-            Fn[v] = nw;
+            fg_st_shared(&Fn[v], nw);
             if (nw) {
-              P.visit[v] = vis | nw;
+              fg_st_shared(&P.visit[v], vis | nw);
               write_depths(P, v, nw, it1);
             }
             lor2 |= nw;
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             if (bor) atomicOr(livew, bor);
             if (bact) atomicAdd(&C.cnt.v, (ull)bact);
           }
-          if (!(ok = gs.sync(&L.flag))) break;
+          if (!(ok = gs.sync_acquire(&L.flag))) break;
         }
       }
       const ull lv = fg_atomic_load_u64(livew);
@@ -1023,7 +1024,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         const ull bor = block_or(got, L.redu);
         if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
       }
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - dbp);
       if (ndesc > 0) {
@@ -1031,7 +1032,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
         push_desc(P, S, k, ndesc, qbp, L, got2);
         const ull bor = block_or(got2, L.redu);
         if (threadIdx.x == 0 && bor) atomicOr(livew, bor);
-        if (!(ok = gs.sync(&L.flag))) break;
+        if (!(ok = gs.sync_acquire(&L.flag))) break;
       }
       dbp = dt;
       const ull qt = fg_atomic_load_u64(&C.q.v);

@@ -206,7 +206,8 @@ struct PileStage {
       atomicAdd(count, (ull)cnt);
     }
     pos = __shfl(pos, 0, FG_WAVE) - base;
-    for (int i = fg_lane(); i < cnt; i += FG_WAVE) out[pos + i] = buf[i];
+    // written through: read by other workgroups after the next barrier
+    for (int i = fg_lane(); i < cnt; i += FG_WAVE) fg_st_shared(&out[pos + i], buf[i]);
     wave_lds_fence();
     cnt = 0;
   }
@@ -940,7 +941,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
           u = Qc[i];
           m = Fc[u];
           if (m) {
-            Fc[u] = 0ull;  // only this thread reads u's word in this iteration
+            fg_st_shared(&Fc[u], 0ull);  // only this thread reads u's word in this iteration
             b = P.off[u];
             d = P.off[u + 1] - b;
           }
@@ -967,8 +968,9 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
           for (int32_t t = lane; t < NC; t += FG_WAVE) {
             const int32_t j = upper_idx(sc, FG_WAVE, t);
             const ull mj = sm[j];
-            P.desc[d0 + t] = make_int4(su[j], sb[j] + (t - sc[j]) * CHS, (int32_t)(uint32_t)mj,
-                                       (int32_t)(uint32_t)(mj >> 32));
+            fg_st_shared(&P.desc[d0 + t],
+                         make_int4(su[j], sb[j] + (t - sc[j]) * CHS, (int32_t)(uint32_t)mj,
+                                   (int32_t)(uint32_t)(mj >> 32)));
           }
           wave_lds_fence();
         }
@@ -1060,7 +1062,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
       if (threadIdx.x < MAXL && ((bs >> threadIdx.x) & 1ull))
         atomicMin(&C->minst[s][threadIdx.x], L.minl[threadIdx.x]);
     }
-    if (!(ok = gs.sync(&L.flag))) break;
+    if (!(ok = gs.sync_acquire(&L.flag))) break;
     // ---- edge chunks of high-degree vertices: one chunk per wave
     const int64_t nd = (int64_t)fg_atomic_load_u64(&C->dcnt[s].v);
     if (nd > 0) {
@@ -1091,7 +1093,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
       fst.flush(O.fpos, O.fcnt, O.fbase, O.pile);
       const ull bn = block_or(nb2, L.redu);
       if (threadIdx.x == 0 && bn) atomicOr(&C->nearw[s].v, bn);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
     }
     // ---- next state (identical in every workgroup)
     const ull nw = fg_atomic_load_u64(&C->nearw[s].v);

@@ -158,7 +158,8 @@ struct PileStage {
       if (count) atomicAdd(count, (ull)cnt);
     }
     pos = __shfl(pos, 0, FG_WAVE) - base;
-    for (int i = fg_lane(); i < cnt; i += FG_WAVE) out[pos + i] = buf[i];
+    // written through: read by other workgroups after the next barrier
+    for (int i = fg_lane(); i < cnt; i += FG_WAVE) fg_st_shared(&out[pos + i], buf[i]);
     wave_lds_fence();
     cnt = 0;
   }
@@ -334,7 +335,7 @@ __device__ void phase_a(const SsspParams& P, const St& S, Lds& L) {
       b = P.off[u];
       deg = P.off[u + 1] - b;
       du = (uint32_t)(P.key[u] >> 32);
-      inq_cur[u >> 5] = 0u;
+      fg_st_shared(&inq_cur[u >> 5], 0u);
     }
     insp += deg;
     const bool big = deg >= P.big_deg;
@@ -1129,7 +1130,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
       // full-grid split of a large pile
       const uint32_t Tnew = S.Tnext;
       split_full(P, S, Tnew, L);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
       const int sl = S.ph % 3;
       const ull sq = fg_atomic_load_u64(&P.ctl->sqcnt[sl].v);
       const ull fc = fg_atomic_load_u64(&P.ctl->fcnt[sl].v);
@@ -1149,12 +1150,12 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
     phase_a(P, S, L);
-    if (!(ok = gs.sync(&L.flag))) break;
+    if (!(ok = gs.sync_acquire(&L.flag))) break;
     const ull dt = fg_atomic_load_u64(&C.desc.v);
     const int64_t ndesc = (int64_t)(dt - B.desc);
     if (ndesc > 0) {
       phase_b(P, S, ndesc, L);
-      if (!(ok = gs.sync(&L.flag))) break;
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
     }
     B.desc = dt;
     const ull qt = fg_atomic_load_u64(&C.q.v);
