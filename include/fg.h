@@ -212,7 +212,8 @@ typedef struct {
                              frontier Bellman-Ford).  Results do not depend
                              on it.                                          */
   int32_t team_blocks;    /* workgroups that run medium frontiers from LDS
-                             queues as a team (0 = 32, -1 = no team)         */
+                             queues as a team (0 = 32 on graphs of mean
+                             degree <= 8, no team on others; -1 = no team) */
   int32_t team_edges;     /* ... while the frontier's degree sum is at most
                              this (0 = 65536)                                */
 } fg_sssp_opts;
@@ -381,11 +382,13 @@ typedef struct {
   int32_t split_lanes;   /* lanes whose near frontier is empty wait until this
                             many can split in one scan of the far list (0 = 8) */
   int32_t split_wait;    /* ... or until they have waited this many
-                            iterations (0 = 8); 1 = split at once             */
+                            iterations (0 = 8 on graphs of mean degree <= 8,
+                            1 on others); 1 = split at once                 */
   int32_t team_blocks;   /* workgroups that run near iterations of medium
-                            frontiers from LDS queues as a team (0 = 32 while
-                            fewer than 4 lanes hold queries, 64 otherwise;
-                            -1 = no team)                                    */
+                            frontiers from LDS queues as a team (0 = on
+                            graphs of mean degree <= 8: 32 while fewer than
+                            4 lanes hold queries, 64 otherwise; no team on
+                            others; -1 = no team)                            */
   int32_t team_edges;    /* ... while the frontier's degree sum is at most
                             this (0 = 262144)                                */
 } fg_mssp_opts;

@@ -713,6 +713,9 @@ __device__ bool team_levels(const MsParams& P, MsState& S, Lds& L, uint32_t T, T
   }
 }
 
+// TEAM = false compiles the kernel without the team episodes, whose code
+// raises the register pressure (and the spills) of the whole kernel.
+template <bool TEAM>
 __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -782,7 +785,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
     const int32_t it1 = S.it + 1;
     const bool want_pull = S.mode == 0 ? S.qlen > P.n / P.pull_div : S.qlen >= P.n / P.push_div;
     // ---- push levels of medium frontiers as a team (the others sleep)
-    if (!force_full && S.mode == 0 && !want_pull && P.team > 1 && S.qlen >= TEAM_MIN_Q &&
+    if (TEAM && !force_full && S.mode == 0 && !want_pull && P.team > 1 && S.qlen >= TEAM_MIN_Q &&
         S.qlen <= (int64_t)QCAP * P.team / 2) {
       sm_seen++;
       int32_t nl = 0;
@@ -1196,7 +1199,8 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_msbfs_step: no cooperative launch");
   if (dev >= 0 && dev < 64 && g_ms_occ[dev] == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, msbfs_persistent, PB, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, msbfs_persistent<true>, PB, 0) !=
+            hipSuccess ||
         nb < 1)
       nb = 1;
     g_ms_occ[dev] = nb;
@@ -1245,8 +1249,10 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   P.team_e = b->opts.team_edges > 0 ? b->opts.team_edges : DEF_TEAM_E;
   if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
 
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)msbfs_persistent, dim3(grid),
-                                        dim3(PB), args, 0, (hipStream_t)stream));
+  const void* kern = P.team > 1 ? (const void*)msbfs_persistent<true>
+                                : (const void*)msbfs_persistent<false>;
+  FG_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(PB), args, 0,
+                                        (hipStream_t)stream));
   b->npend = 0;
   return FG_OK;
 }

@@ -62,6 +62,7 @@ constexpr int LDS_MEAN_DEG = 64;
 constexpr int32_t DEF_TEAM = 32;
 constexpr int32_t DEF_TEAM_WIDE = 64;
 constexpr int64_t DEF_TEAM_E = 1 << 18;
+constexpr int64_t TEAM_AUTO_DEG = 8;
 
 struct MpState {
   int32_t it;      // iterations since open
@@ -723,6 +724,10 @@ __device__ bool mp_team(const MpParams& P, MpRun& R, Lds& L, uint32_t T, TeamSyn
   }
 }
 
+// TEAM = false compiles the kernel without the team episodes: their code
+// raises the register pressure of the whole kernel (spills on every path),
+// which costs more than the team saves on graphs of high mean degree.
+template <bool TEAM>
 __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -817,7 +822,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
       const bool split_now = idle0 && plen > 0 &&
                              (__popcll(idle0) >= P.split_lanes || (live & nearl) == 0 ||
                               swait + 1 >= P.split_wait);
-      if (!force_full && !split_now && P.team > 1 && qlen > 0 &&
+      if (TEAM && !force_full && !split_now && P.team > 1 && qlen > 0 &&
           qlen <= (int64_t)QCAP * P.team / 2) {
         sm_seen++;
         int32_t nl = 0;
@@ -1303,7 +1308,8 @@ extern "C" fg_status fg_mssp_step(fg_mssp* b, int32_t k_iters, void* stream) {
   if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_mssp_step: no cooperative launch");
   if (dev >= 0 && dev < 64 && g_mp_occ[dev] == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mssp_persistent, PB, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mssp_persistent<true>, PB, 0) !=
+            hipSuccess ||
         nb < 1)
       nb = 1;
     g_mp_occ[dev] = nb;
@@ -1339,22 +1345,31 @@ extern "C" fg_status fg_mssp_step(fg_mssp* b, int32_t k_iters, void* stream) {
   P.big_deg = b->opts.big_degree > 0 ? b->opts.big_degree : 4 * CHS;
   if (P.big_deg > 65536) P.big_deg = 65536;  // keeps a wave's (edge, lane) count in int32
   P.dense = b->opts.dense_lanes > 0 ? b->opts.dense_lanes : 16;
+  // defaults by graph shape: on graphs of mean degree <= 8 (grids,
+  // road-like graphs: long, thin near frontiers) idle lanes wait to split
+  // together and near iterations of medium frontiers run as a team; on
+  // others a lane splits as soon as its near frontier is empty (waiting
+  // makes the other lanes' iterations expand more vertices there) and the
+  // kernel without the team runs
+  const bool low_deg = g->m <= (int64_t)TEAM_AUTO_DEG * g->n;
   P.split_lanes = b->opts.split_lanes > 0 ? b->opts.split_lanes : 8;
-  P.split_wait = b->opts.split_wait > 0 ? b->opts.split_wait : 8;
+  P.split_wait = b->opts.split_wait > 0 ? b->opts.split_wait : (low_deg ? 8 : 1);
   void* args[] = {&P};
   int grid = pr.cus * bpc;
   if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
   const int lanes_in = __builtin_popcountll(b->admitted);
   P.team = b->opts.team_blocks > 0 ? b->opts.team_blocks
-           : b->opts.team_blocks < 0 ? 1
+           : (b->opts.team_blocks < 0 || !low_deg) ? 1
            : (lanes_in >= 4 ? DEF_TEAM_WIDE : DEF_TEAM);
   if (P.team > TEAM_MAX) P.team = TEAM_MAX;
   if (P.team > grid) P.team = grid;
   P.team_e = b->opts.team_edges > 0 ? b->opts.team_edges : DEF_TEAM_E;
   if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
 
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)mssp_persistent, dim3(grid),
-                                        dim3(PB), args, 0, (hipStream_t)stream));
+  const void* kern = P.team > 1 ? (const void*)mssp_persistent<true>
+                                : (const void*)mssp_persistent<false>;
+  FG_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(PB), args, 0,
+                                        (hipStream_t)stream));
   b->npend = 0;
   return FG_OK;
 }

@@ -60,6 +60,7 @@ constexpr int LDS_MEAN_DEG = 64;
 constexpr int TPV = 4;
 constexpr int32_t DEF_TEAM = 32;
 constexpr int64_t DEF_TEAM_E = 65536;
+constexpr int64_t TEAM_AUTO_DEG = 8;
 
 struct CtrSlot {
   Line64 q;
@@ -1020,6 +1021,10 @@ __device__ bool team_mode(const SsspParams& P, St& S, Lds& L, uint32_t T, TeamSy
   }
 }
 
+// TEAM = false compiles the kernel without the team episodes: their code
+// raises the register pressure (and the spills) of the whole kernel, which
+// is not worth it on graphs whose frontiers rarely suit a team.
+template <bool TEAM>
 __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
@@ -1059,7 +1064,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   trace_iter(S, P);
   while (ok && (S.qlen > 0 || S.flen > 0)) {
     const bool small = S.qlen == 0 ? S.flen <= SMALL_FAR : (!force_full && S.qlen <= P.small_q);
-    const bool team = !small && S.qlen > 0 && !force_full && P.team > 1 &&
+    const bool team = TEAM && !small && S.qlen > 0 && !force_full && P.team > 1 &&
                       S.qlen <= (int64_t)QCAP * P.team / 2;
     if (small || team) {
       sm_seen++;
@@ -1284,7 +1289,8 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_sssp: device lacks cooperative launch");
   if (dev >= 0 && dev < 64 && g_sssp_occ[dev] == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sssp_persistent, PB, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sssp_persistent<true>, PB, 0) !=
+            hipSuccess ||
         nb < 1)
       nb = 1;
     g_sssp_occ[dev] = nb;
@@ -1321,14 +1327,18 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   P.small_e = o.small_edges > 0 ? o.small_edges : DEF_SMALL_E;
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
   P.delta = o.delta > 0 ? o.delta : fg_sssp_default_delta(g);
-  P.team = o.team_blocks > 0 ? o.team_blocks : (o.team_blocks < 0 ? 1 : DEF_TEAM);
+  // by default the team kernel runs on graphs of mean degree <= 8 (grids,
+  // road-like graphs), where near frontiers are long and thin
+  const bool low_deg = g->m <= (int64_t)TEAM_AUTO_DEG * g->n;
+  P.team = o.team_blocks > 0 ? o.team_blocks : (o.team_blocks < 0 || !low_deg ? 1 : DEF_TEAM);
   if (P.team > TEAM_MAX) P.team = TEAM_MAX;
   if (P.team > grid) P.team = grid;
   P.team_e = o.team_edges > 0 ? o.team_edges : DEF_TEAM_E;
   if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
   P.clock_khz = pr.clock_khz;
   void* args[] = {&P};
-  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)sssp_persistent, dim3(grid), dim3(PB), args,
-                                        0, (hipStream_t)stream));
+  const void* kern = P.team > 1 ? (const void*)sssp_persistent<true>
+                                : (const void*)sssp_persistent<false>;
+  FG_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(PB), args, 0, (hipStream_t)stream));
   return FG_OK;
 }
