@@ -423,6 +423,67 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
   st.flush(&C.q.v, B.q, Qout);
 }
 
+// ---- push, full grid, frontier of at most 64 vertices (the hubs an R-MAT
+// source reaches first): every wave lists the frontier's CH-edge chunks
+// itself (one lane per vertex, a wave scan of the chunk counts) and takes
+// chunks gw, gw + W, ...; no descriptors in memory, one grid barrier.
+__device__ void push_tiny(const BfsParams& P, const St& S, Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  const int32_t* Qin = P.q[S.qsel];
+  int32_t* Qout = P.q[S.qsel ^ 1];
+  uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
+  const int32_t d_new = S.k + 1;
+  int32_t* sc = L.w_sc[wid];
+  int32_t* su = L.w_u[wid];
+  int32_t* sb = L.w_b[wid];
+  int32_t* se = L.w_e[wid];
+  CtrSlot& C = P.ctl->slot[S.k & 1];
+  const Bases B = get_bases(S);
+  WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
+  int32_t u = 0, b = 0, deg = 0;
+  if (lane < S.qlen) {
+    u = Qin[lane];
+    b = P.off[u];
+    deg = P.off[u + 1] - b;
+  }
+  const int32_t nch = (deg + CH - 1) / CH;
+  const int32_t incl = fg_wave_incl_scan(nch);
+  const int32_t NC = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+  wave_lds_fence();
+  sc[lane] = incl - nch;
+  su[lane] = u;
+  sb[lane] = b;
+  se[lane] = b + deg;
+  wave_lds_fence();
+  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  static_assert(CH == 4 * FG_WAVE, "one visit4 per chunk");
+  for (int64_t c = gw; c < NC; c += W) {
+    // the last vertex whose first chunk is at or before c (vertices without
+    // chunks share their successor's start and are never picked)
+    const int32_t j = upper_idx(sc, FG_WAVE, (int32_t)c);
+    const int32_t e0 = sb[j] + ((int32_t)c - sc[j]) * CH;
+    const int32_t e1 = e0 + CH < se[j] ? e0 + CH : se[j];
+    int32_t v[4], pu[4];
+    bool ok[4], won[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int32_t e = e0 + r * FG_WAVE + lane;
+      ok[r] = e < e1;
+      v[r] = P.col[ok[r] ? e : e1 - 1];
+      pu[r] = su[j];
+    }
+    visit4(P, vis32, d_new, v, pu, ok, won);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
+  }
+  st.flush(&C.q.v, B.q, Qout);
+  // the frontier's degree sum, once
+  const int32_t tot = fg_wave_sum(deg);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
+}
+
 // Position of the r-th set bit (r = 0 first) of x; x has more than r bits set.
 __device__ __forceinline__ int nth_bit(uint64_t x, int r) {
   int pos = 0;
@@ -677,6 +738,20 @@ struct TeamSync {
     __syncthreads();
     return *s_flag == 0;
   }
+
+  // Without the L2 write-back, as fg_grid_sync::sync_acquire: for data the
+  // members write with fg_st_shared or atomics.
+  __device__ bool sync_acquire(int* s_flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      count++;
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
+    }
+    __syncthreads();
+    return *s_flag == 0;
+  }
 };
 
 // Bases of the global-queue counters, held by the members (identical in
@@ -827,7 +902,7 @@ __device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos,
     ull base = 0;
     if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
     base = fg_uni(base);
-    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
+    if (over) fg_st_shared(&Qo[base - ovf_base + fg_mbcnt(om)], v);
   }
 }
 
@@ -1032,14 +1107,14 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       // in member order
       const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
       int32_t* dst = Qo + nover + before;
-      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      for (int32_t i = tid; i < nloc; i += PB) fg_st_shared(&dst[i], L.lq_v[nxt][i]);
       ovf_base += (ull)nover;
       if (solo) {
         tb.solo_ovf = ovf_base;
         __syncthreads();
       } else {
         tb.ovf = ovf_base;
-        if (!ts.sync(&L.flag)) return false;
+        if (!ts.sync_acquire(&L.flag)) return false;
       }
       S.qsel ^= 1;
       if (!stay) return true;
@@ -1205,7 +1280,11 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     }
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
-    if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
+    if ((MODE != FG_MODE_DO || S.dir == DIR_PUSH) && S.qlen <= FG_WAVE) {
+      push_tiny(P, S, L);
+      if (!(ok = gs.sync_acquire(&L.flag))) break;
+      S.qsel ^= 1;
+    } else if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
       push_phase_a(P, S, L, gridDim.x);
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
