@@ -312,10 +312,9 @@ typedef struct {
                             blocks_per_cu)                                          */
   int32_t team_blocks;   /* workgroups that run push levels of medium frontiers from
                             LDS queues as a team (> 1 = that many; 1 = 32 while
-                            fewer than 4 lanes hold queries, 64 otherwise; 0 or -1
-                            = no team, the default: runs with a team have, rarely,
-                            ended with FG_EDEVICE from fg_msbfs_poll after a team
-                            wait reached its limit, cause not yet found)           */
+                            fewer than 4 lanes hold queries, 64 otherwise; 0 = as 1
+                            on graphs of mean degree <= 8, no team on others;
+                            -1 = no team)                                        */
   int32_t team_edges;    /* ... while the frontier's degree sum is at most this
                             (0 = 262144)                                            */
 } fg_msbfs_opts;

@@ -72,6 +72,8 @@ struct alignas(256) BfsCtl {
   uint32_t bar[FG_BAR_WORDS];  // grid barrier (its second line is the abort flag)
   uint32_t sm_signal;          // small-frontier hand-backs (monotone)
   uint32_t pad2[63];
+  uint32_t sm_ack;             // waiters that have read a hand-back (monotone)
+  uint32_t pad2b[63];
   uint32_t exit_count;         // workgroups that left the launch
   uint32_t pad3[63];
   uint32_t team_arrive;        // barrier of the team (workgroups 0..team-1)
@@ -1139,6 +1141,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   S.qlen = 1;
   S.p = 1;
   uint32_t sm_seen = 0;
+  uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
   bool ok = true;
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
   TeamBases tb = {};
@@ -1210,6 +1213,9 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         if (!lds_mode<MODE>(P, S, L, small_ep ? 1u : (uint32_t)P.team, ts, tb)) ok = false;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           BfsCtl* c = P.ctl;
+          // every waiter of the previous hand-back has read it (on a
+          // timeout the abort flag is set and every wait ends)
+          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
           c->pub_k = S.k;
           c->pub_dir = S.dir;
           c->pub_prevdir = S.prevdir;
@@ -1229,6 +1235,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
           c->pub_b[6] = S.b1insp;
           c->pub_b[7] = S.b1deg;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          ack_need += gridDim.x - (small_ep ? 1u : (uint32_t)P.team);
         }
         __syncthreads();
         if (!ok) break;
@@ -1249,6 +1256,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
             L.bcast[8] = c->pub_insp_sum;
             L.bcast[9] = c->pub_switches;
             for (int i = 0; i < 8; ++i) L.bcast[10 + i] = (int64_t)c->pub_b[i];
+            fg_handoff_ack(&P.ctl->sm_ack);
           }
         }
         __syncthreads();

@@ -199,6 +199,19 @@ __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
   return true;
 }
 
+// Hand-off of an episode's state (small-frontier or team episodes) from
+// workgroup 0 to the workgroups that waited for it: each waiter
+// acknowledges once it has read the published fields, and workgroup 0 waits
+// for every acknowledgement of the previous episode before it writes the
+// fields again.  Without this, two episodes that end a few microseconds
+// apart let a slow waiter read the second episode's state as the first's,
+// after which its iteration count, and so its barrier count, differ from
+// the other workgroups'.
+__device__ __forceinline__ void fg_handoff_ack(uint32_t* ack) {
+  __builtin_amdgcn_s_waitcnt(0);  // the published fields have been read
+  __hip_atomic_fetch_add(ack, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Stores of data that other workgroups read after a barrier which does not
 // write back the L2 (fg_grid_sync::sync_acquire): agent-scope atomic stores
 // write through to the point of coherence, so no dirty copy stays in one

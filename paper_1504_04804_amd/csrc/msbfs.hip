@@ -56,6 +56,7 @@ constexpr int TPV = 4;
 constexpr int32_t DEF_TEAM = 32;
 constexpr int32_t DEF_TEAM_WIDE = 64;
 constexpr int64_t DEF_TEAM_E = 1 << 18;
+constexpr int64_t TEAM_AUTO_DEG = 8;
 constexpr int32_t TEAM_MIN_Q = 1;
 
 struct MsState {
@@ -96,6 +97,8 @@ struct alignas(256) MsCtl {
   // per-member records, level words, overflow counter, episode live words
   uint32_t sm_signal;
   uint32_t pad1[63];
+  uint32_t sm_ack;  // waiters that have read a hand-back (monotone)
+  uint32_t pad1b[63];
   uint32_t team_arrive;
   uint32_t pad2[63];
   ull team_rec[2][TEAM_MAX][2];
@@ -780,6 +783,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
               0u};
   TeamBases tb = {};
   uint32_t sm_seen = 0;
+  uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
   int force_full = 0;
   for (int32_t k = 0; ok && k < P.k_iters && S.live != 0ull; ++k) {
     const int32_t it1 = S.it + 1;
@@ -796,6 +800,9 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           ok = false;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           MsCtl* c = P.ctl;
+          // every waiter of the previous hand-back has read it (on a
+          // timeout the abort flag is set and every wait ends)
+          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
           c->pub_it = S.it;
           c->pub_qsel = S.qsel;
           c->pub_fsel = S.fsel;
@@ -804,6 +811,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           c->pub_tqlen = S.qlen;
           c->pub_tlive = S.live;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          ack_need += gridDim.x - (uint32_t)P.team;
         }
         force_full = hb;
         __syncthreads();
@@ -819,6 +827,7 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
             L.bcast[2] = c->pub_levels;
             L.bcast[3] = c->pub_tqlen;
             L.redu[0] = c->pub_tlive;
+            fg_handoff_ack(&P.ctl->sm_ack);
           }
         }
         __syncthreads();
@@ -1238,11 +1247,13 @@ extern "C" fg_status fg_msbfs_step(fg_msbfs* b, int32_t k_iters, void* stream) {
   void* args[] = {&P};
   int grid = pr.cus * bpc;
   if (b->opts.grid_blocks > 0 && b->opts.grid_blocks < grid) grid = b->opts.grid_blocks;
-  // team mode only on request: a rare wait timeout in it is not explained
-  // yet (see the team_blocks option in fg.h)
+  // by default the team kernel runs on graphs of mean degree <= 8 (grids,
+  // road-like graphs: long, thin push frontiers)
   const int lanes_in = __builtin_popcountll(b->admitted);
-  P.team = b->opts.team_blocks > 1 ? b->opts.team_blocks
-           : b->opts.team_blocks == 1 ? (lanes_in >= 4 ? DEF_TEAM_WIDE : DEF_TEAM)
+  const bool low_deg = g->m <= (int64_t)TEAM_AUTO_DEG * g->n;
+  const int32_t tbo = b->opts.team_blocks;
+  P.team = tbo > 1 ? tbo
+           : (tbo == 1 || (tbo == 0 && low_deg)) ? (lanes_in >= 4 ? DEF_TEAM_WIDE : DEF_TEAM)
            : 1;
   if (P.team > TEAM_MAX) P.team = TEAM_MAX;
   if (P.team > grid) P.team = grid;

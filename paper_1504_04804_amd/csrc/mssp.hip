@@ -105,6 +105,8 @@ struct alignas(256) MpCtl {
   // words, lanes given next-frontier entries per level, overflow counter
   uint32_t sm_signal;
   uint32_t pad1[63];
+  uint32_t sm_ack;  // waiters that have read a hand-back (monotone)
+  uint32_t pad1b[63];
   uint32_t team_arrive;
   uint32_t pad2[63];
   ull team_rec[2][TEAM_MAX][2];
@@ -814,6 +816,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
   TeamSync ts{&C->team_arrive, C->bar + FG_BAR_STRIDE, (uint32_t)(P.team > 1 ? P.team : 1), 0u};
   TeamBases tb = {};
   uint32_t sm_seen = 0;
+  uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
   int force_full = 0;
   for (int32_t k = 0; ok && k < P.k_iters && live != 0ull; ++k) {
     // ---- near iterations of medium frontiers as a team (the others sleep)
@@ -841,6 +844,9 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
           live = R.live;
           nearl = R.nearl;
           if (blockIdx.x == 0 && threadIdx.x == 0) {
+            // every waiter of the previous hand-back has read it (on a
+            // timeout the abort flag is set and every wait ends)
+            fg_wait_geq(&C->sm_ack, ack_need, C->bar + FG_BAR_STRIDE, 1);
             C->tp_it = it;
             C->tp_qsel = qsel;
             C->tp_fsel = fsel;
@@ -852,6 +858,7 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
             C->tp_live = live;
             C->tp_nearl = nearl;
             __hip_atomic_fetch_add(&C->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ack_need += gridDim.x - (uint32_t)P.team;
           }
           force_full = hb;
           __syncthreads();
@@ -877,7 +884,9 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
           plen = cc->tp_plen;
           live = cc->tp_live;
           nearl = cc->tp_nearl;
+          __builtin_amdgcn_s_waitcnt(0);  // every wave has its copy
           __syncthreads();
+          if (threadIdx.x == 0) fg_handoff_ack(&C->sm_ack);
         }
         k += nl - 1;  // the loop adds the last one
         continue;

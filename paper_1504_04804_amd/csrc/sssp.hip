@@ -74,6 +74,8 @@ struct alignas(256) SsspCtl {
   uint32_t bar[FG_BAR_WORDS];
   uint32_t sm_signal;
   uint32_t pad0[63];
+  uint32_t sm_ack;  // waiters that have read a hand-back (monotone)
+  uint32_t pad0b[63];
   uint32_t exit_count;
   uint32_t pad1[63];
   uint32_t overflow;
@@ -1033,6 +1035,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
   S.T = P.delta;
   S.Tnext = sat_add(P.delta, P.delta);
   uint32_t sm_seen = 0;
+  uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
   int force_full = 0;
   bool ok = true;
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)(P.team > 1 ? P.team : 1),
@@ -1078,6 +1081,9 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           SsspCtl* c = P.ctl;
+          // every waiter of the previous hand-back has read it (on a
+          // timeout the abort flag is set and every wait ends)
+          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
           c->pub_k = S.k;
           c->pub_qsel = S.qsel;
           c->pub_force = ff;
@@ -1089,6 +1095,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
           c->pub_T = S.T;
           c->pub_Tnext = S.Tnext;
           __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          ack_need += gridDim.x - (small ? 1u : (uint32_t)P.team);
         }
         force_full = ff;
         __syncthreads();
@@ -1109,6 +1116,7 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
             L.bcast[7] = (int64_t)c->pub_fbase;
             L.bcast2[0] = c->pub_T;
             L.bcast2[1] = c->pub_Tnext;
+            fg_handoff_ack(&P.ctl->sm_ack);
           }
         }
         __syncthreads();

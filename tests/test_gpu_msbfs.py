@@ -110,11 +110,9 @@ def test_grid_64_sources_closed_form(fg):
         assert np.array_equal(to_np(b.read(lane)), np.abs(rr - r0) + np.abs(cc - c0))
 
 
-@pytest.mark.skip(reason="batched-BFS team mode is off by default: a stress run of 1-lane "
-                         "batches on R-MAT 20 ended 12 of 300 steps with a team wait reaching "
-                         "its limit (FG_EDEVICE); the cause is not found yet")
 @pytest.mark.parametrize("team,team_e,lanes", [(32, 0, 1), (32, 0, 8), (2, 0, 5), (7, 0, 64),
-                                               (64, 0, 3), (32, 300, 8), (-1, 0, 8)])
+                                               (64, 0, 3), (32, 300, 8), (-1, 0, 8), (0, 0, 4),
+                                               (1, 0, 2)])
 def test_team_levels(fg, orc, team, team_e, lanes):
     # grid levels run as a team; k_iters=3 ends episodes in mid-flight and
     # the next step resumes them; lanes are admitted between steps
