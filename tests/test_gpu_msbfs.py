@@ -145,6 +145,29 @@ def test_team_levels(fg, orc, team, team_e, lanes):
     check_lanes(fg, orc, b, off, col, srcs)
 
 
+def test_team_back_to_back_handoffs(fg, orc):
+    # One-lane batches on R-MAT with the team requested: a team episode that
+    # leaves because the frontier's degree grew is re-entered and handed back
+    # at once, so two hand-offs follow each other within microseconds.  Every
+    # step must finish (no wait reaching its limit) with the oracle's depths.
+    off, col = synth.rmat_csr(16)
+    g = fg.Graph(off, col)
+    srcs = [int(s) for s in synth.sources(off, 64, seed=99)]
+    want = {s: orc.bfs(off, col, s)[0] for s in srcs[:8]}
+    announce("msbfs team hand-offs: 150 one-lane batches on rmat16")
+    b = fg.MsBatch(g, 64, fg.msbfs_opts(team_blocks=1))
+    for r in range(150):
+        if r:
+            b.release(0)
+        s = srcs[r % 8]
+        b.admit(0, s)
+        b.step(1 << 30)
+        done, _ = b.poll()  # raises FGError (FG_EDEVICE) if a wait hit its limit
+        assert done & 1
+        if r < 8 or r % 16 == 0:
+            assert np.array_equal(to_np(b.read(0)), want[s]), f"batch {r} src {s}"
+
+
 def test_msbfs_argument_errors(fg):
     off, col = synth.from_edge_pairs(4, [(0, 1)])
     g = fg.Graph(off, col)
