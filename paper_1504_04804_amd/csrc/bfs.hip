@@ -46,7 +46,11 @@ constexpr int LDS_MEAN_DEG = 64;  // LDS-queue levels need a frontier of mean de
 constexpr int TPV = 4;        // LDS-queue levels: vertices of degree <= TPV are
                               // expanded by TPV lanes each, without a scan
 constexpr int32_t DEF_SMALL_Q = QCAP;
-constexpr int64_t DEF_SMALL_E = 1536;
+// workgroup 0 alone while the frontier's degree sum fits one pass of its
+// low-degree loop (PB / TPV vertices of TPV edges); larger frontiers go
+// faster as a team (grid 1024²: 3.36 µs per level at 1024, 3.50 at 1536,
+// 5.1 at 3072)
+constexpr int64_t DEF_SMALL_E = PB;
 constexpr int32_t DEF_BIG_DEG = 64;
 constexpr int32_t DEF_TEAM = 32;
 constexpr int64_t DEF_TEAM_E = 65536;
@@ -712,34 +716,25 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S, Lds& L) {
 
 // ---- LDS-queue mode: a team of T workgroups (T = 1 for the smallest
 // frontiers) runs push levels back to back.  Each member keeps its share of
-// the frontier in LDS as (vertex, first edge, end edge) and appends each
-// vertex it discovers, with the offsets loaded alongside the visited
-// test-and-set, to its next LDS queue: no global queue, no global output
-// counter and no offset reloads.  A vertex of degree <= TPV is expanded by
-// TPV adjacent lanes, one edge each (no scan, no search); larger vertices
-// go through a block scan-gather.  Per level the dependent
-// memory chain is column load -> (visited atomic | winner's offsets), then
-// one workgroup barrier, plus the exchange of the members' totals when
-// T > 1.  A member whose LDS queue is full appends the overflow to the
-// global queue, which ends the episode.  On exit the members write their
-// LDS queues to the global queue, so the other modes continue from
-// Q[qsel] as usual.
+// the frontier in LDS as (vertex, first edge, end edge, head entry) and
+// appends each vertex it discovers, with the offsets and head entry loaded
+// once its visited test-and-set is won, to its next LDS queue: no global
+// queue, no global output counter and no offset reloads.  A vertex of
+// degree <= TPV is expanded by TPV adjacent lanes, one edge each, the
+// neighbour taken from its head entry (no scan, no search, no column
+// load); larger vertices go through a block scan-gather.  Per level the
+// dependent memory chain is visited atomic -> winner's offsets and head
+// entry, then one workgroup barrier, plus the exchange of the members'
+// totals when T > 1.  A member whose LDS queue is full appends the
+// overflow to the global queue, which ends the episode.  On exit the
+// members write their LDS queues to the global queue (written through, so
+// the team barrier needs no L2 write-back), and the other modes continue
+// from Q[qsel] as usual.
 struct TeamSync {
   uint32_t* arrive;
   uint32_t* abort_flag;
   uint32_t T;
   uint32_t count;
-
-  __device__ bool sync(int* s_flag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      count++;
-      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
-    }
-    __syncthreads();
-    return *s_flag == 0;
-  }
 
   // Without the L2 write-back, as fg_grid_sync::sync_acquire: for data the
   // members write with fg_st_shared or atomics.

@@ -641,11 +641,14 @@ struct TeamSync {
   uint32_t T;
   uint32_t count;
 
-  __device__ bool sync(int* s_flag) {
+  // Without the L2 write-back: for data the members write with
+  // fg_st_shared or atomics.
+  __device__ bool sync_acquire(int* s_flag) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
       count++;
-      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       *s_flag = !fg_wait_geq(arrive, count * T, abort_flag, 1);
     }
     __syncthreads();
@@ -784,7 +787,7 @@ __device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos,
     ull base = 0;
     if (fg_lane() == 0) base = atomicAdd(ovf, (ull)__popcll(om));
     base = fg_uni(base);
-    if (over) Qo[base - ovf_base + fg_mbcnt(om)] = v;
+    if (over) fg_st_shared(&Qo[base - ovf_base + fg_mbcnt(om)], v);
   }
 }
 
@@ -796,7 +799,7 @@ __device__ __forceinline__ void far_put(const SsspParams& P, bool put, int32_t v
     ull base = 0;
     if (fg_lane() == 0) base = atomicAdd(&P.ctl->farpos.v, (ull)__popcll(m));
     base = fg_uni(base);
-    if (put) pile[base - fbase + fg_mbcnt(m)] = v;
+    if (put) fg_st_shared(&pile[base - fbase + fg_mbcnt(m)], v);
   }
 }
 
@@ -1002,10 +1005,10 @@ __device__ bool team_mode(const SsspParams& P, St& S, Lds& L, uint32_t T, TeamSy
       // in member order
       const int32_t nloc = bcnt < QCAP ? bcnt : QCAP;
       int32_t* dst = Qo + nover + before;
-      for (int32_t i = tid; i < nloc; i += PB) dst[i] = L.lq_v[nxt][i];
+      for (int32_t i = tid; i < nloc; i += PB) fg_st_shared(&dst[i], L.lq_v[nxt][i]);
       ovf_base += (ull)nover;
       tb.ovf = ovf_base;
-      if (!ts.sync(&L.flag)) return false;
+      if (!ts.sync_acquire(&L.flag)) return false;
       S.qsel ^= 1;
       if (!stay) {
         // the far pile grew by the members' appends (all done before the
