@@ -37,8 +37,8 @@ GRID = 4096
 # rmat22x64_grid4096.md).  They hold only for the kernel sources they were
 # taken with: `traffic` is null when these files hash differently.
 TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
-TRAFFIC_SHA256 = "5afaa4021cff1ee00616f35616e8a5bce2e19990bfe2903b90b4788298d5bb65"
-TRAFFIC_BYTES = {"bfs_persistent<DO>": 248637444, "bfs_persistent<PUSH>": 2950037812}
+TRAFFIC_SHA256 = "08770a3d2b721cf18fc59d5e71a109e86d3901d9b0097cc78b8f42f8004a6181"
+TRAFFIC_BYTES = {"bfs_persistent<DO>": 251101576, "bfs_persistent<PUSH>": 2947092239}
 
 # direction-switch thresholds of the DO runs (Sec. VI-A do_a, do_b), as
 # chosen for this workload by paper_1504_04804_amd.autotune (stage-1 sweep
