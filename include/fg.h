@@ -368,7 +368,8 @@ typedef struct fg_mssp fg_mssp;
 
 typedef struct {
   uint32_t delta;        /* near-far threshold step of every lane (0 = the
-                            fg_sssp default, UINT32_MAX = no threshold)      */
+                            fg_sssp default on graphs of mean degree <= 8,
+                            twice it on others; UINT32_MAX = no threshold) */
   int32_t big_degree;    /* vertices of at least this degree are relaxed in
                             64-edge chunks by many waves (0 = 256)           */
   int32_t blocks_per_cu; /* persistent launch width (0 = default)            */
