@@ -306,7 +306,7 @@ typedef struct fg_msbfs fg_msbfs;
 typedef struct {
   int32_t big_degree;    /* push: degree from which edges go to descriptors (0 = 64) */
   int32_t pull_div;      /* push -> pull when active vertices > n / pull_div (0 = 64) */
-  int32_t push_div;      /* pull -> push when active vertices < n / push_div (0 = 512) */
+  int32_t push_div;      /* pull -> push when active vertices < n / push_div (0 = 64) */
   int32_t blocks_per_cu; /* persistent launch width (0 = default)                     */
   int32_t grid_blocks;   /* workgroups of the persistent launch (0 = every CU x
                             blocks_per_cu)                                          */
