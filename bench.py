@@ -520,8 +520,8 @@ def side_serving(fg, torch, cpu_graphs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported",
-              file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU (the traversal of one GPU's share); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1504_04804_amd as fg
