@@ -52,7 +52,10 @@ constexpr int32_t DEF_SMALL_Q = QCAP;
 // 5.1 at 3072)
 constexpr int64_t DEF_SMALL_E = PB;
 constexpr int32_t DEF_BIG_DEG = 64;
-constexpr int32_t DEF_TEAM = 32;
+// team width: grid 4096² / 2048² / 1024² push BFS take 35.8 / 14.6 / 6.8 ms
+// with 24 members, 36.2 / 15.1 / 7.2 ms with 32 (narrower frontiers prefer
+// narrower teams: 16 is best at 1024², 24-28 at 4096²)
+constexpr int32_t DEF_TEAM = 24;
 constexpr int64_t DEF_TEAM_E = 65536;
 
 typedef unsigned __int128 u128;
@@ -867,6 +870,16 @@ __device__ bool team_records(const BfsParams& P, Lds& L, uint32_t T, uint32_t se
   return L.flag == 0;
 }
 
+// The head entry of a vertex just discovered from `u`, with u's slots set
+// to -1: u is visited, so testing it again next level is wasted work.
+__device__ __forceinline__ int4 blank_parent(int4 h, int32_t u) {
+  h.x = h.x == u ? -1 : h.x;
+  h.y = h.y == u ? -1 : h.y;
+  h.z = h.z == u ? -1 : h.z;
+  h.w = h.w == u ? -1 : h.w;
+  return h;
+}
+
 // Reserves `w` consecutive slots per lane behind `*counter` (LDS) for the
 // whole wave with one atomic; returns this lane's first slot.  Every lane of
 // the wave must take part.
@@ -987,8 +1000,11 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       int4 vh = make_int4(0, 0, 0, 0);
       if (d <= TPV && j < d) {
         v = ((const int32_t*)&L.lq_h[cur][i])[j];
-        const uint32_t bit = 1u << (v & 31);
-        won = !(atomicOr(&vis32[v >> 5], bit) & bit);
+        // -1: the slot of the vertex's discoverer (visited), skipped
+        if (v >= 0) {
+          const uint32_t bit = 1u << (v & 31);
+          won = !(atomicOr(&vis32[v >> 5], bit) & bit);
+        }
       }
       // only the winners fetch what the next level needs: most targets of
       // a low-degree frontier are already visited, and these random line
@@ -996,7 +1012,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       if (won) {
         vb = P.off[v];
         ve = P.off[v + 1];
-        vh = P.head[v];
+        vh = blank_parent(P.head[v], u);
         P.depth[v] = d_new;
         if (P.parent) P.parent[v] = u;
       }
@@ -1040,7 +1056,7 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
           if (won) {
             vb = P.off[v];
             ve = P.off[v + 1];
-            vh = P.head[v];
+            vh = blank_parent(P.head[v], pu);
             P.depth[v] = d_new;
             if (P.parent) P.parent[v] = pu;
           }
