@@ -375,8 +375,11 @@ def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None):
     out = []
     o = fg.bfs_opts(mode=fg.FG_MODE_DO)
     for r in reqs:
-        while now() < r.arrival:
-            time.sleep(min(r.arrival - now(), 0.002))
+        while True:
+            dt = r.arrival - now()  # one clock read: the wait left, if any
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
         r.start = now()
         g = graphs[r.graph]
         d = torch.empty(g.n, dtype=torch.int32, device="cuda")
