@@ -37,8 +37,8 @@ GRID = 4096
 # rmat22x64_grid4096.md).  They hold only for the kernel sources they were
 # taken with: `traffic` is null when these files hash differently.
 TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
-TRAFFIC_SHA256 = "08770a3d2b721cf18fc59d5e71a109e86d3901d9b0097cc78b8f42f8004a6181"
-TRAFFIC_BYTES = {"bfs_persistent<DO>": 251080598, "bfs_persistent<PUSH>": 2946505457}
+TRAFFIC_SHA256 = "7bec563685e8ba917f2e97907da4786e28aeb4c6426c8ccf9e371870350c71fd"
+TRAFFIC_BYTES = {"bfs_persistent<DO>": 251131379, "bfs_persistent<PUSH>": 2404036854}
 
 # direction-switch thresholds of the DO runs (Sec. VI-A do_a, do_b), as
 # chosen for this workload by paper_1504_04804_amd.autotune (stage-1 sweep
