@@ -78,6 +78,23 @@ def test_team_mode(fg, orc, team, team_e, delta):
     check(fg, orc, g, off, col, w, 77, team_blocks=team, team_edges=team_e, delta=delta)
 
 
+def test_team_handoffs_repeated(fg, orc):
+    # back-to-back launches with the team forced on R-MAT and the solo
+    # threshold varied, so episodes hand off to each other in quick
+    # succession; every run must finish with Dijkstra's distances
+    off, col = synth.rmat_csr(14)
+    w = synth.weights(off, col)
+    g = fg.Graph(off, col, weights=w)
+    srcs = [int(s) for s in synth.sources(off, 4, seed=7)]
+    want = {s: orc.dijkstra(off, col, w, s)[0] for s in srcs}
+    announce("sssp team hand-offs: 60 runs on rmat14")
+    for r in range(60):
+        s = srcs[r % 4]
+        dist, _, st = fg.sssp(g, s, team_blocks=32, small_frontier=(r % 3) * 300 + 1)
+        assert st.status == 0, f"run {r}: status {st.status}"
+        assert np.array_equal(to_np(dist).astype(np.uint32), want[s]), f"run {r} src {s}"
+
+
 def test_near_far_gaps(fg, orc):
     # weights far above the step: each split first finds no vertex below the
     # new threshold and jumps to the smallest distance in the pile
