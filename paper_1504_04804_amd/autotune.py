@@ -6,12 +6,20 @@ graphs on the paper's GPUs), the high-degree cut of the push load balance,
 the team-mode width, and for batched BFS the push/pull switch points.  Every
 candidate runs on the device on a sample of sources; the fastest mean time
 wins.  Results never change depths (the schedule only affects speed), which
-the test suite checks separately.  The cache is a JSON file keyed by a graph
-signature.
+the test suite checks separately.
+
+Two caches:
+  * a JSON file keyed by a graph signature (tuned_bfs_opts), tuned on a miss;
+  * ``tuned.json`` beside this file, keyed by workload name, written by
+    ``python -m paper_1504_04804_amd.autotune`` for the benchmark
+    workloads and read (never re-tuned) by the benchmark and the
+    config-scale tests through workload_opts().
 """
 import itertools
 import json
 import os
+import sys
+import time
 
 import torch
 
@@ -20,7 +28,11 @@ import paper_1504_04804_amd as fg
 DO_A = [(1, 10), (1, 100), (1, 1000), (1, 10000), (1, 100000)]
 DO_B = [(1, 10), (1, 1), (10, 1)]
 BIG_DEG = [32, 64, 256]
-TEAM = [-1, 8, 16, 32]
+TEAM = [-1, 8, 16, 24, 32]
+PULL_DIV = [4, 8, 16, 64, 256]
+PUSH_DIV = [64, 512, 4096]
+
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
 def signature(g):
@@ -45,10 +57,14 @@ def _time_bfs(g, srcs, opts, reps=2):
     return a.elapsed_time(b) / (reps * len(srcs))
 
 
-def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None):
-    """Returns (best kwargs for fg.bfs_opts, ms per traversal)."""
+def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None, do_a=None, do_b=None, big_deg=None,
+             team=None):
+    """Returns (best kwargs for fg.bfs_opts, ms per traversal).  The search
+    spaces default to the module lists; tests pass smaller ones."""
     best = None
-    do_space = itertools.product(DO_A, DO_B) if mode == fg.FG_MODE_DO else [((1, 100), (1, 10))]
+    da_l = DO_A if do_a is None else do_a
+    db_l = DO_B if do_b is None else do_b
+    do_space = itertools.product(da_l, db_l) if mode == fg.FG_MODE_DO else [((1, 100), (1, 10))]
     base = dict(mode=mode)
     # stage 1: direction thresholds with default balance parameters
     for da, db in do_space:
@@ -59,8 +75,9 @@ def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None):
         if best is None or ms < best[1]:
             best = (kw, ms)
     # stage 2: load balance cut and team width around the best thresholds
-    for bd, team in itertools.product(BIG_DEG, TEAM):
-        kw = dict(best[0], big_degree=bd, team_blocks=team)
+    for bd, tm in itertools.product(BIG_DEG if big_deg is None else big_deg,
+                                    TEAM if team is None else team):
+        kw = dict(best[0], big_degree=bd, team_blocks=tm)
         ms = _time_bfs(g, srcs, fg.bfs_opts(**kw))
         if log:
             log(f"bfs {kw}: {ms:.4f} ms")
@@ -69,22 +86,30 @@ def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None):
     return best
 
 
-def tune_msbfs(g, srcs, log=None):
+def tune_msbfs(g, srcs, log=None, pull_div=None, push_div=None, reps=2):
+    """Returns (best kwargs for fg.msbfs_opts, ms per batch of len(srcs) <= 64
+    queries); each candidate's time is the faster of `reps` runs."""
     best = None
-    for pull_div, push_div in itertools.product([4, 8, 16, 64, 256], [64, 512, 4096]):
-        b = fg.MsBatch(g, min(64, len(srcs)), fg.msbfs_opts(pull_div=pull_div, push_div=push_div))
-        for lane, s in enumerate(srcs[:64]):
-            b.admit(lane, int(s))
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        a.record()
-        b.step(1 << 30)
-        e.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(e)
+    for pd, sd in itertools.product(PULL_DIV if pull_div is None else pull_div,
+                                    PUSH_DIV if push_div is None else push_div):
+        b = fg.MsBatch(g, min(64, len(srcs)), fg.msbfs_opts(pull_div=pd, push_div=sd))
+        ts = []
+        for rep in range(reps):
+            for lane, s in enumerate(srcs[:64]):
+                if rep:
+                    b.release(lane)
+                b.admit(lane, int(s))
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record()
+            b.step(1 << 30)
+            e.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(e))
         b.close()
-        kw = dict(pull_div=pull_div, push_div=push_div)
+        ms = min(ts)
+        kw = dict(pull_div=pd, push_div=sd)
         if log:
             log(f"msbfs {kw}: {ms:.3f} ms")
         if best is None or ms < best[1]:
@@ -103,17 +128,80 @@ def save(path, cache):
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
+        f.write("\n")
     os.replace(tmp, path)
 
 
-def tuned_bfs_opts(g, srcs, path, mode=fg.FG_MODE_DO, log=None):
+def _to_json(kw):
+    return {k: (list(v) if isinstance(v, tuple) else v) for k, v in kw.items()}
+
+
+def _from_json(kw):
+    return {k: (tuple(v) if isinstance(v, list) else v) for k, v in kw.items()}
+
+
+def tuned_bfs_opts(g, srcs, path, mode=fg.FG_MODE_DO, log=None, **space):
     """fg.bfs_opts for `g` from the cache at `path`, tuning on a miss."""
     cache = load(path)
     key = f"bfs{mode}:{signature(g)}"
     if key not in cache:
-        kw, ms = tune_bfs(g, srcs, mode, log)
-        cache[key] = dict(kwargs={k: (list(v) if isinstance(v, tuple) else v) for k, v in kw.items()},
-                          ms=ms)
+        kw, ms = tune_bfs(g, srcs, mode, log, **space)
+        cache[key] = dict(kwargs=_to_json(kw), ms=ms)
         save(path, cache)
-    kw = {k: (tuple(v) if isinstance(v, list) else v) for k, v in cache[key]["kwargs"].items()}
+    kw = _from_json(cache[key]["kwargs"])
     return fg.bfs_opts(**kw), kw
+
+
+def workload_opts(name, g, path=TUNED_PATH):
+    """(options object, kwargs) the autotuner stored for workload `name`;
+    raises if the entry is missing or was tuned on another graph."""
+    cache = load(path)
+    if name not in cache:
+        raise KeyError(f"{path} has no entry for {name}: run python -m paper_1504_04804_amd.autotune")
+    ent = cache[name]
+    if ent["signature"] != signature(g):
+        raise ValueError(f"{name} was tuned on {ent['signature']}, not {signature(g)}")
+    kw = _from_json(ent["kwargs"])
+    make = fg.msbfs_opts if ent["kind"] == "msbfs" else fg.bfs_opts
+    return make(**kw), kw
+
+
+def main():
+    """Tunes the benchmark workloads and writes tuned.json:
+    rmat22_dobfs (direction-optimizing BFS, R-MAT 22, the 64 sources),
+    grid4096_push (push BFS, 4096 x 4096 grid, vertex 0),
+    rmat23_msbfs and grid2048_msbfs (64-lane batches, their 64 sources)."""
+    ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import synth
+    torch.cuda.set_device(0)
+    log = lambda s: print(f"[autotune] {s}", flush=True)
+    cache = load(TUNED_PATH)
+    jobs = [("rmat22_dobfs", lambda: synth.rmat_csr(22, 16), "bfs", fg.FG_MODE_DO),
+            ("grid4096_push", lambda: synth.grid_csr(4096, 4096), "bfs", fg.FG_MODE_PUSH),
+            ("rmat23_msbfs", lambda: synth.rmat_csr(23, 16), "msbfs", None),
+            ("grid2048_msbfs", lambda: synth.grid_csr(2048, 2048), "msbfs", None)]
+    only = set(sys.argv[1:])
+    for name, make, kind, mode in jobs:
+        if only and name not in only:
+            continue
+        t0 = time.time()
+        off, col = make()
+        g = fg.Graph(off, col, symmetric=True, validate=False)
+        if kind == "bfs":
+            srcs = [0] if mode == fg.FG_MODE_PUSH else [int(s) for s in synth.sources(off, 64)]
+            kw, ms = tune_bfs(g, srcs, mode, log)
+        else:
+            srcs = [int(s) for s in synth.sources(off, 64)]
+            kw, ms = tune_msbfs(g, srcs, log)
+        cache[name] = dict(kind=kind, signature=signature(g), kwargs=_to_json(kw),
+                           ms=round(ms, 4), sources=len(srcs),
+                           tuned_s=round(time.time() - t0, 1))
+        log(f"{name}: {kw} {ms:.4f} ms")
+        g.close()
+        save(TUNED_PATH, cache)
+
+
+if __name__ == "__main__":
+    main()

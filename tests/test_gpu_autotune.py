@@ -1,0 +1,82 @@
+"""The autotuner: a reduced sweep on a small graph returns options that give
+the oracle's depths, the JSON caches round-trip, and the committed
+workload cache holds an entry for every timed workload."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import announce, gpu, need_gpu, to_np
+
+pytestmark = gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    need_gpu()
+    import paper_1504_04804_amd as fg
+    from paper_1504_04804_amd import autotune
+    fg.lib()
+    return fg, autotune
+
+
+def test_tune_bfs_small(env, orc, tmp_path):
+    fg, at = env
+    off, col = synth.rmat_csr(14)
+    g = fg.Graph(off, col)
+    srcs = [int(s) for s in synth.sources(off, 4, seed=5)]
+    announce("autotune bfs rmat14")
+    path = str(tmp_path / "cache.json")
+    opts, kw = at.tuned_bfs_opts(g, srcs, path, log=print, do_a=[(1, 100), (1, 10000)],
+                                 do_b=[(1, 10), (1, 1)], big_deg=[64], team=[-1, 16])
+    assert kw["mode"] == fg.FG_MODE_DO
+    assert kw["do_a"] in [(1, 100), (1, 10000)] and kw["do_b"] in [(1, 10), (1, 1)]
+    # the cache round-trips: a second call reads the same options, no tuning
+    with open(path) as f:
+        cached = json.load(f)
+    assert len(cached) == 1
+    opts2, kw2 = at.tuned_bfs_opts(g, srcs, path, log=None, do_a=[(1, 2)])
+    assert kw2 == kw
+    for s in srcs:
+        d, p, st = fg.bfs(g, s, opts=opts2)
+        want = orc.bfs(off, col, s)[0]
+        assert st.status == 0
+        assert np.array_equal(to_np(d), want)
+        assert orc.check_bfs(off, col, s, to_np(d), to_np(p)) is None
+
+
+def test_tune_msbfs_small(env, orc):
+    fg, at = env
+    off, col = synth.rmat_csr(13)
+    g = fg.Graph(off, col)
+    srcs = [int(s) for s in synth.sources(off, 16, seed=6)]
+    announce("autotune msbfs rmat13")
+    kw, ms = at.tune_msbfs(g, srcs, pull_div=[8, 64], push_div=[64, 512], reps=1)
+    assert ms > 0 and kw["pull_div"] in (8, 64) and kw["push_div"] in (64, 512)
+    b = fg.MsBatch(g, 16, fg.msbfs_opts(**kw))
+    for lane, s in enumerate(srcs):
+        b.admit(lane, s)
+    b.run(k_iters=8)
+    for lane, s in enumerate(srcs):
+        assert np.array_equal(to_np(b.read(lane)), orc.bfs(off, col, s)[0])
+
+
+def test_workload_cache_entries(env):
+    """Every workload the benchmark times has an entry, looked up by name
+    and checked against the graph it was tuned on."""
+    fg, at = env
+    cache = at.load(at.TUNED_PATH)
+    for name in ("rmat22_dobfs", "grid4096_push", "rmat23_msbfs", "grid2048_msbfs"):
+        assert name in cache, name
+        ent = cache[name]
+        assert ent["kind"] in ("bfs", "msbfs") and "signature" in ent and "kwargs" in ent
+    off, col = synth.grid_csr(2048, 2048)
+    g = fg.Graph(off, col)
+    opts, kw = at.workload_opts("grid2048_msbfs", g)
+    assert isinstance(opts, fg.MsOpts) and set(kw) == {"pull_div", "push_div"}
+    with pytest.raises(ValueError):
+        at.workload_opts("rmat23_msbfs", g)  # tuned on another graph
+    with pytest.raises(KeyError):
+        at.workload_opts("no_such_workload", g)

@@ -85,3 +85,52 @@ def test_fifo_path_same_answers(env, orc):
     ws = {n: g.workspace(fg.FG_PRIM_SSSP) for n, g in graphs.items()}
     done = serve.serve_fifo(graphs, reqs, ws, time_limit=120)
     check_results(orc, csr, done, serve)
+
+
+@pytest.mark.slow
+def test_served_config_graphs_equal_alone(orc):
+    """The serving workload's graph set at full size (R-MAT 16/18/20/22/24,
+    grids 1024^2/2048^2/4096^2, weights in [1, 64]) under the benchmark's
+    policy and HBM budget: a Poisson stream offered faster than it can be
+    served, so queries share batches; every result kept and compared with
+    the oracle's answer for that query alone."""
+    need_gpu()
+    import paper_1504_04804_amd as fg
+    from paper_1504_04804_amd import serve
+    import workloads
+    names = ["rmat16", "rmat18", "rmat20", "rmat22", "rmat24", "grid1024", "grid2048", "grid4096"]
+    graphs, specs, csr, srcs = {}, {}, {}, {}
+    for name in names:
+        off, col, w = workloads.graph(name)
+        graphs[name] = fg.Graph(off, col, weights=w, symmetric=True, validate=False)
+        specs[name] = (off, True)
+        csr[name] = (off, col, w)
+        srcs[name] = synth.sources(off, 8, seed=77)
+    announce("serve config graphs: calibrate")
+    costs = serve.calibrate(graphs, srcs)
+    reqs = serve.make_requests(specs, 120, qps=400.0, bfs_frac=0.8, seed=11)
+    announce("serve config graphs: 120 requests at 400 q/s, 16 GiB budget")
+    srv = serve.Server(graphs, hbm_budget=16 << 30, policy="auto", costs=costs, keep_results=True)
+    done = serve.serve_stream(srv, reqs, time_limit=300)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    assert sum(1 for r in done if r.path == "batch") > 0
+    reads = [(r.rid, r.graph, r.kind, r.src, to_np(r.result)) for r in done]
+    for r in done:
+        r.result = None
+
+    def check(rid, name, kind, src, got):
+        off, col, w = csr[name]
+        if kind == serve.BFS:
+            want = orc.bfs(off, col, src)[0]
+        else:
+            want = orc.dijkstra(off, col, w, src)[0]
+            got = got.view(np.uint32)
+        if not np.array_equal(got, want):
+            return f"request {rid} ({name}, kind {kind}, src {src}) differs"
+        return None
+
+    with workloads.pool() as ex:
+        bad = [e for e in ex.map(lambda t: check(*t), reads) if e is not None]
+    assert not bad, bad[:4]
+    for g in graphs.values():
+        g.close()
