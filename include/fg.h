@@ -242,19 +242,30 @@ fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts* opts, void
 /* ----------------------------------------------------------- BFS operators */
 
 /*
+ * Device-resident frontier lengths (the boundary's "length from the device
+ * or the host"): the operators below that take a frontier length also take
+ * `len_dev`.  When len_dev is NULL, `len` is the length.  Otherwise the
+ * length is read on the device from *len_dev when the call's kernels run
+ * (so a caller can chain operators without reading lengths back), and
+ * `len` is an upper bound the caller guarantees; device lengths above it
+ * are clamped to it.  Work is sized for `len`, so a tight bound is faster.
+ */
+
+/*
  * Advance (Sec. II-B): the edge frontier of `frontier` (device int32[len]).
  * For frontier entry i = 0..len-1 and its CSR neighbours j in order, writes
  * out_dst[k] = neighbour and out_src[k] = frontier[i] at k = sum of the
  * degrees of entries 0..i-1 plus j (a deterministic layout).  The total is
  * written to *out_len (device int64).  If it exceeds `capacity`, nothing
- * beyond capacity is written and the call's stats status (if any) and
- * *out_len report the needed size; the host-visible return is FG_OK (the
- * size is only known on the device).  ws: device workspace of at least
- * fg_workspace_bytes(g, FG_PRIM_BFS_UNFUSED, 0) bytes.
+ * beyond capacity is written and *out_len reports the needed size; the
+ * host-visible return is FG_OK (the size is only known on the device).
+ * len_dev: device int32 length or NULL (see above).  ws: device workspace
+ * of at least fg_workspace_bytes(g, FG_PRIM_BFS_UNFUSED, 0) bytes.
  */
 fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int32_t len,
-                     int32_t* out_dst, int32_t* out_src, int64_t capacity,
-                     int64_t* out_len, void* ws, size_t ws_bytes, void* stream);
+                     const int32_t* len_dev, int32_t* out_dst, int32_t* out_src,
+                     int64_t capacity, int64_t* out_len, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /*
  * Filter (Sec. II-B, with the computation step fused): for each edge-
@@ -264,10 +275,12 @@ fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int32_t len,
  * parent[dst] = src[k] (parent may be NULL) and dst is appended to out_q
  * (device int32, capacity n).  Each vertex is appended at most once; the
  * order of out_q is unspecified.  *out_len (device int32) receives the count.
+ * len_dev: device int64 edge-frontier length (e.g. fg_advance's *out_len)
+ * or NULL, as described above.
  */
 fg_status fg_filter(const fg_graph* g, const int32_t* dst, const int32_t* src,
-                    int64_t len, uint32_t* visited, int32_t iter, int32_t* depth,
-                    int32_t* parent, int32_t* out_q, int32_t* out_len,
+                    int64_t len, const int64_t* len_dev, uint32_t* visited, int32_t iter,
+                    int32_t* depth, int32_t* parent, int32_t* out_q, int32_t* out_len,
                     void* stream);
 
 /*
@@ -463,6 +476,20 @@ fg_status fg_share_create(int32_t n, int64_t m, const int32_t* row_offsets,
                           int32_t part, void* stream, fg_share** out);
 fg_status fg_share_destroy(fg_share* s);
 
+/*
+ * Source setting on a share (the framework's reset for a new source: the
+ * GPU that hosts the source seeds its frontier, the others start empty;
+ * Sec. III-B): clears `visited` (device uint32[ceil(n_total/32)]), sets
+ * depth (and parent, if not NULL) to -1 over the share's n_total vertices,
+ * and if the share hosts global vertex `src`, marks its local id visited at
+ * depth 0 (parent = src, the global id) and writes it to queue[0]; *qlen
+ * (device int32) receives 1 or 0.  Everything happens on the device,
+ * asynchronously on `stream`.  Errors: FG_EINVAL (NULL arguments, src
+ * outside [0, n_global)).
+ */
+fg_status fg_share_seed(const fg_share* s, int32_t src, uint32_t* visited, int32_t* depth,
+                        int32_t* parent, int32_t* queue, int32_t* qlen, void* stream);
+
 typedef struct {
   int32_t n_global;
   int32_t n_local;
@@ -502,12 +529,14 @@ size_t fg_package_workspace_bytes(const fg_share* s, int32_t max_len);
  * appended to the buffer of its owner p as (conv[v], depth[v], global id of
  * parent[v] if parent != NULL).  Buffers keep frontier order (stable), so the
  * result is deterministic.  depth / parent are device int32[n_total] (local
- * ids).  Errors: FG_EINVAL (len outside [0, n_total], capacity < len, NULL
- * buffers), FG_ENOMEM (workspace), FG_EDEVICE.
+ * ids).  len_dev: device int32 frontier length or NULL (device-resident
+ * lengths, above); the workspace is sized for `len`.  Errors: FG_EINVAL
+ * (len outside [0, n_total], capacity < len, NULL buffers), FG_ENOMEM
+ * (workspace), FG_EDEVICE.
  */
 fg_status fg_package(const fg_share* s, const int32_t* frontier, int32_t len,
-                     const int32_t* depth, const int32_t* parent, const fg_peer_bufs* out,
-                     void* ws, size_t ws_bytes, void* stream);
+                     const int32_t* len_dev, const int32_t* depth, const int32_t* parent,
+                     const fg_peer_bufs* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Combine (Sec. III-B merge step; Alg. 1 combination rule): for each
@@ -517,11 +546,14 @@ fg_status fg_package(const fg_share* s, const int32_t* frontier, int32_t len,
  * when both are given) and append v to out_q at position atomicAdd(out_len).
  * *out_len (device int32) is not reset, so received vertices can be appended
  * after the local sub-frontier.  A vertex received several times is taken
- * once.  Errors: FG_EINVAL.
+ * once.  len_dev: device int32 count (e.g. an entry of the sender's
+ * fg_peer_bufs.counts) or NULL, as for the operators above.
+ * Errors: FG_EINVAL.
  */
 fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int32_t* labels,
-                     const int32_t* parents, int32_t len, uint32_t* visited, int32_t* depth,
-                     int32_t* parent, int32_t* out_q, int32_t* out_len, void* stream);
+                     const int32_t* parents, int32_t len, const int32_t* len_dev,
+                     uint32_t* visited, int32_t* depth, int32_t* parent, int32_t* out_q,
+                     int32_t* out_len, void* stream);
 
 #ifdef __cplusplus
 }

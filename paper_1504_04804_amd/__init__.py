@@ -191,10 +191,11 @@ SIGNATURES = {
     "fg_share_graph": (_P, [_P]),
     "fg_share_tables": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "fg_package_workspace_bytes": (_SZ, [_P, _I32]),
-    "fg_package": (_I32, [_P, _P, _I32, _P, _P, ctypes.POINTER(PeerBufs), _P, _SZ, _P]),
-    "fg_combine": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
-    "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _I64, _P, _P, _SZ, _P]),
-    "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
+    "fg_package": (_I32, [_P, _P, _I32, _P, _P, _P, ctypes.POINTER(PeerBufs), _P, _SZ, _P]),
+    "fg_combine": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "fg_share_seed": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
+    "fg_advance": (_I32, [_P, _P, _I32, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "fg_filter": (_I32, [_P, _P, _P, _I64, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "fg_queue_to_bitmap": (_I32, [_P, _P, _I32, _P, _P]),
     "fg_bitmap_to_queue": (_I32, [_P, _P, _P, _P, _P, _SZ, _P]),
@@ -376,22 +377,26 @@ def sssp(g, src, parents=True, opts=None, **kw):
     return dist.to(torch.int64) & 0xFFFFFFFF, parent, st
 
 
-def advance(g, frontier, capacity=None, ws=None):
-    """Edge frontier (dst, src, total) of `frontier` (fg_advance)."""
+def advance(g, frontier, capacity=None, ws=None, len_dev=None, length=None):
+    """Edge frontier (dst, src, total) of `frontier` (fg_advance).  With
+    `len_dev` (device int32[1]) the length is read on the device and
+    `length` (default frontier.numel()) is its upper bound."""
     dev = g.off.device
     cap = g.m if capacity is None else capacity
     dst = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     out_len = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = ws if ws is not None else g.workspace(FG_PRIM_BFS_UNFUSED)
-    _check(lib().fg_advance(g.handle, _ptr(frontier), frontier.numel(), _ptr(dst), _ptr(src),
+    n = frontier.numel() if length is None else int(length)
+    _check(lib().fg_advance(g.handle, _ptr(frontier), n, _ptr(len_dev), _ptr(dst), _ptr(src),
                             cap, _ptr(out_len), _ptr(ws), ws.numel(), _stream()))
     return dst, src, out_len
 
 
-def filter_(g, dst, src, length, visited, it, depth, parent, out_q, out_len):
-    _check(lib().fg_filter(g.handle, _ptr(dst), _ptr(src), int(length), _ptr(visited), int(it),
-                           _ptr(depth), _ptr(parent), _ptr(out_q), _ptr(out_len), _stream()))
+def filter_(g, dst, src, length, visited, it, depth, parent, out_q, out_len, len_dev=None):
+    _check(lib().fg_filter(g.handle, _ptr(dst), _ptr(src), int(length), _ptr(len_dev),
+                           _ptr(visited), int(it), _ptr(depth), _ptr(parent), _ptr(out_q),
+                           _ptr(out_len), _stream()))
 
 
 def pull_step(g, frontier_bits, visited, next_bits, it, depth, parent, out_q, out_len,
@@ -475,8 +480,10 @@ def _memcpy_d2h(dst_np, src_dev_ptr, nbytes):
         raise RuntimeError(f"hipMemcpy failed ({err})")
 
 
-def package(share, frontier, length, depth, parent=None, capacity=None, ws=None):
-    """fg_package: returns device tensors (ids, depth, parent, counts, local, local_count)."""
+def package(share, frontier, length, depth, parent=None, capacity=None, ws=None, len_dev=None):
+    """fg_package: returns device tensors (ids, depth, parent, counts, local, local_count).
+    With `len_dev` (device int32[1]) the length is read on the device and
+    `length` is its upper bound."""
     cap = int(capacity if capacity is not None else max(length, 1))
     P = share.nparts
     dev = "cuda"
@@ -489,8 +496,8 @@ def package(share, frontier, length, depth, parent=None, capacity=None, ws=None)
     bufs = PeerBufs(ids.data_ptr(), dep.data_ptr(), par.data_ptr() if par is not None else None,
                     counts.data_ptr(), local.data_ptr(), lc.data_ptr(), cap)
     ws = ws if ws is not None else share.workspace(length)
-    _check(lib().fg_package(share.handle, _ptr(frontier), int(length), _ptr(depth), _ptr(parent),
-                            ctypes.byref(bufs), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().fg_package(share.handle, _ptr(frontier), int(length), _ptr(len_dev), _ptr(depth),
+                            _ptr(parent), ctypes.byref(bufs), _ptr(ws), ws.numel(), _stream()))
     return ids, dep, par, counts, local, lc
 
 
@@ -664,11 +671,12 @@ class MsspBatch:
             pass
 
 
-def combine(graph_handle, ids, labels, parents, length, visited, depth, parent, out_q, out_len):
+def combine(graph_handle, ids, labels, parents, length, visited, depth, parent, out_q, out_len,
+            len_dev=None):
     """fg_combine on the graph handle (e.g. Share.graph_handle)."""
     _check(lib().fg_combine(graph_handle, _ptr(ids), _ptr(labels), _ptr(parents), int(length),
-                            _ptr(visited), _ptr(depth), _ptr(parent), _ptr(out_q), _ptr(out_len),
-                            _stream()))
+                            _ptr(len_dev), _ptr(visited), _ptr(depth), _ptr(parent), _ptr(out_q),
+                            _ptr(out_len), _stream()))
 
 
 def _op_handle(g):

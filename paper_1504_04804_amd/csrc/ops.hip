@@ -54,10 +54,14 @@ __global__ void tile_scan_kernel(int64_t len, F val, const int64_t* __restrict__
   if (i < len) out[i] = sums[blockIdx.x] + ex;
 }
 
+// Degree of frontier entry i; entries at or past the device-resident
+// length *dlen (when given) count as degree 0.
 struct DegOf {
   const int32_t* off;
   const int32_t* q;
+  const int32_t* dlen;
   __device__ int64_t operator()(int64_t i) const {
+    if (dlen && i >= (int64_t)*dlen) return 0;
     int32_t u = q[i];
     return (int64_t)(off[u + 1] - off[u]);
   }
@@ -348,10 +352,13 @@ extern "C" size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32
 }
 
 static fg_status advance_impl(const fg_graph* g, const int32_t* frontier, int64_t len,
-                              int32_t* out_dst, int32_t* out_src, int64_t capacity,
-                              int64_t* out_len, const OpsLayout& L, hipStream_t s) {
+                              const int32_t* len_dev, int32_t* out_dst, int32_t* out_src,
+                              int64_t capacity, int64_t* out_len, const OpsLayout& L,
+                              hipStream_t s) {
   ScanWs sw{L.sums, L.scan, L.total};
-  run_scan(len, DegOf{g->off, frontier}, sw, s);
+  // with a device-resident length the scan runs over the host bound `len`,
+  // entries past the device length contributing no edges
+  run_scan(len, DegOf{g->off, frontier, len_dev}, sw, s);
   int blocks = grid_for(g->m > 0 ? g->m : 1, EXP_PER_BLOCK, 4096);
   advance_expand_kernel<<<blocks, 256, 0, s>>>(len, frontier, g->off, g->col, L.scan, L.total,
                                                capacity, out_dst, out_src, out_len);
@@ -360,8 +367,9 @@ static fg_status advance_impl(const fg_graph* g, const int32_t* frontier, int64_
 }
 
 extern "C" fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int32_t len,
-                                int32_t* out_dst, int32_t* out_src, int64_t capacity,
-                                int64_t* out_len, void* ws, size_t ws_bytes, void* stream) {
+                                const int32_t* len_dev, int32_t* out_dst, int32_t* out_src,
+                                int64_t capacity, int64_t* out_len, void* ws, size_t ws_bytes,
+                                void* stream) {
   if (!g || !out_dst || !out_src || !out_len || !ws)
     return fg_set_error(FG_EINVAL, "fg_advance: NULL argument");
   if (len < 0 || len > g->n) return fg_set_error(FG_EINVAL, "fg_advance: len=%d outside [0, n]", len);
@@ -371,13 +379,14 @@ extern "C" fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int3
   if (ws_bytes < L.bytes)
     return fg_set_error(FG_ENOMEM, "fg_advance: workspace of %zu bytes < required %zu", ws_bytes,
                         L.bytes);
-  return advance_impl(g, frontier, len, out_dst, out_src, capacity, out_len, L,
+  return advance_impl(g, frontier, len, len_dev, out_dst, out_src, capacity, out_len, L,
                       (hipStream_t)stream);
 }
 
 extern "C" fg_status fg_filter(const fg_graph* g, const int32_t* dst, const int32_t* src,
-                               int64_t len, uint32_t* visited, int32_t iter, int32_t* depth,
-                               int32_t* parent, int32_t* out_q, int32_t* out_len, void* stream) {
+                               int64_t len, const int64_t* len_dev, uint32_t* visited,
+                               int32_t iter, int32_t* depth, int32_t* parent, int32_t* out_q,
+                               int32_t* out_len, void* stream) {
   if (!g || !visited || !depth || !out_q || !out_len)
     return fg_set_error(FG_EINVAL, "fg_filter: NULL argument");
   if (len < 0) return fg_set_error(FG_EINVAL, "fg_filter: negative len");
@@ -386,7 +395,7 @@ extern "C" fg_status fg_filter(const fg_graph* g, const int32_t* dst, const int3
   hipStream_t s = (hipStream_t)stream;
   fill_i32_kernel<<<1, 64, 0, s>>>(out_len, 1, 0);
   if (len > 0)
-    filter_kernel<<<grid_for(len, 256, 8192), 256, 0, s>>>(dst, src, nullptr, len, len, visited,
+    filter_kernel<<<grid_for(len, 256, 8192), 256, 0, s>>>(dst, src, len_dev, len, len, visited,
                                                            iter + 1, depth, parent, out_q, out_len);
   FG_HIP_TRY(hipGetLastError());
   return FG_OK;
@@ -458,7 +467,7 @@ fg_status fg_bfs_unfused(const fg_graph* g, int32_t src, void* ws, size_t ws_byt
   int32_t k = 0, sel = 0;
   while (len > 0) {
     front.push_back(len);
-    fg_status st = advance_impl(g, L.q[sel], len, L.edst, L.esrc, g->m, L.misc, L, s);
+    fg_status st = advance_impl(g, L.q[sel], len, nullptr, L.edst, L.esrc, g->m, L.misc, L, s);
     if (st != FG_OK) return st;
     fill_i32_kernel<<<1, 64, 0, s>>>(L.len32, 1, 0);
     filter_kernel<<<grid_for(g->m > 0 ? g->m : 1, 256, 8192), 256, 0, s>>>(

@@ -39,10 +39,20 @@ constexpr int KB = 1024;        // threads per block
 constexpr int TILE = 4 * KB;    // frontier entries per tile
 constexpr int MAXP = 16;        // partitions (owner fits 4 bits)
 
-__global__ void pkg_count_kernel(const int32_t* __restrict__ frontier, int32_t len,
+// Frontier length: the host value, or the smaller of it and the device-
+// resident length when one is given.
+__device__ __forceinline__ int32_t eff_len(int32_t len, const int32_t* len_dev) {
+  if (!len_dev) return len;
+  const int32_t d = *len_dev;
+  return d < len ? (d < 0 ? 0 : d) : len;
+}
+
+__global__ void pkg_count_kernel(const int32_t* __restrict__ frontier, int32_t hlen,
+                                 const int32_t* __restrict__ len_dev,
                                  const uint32_t* __restrict__ route, int32_t n_local,
                                  int32_t part, int32_t nparts, int32_t* __restrict__ tile_cnt) {
   __shared__ int32_t cnt[MAXP];
+  const int32_t len = eff_len(hlen, len_dev);
   if (threadIdx.x < MAXP) cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t t0 = (int64_t)blockIdx.x * TILE;
@@ -84,7 +94,8 @@ __global__ void pkg_scan_kernel(int32_t tiles, int32_t nparts, int32_t* __restri
   }
 }
 
-__global__ void pkg_scatter_kernel(const int32_t* __restrict__ frontier, int32_t len,
+__global__ void pkg_scatter_kernel(const int32_t* __restrict__ frontier, int32_t hlen,
+                                   const int32_t* __restrict__ len_dev,
                                    const uint32_t* __restrict__ route,
                                    const int32_t* __restrict__ l2g, int32_t n_local, int32_t part,
                                    int32_t nparts, const int32_t* __restrict__ depth,
@@ -95,6 +106,7 @@ __global__ void pkg_scatter_kernel(const int32_t* __restrict__ frontier, int32_t
                                    int32_t* __restrict__ local_out) {
   __shared__ int32_t wcnt[KB / FG_WAVE][MAXP];
   __shared__ int32_t run[MAXP];
+  const int32_t len = eff_len(hlen, len_dev);
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   if (threadIdx.x < MAXP) run[threadIdx.x] = threadIdx.x < nparts
@@ -154,10 +166,12 @@ __global__ void pkg_scatter_kernel(const int32_t* __restrict__ frontier, int32_t
 // so a vertex received from several peers (or also found locally) is
 // taken once.
 __global__ void combine_kernel(const int32_t* __restrict__ ids, const int32_t* __restrict__ labels,
-                               const int32_t* __restrict__ parents, int32_t len,
+                               const int32_t* __restrict__ parents, int32_t hlen,
+                               const int32_t* __restrict__ len_dev,
                                uint32_t* __restrict__ visited, int32_t* __restrict__ depth,
                                int32_t* __restrict__ parent, int32_t* __restrict__ out_q,
                                int32_t* __restrict__ out_len) {
+  const int32_t len = eff_len(hlen, len_dev);
   const int lane = fg_lane();
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < len; i0 += nth) {
@@ -190,7 +204,62 @@ __global__ void route_kernel(int32_t n, const uint8_t* __restrict__ owner,
     route[i] = ((uint32_t)owner[i] << 28) | (uint32_t)conv[i];
 }
 
+// a1 on a share: visited cleared, depth (and parent) -1; if the share
+// hosts global vertex `src` (l2g is ascending over the hosted vertices,
+// found by binary search), its local id is marked visited at depth 0 and
+// becomes the one-entry frontier; *qlen receives the frontier length.
+__global__ void share_clear_kernel(int32_t n_total, uint32_t* __restrict__ visited,
+                                   int32_t* __restrict__ depth, int32_t* __restrict__ parent) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t; i < n_total; i += nth) {
+    depth[i] = -1;
+    if (parent) parent[i] = -1;
+  }
+  const int64_t nwords = ((int64_t)n_total + 31) / 32;
+  for (int64_t w = t; w < nwords; w += nth) visited[w] = 0u;
+}
+
+__global__ void share_seed_src_kernel(int32_t n_local, const int32_t* __restrict__ l2g, int32_t src,
+                                      uint32_t* __restrict__ visited, int32_t* __restrict__ depth,
+                                      int32_t* __restrict__ parent, int32_t* __restrict__ queue,
+                                      int32_t* __restrict__ qlen) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t lo = 0, hi = n_local;  // first hosted local id with l2g >= src
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (l2g[mid] < src) lo = mid + 1; else hi = mid;
+  }
+  if (lo < n_local && l2g[lo] == src) {
+    depth[lo] = 0;
+    if (parent) parent[lo] = src;
+    visited[lo >> 5] |= 1u << (lo & 31);
+    queue[0] = lo;
+    *qlen = 1;
+  } else {
+    *qlen = 0;
+  }
+}
+
 }  // namespace
+
+extern "C" fg_status fg_share_seed(const fg_share* s, int32_t src, uint32_t* visited,
+                                   int32_t* depth, int32_t* parent, int32_t* queue, int32_t* qlen,
+                                   void* stream) {
+  if (!s || !visited || !depth || !queue || !qlen)
+    return fg_set_error(FG_EINVAL, "fg_share_seed: NULL argument");
+  if (src < 0 || src >= s->n)
+    return fg_set_error(FG_EINVAL, "fg_share_seed: src=%d outside [0, %d)", src, s->n);
+  hipStream_t hs = (hipStream_t)stream;
+  int blocks = (int)((s->n_total + 1023) / 1024);
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  share_clear_kernel<<<blocks, 256, 0, hs>>>(s->n_total, visited, depth, parent);
+  share_seed_src_kernel<<<1, 64, 0, hs>>>(s->n_local, s->l2g, src, visited, depth, parent, queue,
+                                          qlen);
+  FG_HIP_TRY(hipGetLastError());
+  return FG_OK;
+}
 
 extern "C" fg_status fg_share_destroy(fg_share* s) {
   if (!s) return FG_OK;
@@ -334,9 +403,9 @@ extern "C" size_t fg_package_workspace_bytes(const fg_share* s, int32_t max_len)
 }
 
 extern "C" fg_status fg_package(const fg_share* s, const int32_t* frontier, int32_t len,
-                                const int32_t* depth, const int32_t* parent,
-                                const fg_peer_bufs* out, void* ws, size_t ws_bytes,
-                                void* stream) {
+                                const int32_t* len_dev, const int32_t* depth,
+                                const int32_t* parent, const fg_peer_bufs* out, void* ws,
+                                size_t ws_bytes, void* stream) {
   if (!s || !out || !depth || !out->ids || !out->depth || !out->counts)
     return fg_set_error(FG_EINVAL, "fg_package: NULL argument");
   if (len < 0 || len > s->n_total)
@@ -355,13 +424,13 @@ extern "C" fg_status fg_package(const fg_share* s, const int32_t* frontier, int3
   const int32_t tiles = (int32_t)(((int64_t)len + TILE - 1) / TILE);
   int32_t* tile_cnt = (int32_t*)ws;
   if (tiles > 0)
-    pkg_count_kernel<<<tiles, KB, 0, hs>>>(frontier, len, s->route, s->n_local, s->part,
-                                           s->nparts, tile_cnt);
+    pkg_count_kernel<<<tiles, KB, 0, hs>>>(frontier, len, len_dev, s->route, s->n_local,
+                                           s->part, s->nparts, tile_cnt);
   pkg_scan_kernel<<<1, KB, 0, hs>>>(tiles, s->nparts, tile_cnt, out->counts, s->part,
                                     out->local_count);
   if (tiles > 0)
-    pkg_scatter_kernel<<<tiles, KB, 0, hs>>>(frontier, len, s->route, s->l2g, s->n_local, s->part,
-                                             s->nparts, depth, parent, tile_cnt, out->capacity,
+    pkg_scatter_kernel<<<tiles, KB, 0, hs>>>(frontier, len, len_dev, s->route, s->l2g, s->n_local,
+                                             s->part, s->nparts, depth, parent, tile_cnt, out->capacity,
                                              out->ids, out->depth, parent ? out->parent : nullptr,
                                              out->local);
   FG_HIP_TRY(hipGetLastError());
@@ -369,9 +438,9 @@ extern "C" fg_status fg_package(const fg_share* s, const int32_t* frontier, int3
 }
 
 extern "C" fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int32_t* labels,
-                                const int32_t* parents, int32_t len, uint32_t* visited,
-                                int32_t* depth, int32_t* parent, int32_t* out_q,
-                                int32_t* out_len, void* stream) {
+                                const int32_t* parents, int32_t len, const int32_t* len_dev,
+                                uint32_t* visited, int32_t* depth, int32_t* parent,
+                                int32_t* out_q, int32_t* out_len, void* stream) {
   if (!g || !visited || !depth || !out_q || !out_len)
     return fg_set_error(FG_EINVAL, "fg_combine: NULL argument");
   if (len < 0) return fg_set_error(FG_EINVAL, "fg_combine: negative len");
@@ -379,8 +448,8 @@ extern "C" fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int
   if (len == 0) return FG_OK;
   int blocks = (len + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  combine_kernel<<<blocks, 256, 0, (hipStream_t)stream>>>(ids, labels, parents, len, visited,
-                                                          depth, parent, out_q, out_len);
+  combine_kernel<<<blocks, 256, 0, (hipStream_t)stream>>>(ids, labels, parents, len, len_dev,
+                                                          visited, depth, parent, out_q, out_len);
   FG_HIP_TRY(hipGetLastError());
   return FG_OK;
 }

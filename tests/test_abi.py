@@ -45,8 +45,8 @@ def test_argument_errors_without_gpu(fg):
     assert L.fg_graph_create_csr(4, 3, arr, arr, None, 0, None, None) == fg.FG_EINVAL
     assert L.fg_bfs(None, 0, None, None, 0, None, None, None, None) == fg.FG_EINVAL
     assert L.fg_workspace_bytes(None, 0, 0) == 0
-    assert L.fg_advance(None, None, 0, None, None, 0, None, None, 0, None) == fg.FG_EINVAL
-    assert L.fg_filter(None, None, None, 0, None, 0, None, None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_advance(None, None, 0, None, None, None, 0, None, None, 0, None) == fg.FG_EINVAL
+    assert L.fg_filter(None, None, None, 0, None, None, 0, None, None, None, None, None) == fg.FG_EINVAL
     assert L.fg_stats_read(None, None, None) == fg.FG_EINVAL
     assert L.fg_graph_destroy(None) == fg.FG_OK
     assert fg.lib().fg_version().decode().count(".") == 2
@@ -71,7 +71,10 @@ def test_new_entry_points_argument_errors(fg):
     bad_off = np.array([0, 1, 3], np.int32)
     assert L.fg_share_create(2, 2, P(bad_off), P(col), P(own), 2, 0, None, ctypes.byref(h)) == fg.FG_EINVAL
     assert L.fg_share_destroy(None) == fg.FG_OK
-    assert L.fg_package(None, None, 0, None, None, None, None, 0, None) == fg.FG_EINVAL
+    assert L.fg_package(None, None, 0, None, None, None, None, None, 0, None) == fg.FG_EINVAL
+    assert L.fg_combine(None, None, None, None, 0, None, None, None, None, None, None,
+                        None) == fg.FG_EINVAL
+    assert L.fg_share_seed(None, 0, None, None, None, None, None, None) == fg.FG_EINVAL
     assert L.fg_package_workspace_bytes(None, 10) == 0
     # sssp / batched BFS
     assert L.fg_sssp(None, 0, None, None, 0, None, None, None, None) == fg.FG_EINVAL
