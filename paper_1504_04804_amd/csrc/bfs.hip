@@ -300,6 +300,7 @@ struct Lds {
   int32_t red32[PWAVES + 1];
   int32_t newcnt;
   int32_t flag;
+  int32_t ackbad;  // workgroup 0: a hand-off acknowledgement wait failed
   int64_t bcast[20];
   int32_t tsum[6];
 };
@@ -1226,30 +1227,38 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
           BfsCtl* c = P.ctl;
           // every waiter of the previous hand-back has read it (on a
           // timeout the abort flag is set and every wait ends)
-          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
-          c->pub_k = S.k;
-          c->pub_dir = S.dir;
-          c->pub_prevdir = S.prevdir;
-          c->pub_switched = S.switched;
-          c->pub_qsel = S.qsel;
-          c->pub_qlen = S.qlen;
-          c->pub_qdeg = S.qdeg;
-          c->pub_p = S.p;
-          c->pub_insp_sum = S.insp_sum;
-          c->pub_switches = S.switches;
-          c->pub_b[0] = S.b0q;
-          c->pub_b[1] = S.b0desc;
-          c->pub_b[2] = S.b0insp;
-          c->pub_b[3] = S.b0deg;
-          c->pub_b[4] = S.b1q;
-          c->pub_b[5] = S.b1desc;
-          c->pub_b[6] = S.b1insp;
-          c->pub_b[7] = S.b1deg;
-          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          ack_need += gridDim.x - (small_ep ? 1u : (uint32_t)P.team);
+          L.ackbad = !fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
+          // a failed wait has set the abort flag: publish nothing (a slow
+          // waiter may still be reading the previous hand-off); the waiters
+          // see the flag and leave
+          if (!L.ackbad) {
+            c->pub_k = S.k;
+            c->pub_dir = S.dir;
+            c->pub_prevdir = S.prevdir;
+            c->pub_switched = S.switched;
+            c->pub_qsel = S.qsel;
+            c->pub_qlen = S.qlen;
+            c->pub_qdeg = S.qdeg;
+            c->pub_p = S.p;
+            c->pub_insp_sum = S.insp_sum;
+            c->pub_switches = S.switches;
+            c->pub_b[0] = S.b0q;
+            c->pub_b[1] = S.b0desc;
+            c->pub_b[2] = S.b0insp;
+            c->pub_b[3] = S.b0deg;
+            c->pub_b[4] = S.b1q;
+            c->pub_b[5] = S.b1desc;
+            c->pub_b[6] = S.b1insp;
+            c->pub_b[7] = S.b1deg;
+            __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ack_need += gridDim.x - (small_ep ? 1u : (uint32_t)P.team);
+          }
         }
         __syncthreads();
-        if (!ok) break;
+        if (!ok || (blockIdx.x == 0 && L.ackbad)) {
+          ok = false;
+          break;
+        }
       } else {
         if (threadIdx.x == 0) {
           const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
@@ -1340,7 +1349,10 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
     fg_run_stats* st = P.stats;
-    st->status = ok ? FG_OK : FG_EDEVICE;
+    // a wait that failed in any workgroup has set the abort flag
+    const uint32_t aborted = __hip_atomic_load(P.ctl->bar + FG_BAR_STRIDE, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    st->status = (ok && !aborted) ? FG_OK : FG_EDEVICE;
     st->iterations = S.k;
     st->reached = S.p;
     st->edges_inspected = S.insp_sum;
@@ -1462,31 +1474,31 @@ void fg_bfs_launch_init(const fg_graph* g, int32_t src, int32_t* depth, int32_t*
   bfs_seed_kernel<<<1, 64, 0, s>>>(src, depth, parent, vis0, q0);
 }
 
-extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts, void* ws,
-                            size_t ws_bytes, int32_t* depth, int32_t* parent,
-                            fg_run_stats* stats, void* stream) {
-  if (!g) return fg_set_error(FG_EINVAL, "fg_bfs: graph is NULL");
+// Argument checks shared by fg_bfs and fg_bfs_noalloc; fills *o.
+static fg_status bfs_check(const char* fn, const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
+                           int32_t* depth, fg_bfs_opts* o) {
+  if (!g) return fg_set_error(FG_EINVAL, "%s: graph is NULL", fn);
   if (src < 0 || src >= g->n)
-    return fg_set_error(FG_EINVAL, "fg_bfs: src=%d outside [0, %d)", src, g->n);
-  if (!depth) return fg_set_error(FG_EINVAL, "fg_bfs: depth is NULL");
-  if (!ws) return fg_set_error(FG_EINVAL, "fg_bfs: workspace is NULL");
-  fg_bfs_opts o;
-  if (opts) o = *opts; else fg_bfs_opts_default(&o);
-  if (o.mode != FG_MODE_DO && o.mode != FG_MODE_PUSH && o.mode != FG_MODE_PUSH_UNFUSED)
-    return fg_set_error(FG_EINVAL, "fg_bfs: unknown mode %d", o.mode);
-  if (o.mode == FG_MODE_DO) {
+    return fg_set_error(FG_EINVAL, "%s: src=%d outside [0, %d)", fn, src, g->n);
+  if (!depth) return fg_set_error(FG_EINVAL, "%s: depth is NULL", fn);
+  if (opts) *o = *opts; else fg_bfs_opts_default(o);
+  if (o->mode != FG_MODE_DO && o->mode != FG_MODE_PUSH && o->mode != FG_MODE_PUSH_UNFUSED)
+    return fg_set_error(FG_EINVAL, "%s: unknown mode %d", fn, o->mode);
+  if (o->mode == FG_MODE_DO) {
     if (!g->symmetric)
       return fg_set_error(FG_EUNSUPPORTED,
-                          "fg_bfs: the pull step needs an undirected graph (FG_SYMMETRIC)");
-    if (o.do_a_den == 0 || o.do_b_den == 0)
-      return fg_set_error(FG_EINVAL, "fg_bfs: zero denominator in do_a / do_b");
+                          "%s: the pull step needs an undirected graph (FG_SYMMETRIC)", fn);
+    if (o->do_a_den == 0 || o->do_b_den == 0)
+      return fg_set_error(FG_EINVAL, "%s: zero denominator in do_a / do_b", fn);
   }
-  if (o.mode == FG_MODE_PUSH_UNFUSED)
-    return fg_bfs_unfused(g, src, ws, ws_bytes, depth, parent, stats, (hipStream_t)stream);
-  BfsLayout lay = bfs_layout(g, ws);
-  if (ws_bytes < lay.bytes)
-    return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
-                        lay.bytes);
+  return FG_OK;
+}
+
+// One persistent launch of the fused BFS kernel over the workspace `lay`
+// (whose control block is zero).
+static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o,
+                            const BfsLayout& lay, int32_t* depth, int32_t* parent,
+                            fg_run_stats* stats, hipStream_t s) {
   int dev = 0;
   FG_HIP_TRY(hipGetDevice(&dev));
   fg_device_props pr = fg_props(dev);
@@ -1496,7 +1508,6 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
   if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
   const int grid = pr.cus * bpc;
-  hipStream_t s = (hipStream_t)stream;
 
   BfsParams P;
   memset(&P, 0, sizeof(P));
@@ -1540,4 +1551,20 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
                                         : (const void*)bfs_persistent<FG_MODE_PUSH>;
   FG_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PB), args, 0, s));
   return FG_OK;
+}
+
+extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts, void* ws,
+                            size_t ws_bytes, int32_t* depth, int32_t* parent,
+                            fg_run_stats* stats, void* stream) {
+  fg_bfs_opts o;
+  fg_status rc = bfs_check("fg_bfs", g, src, opts, depth, &o);
+  if (rc != FG_OK) return rc;
+  if (!ws) return fg_set_error(FG_EINVAL, "fg_bfs: workspace is NULL");
+  if (o.mode == FG_MODE_PUSH_UNFUSED)
+    return fg_bfs_unfused(g, src, ws, ws_bytes, depth, parent, stats, (hipStream_t)stream);
+  BfsLayout lay = bfs_layout(g, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
+                        lay.bytes);
+  return bfs_launch(g, src, o, lay, depth, parent, stats, (hipStream_t)stream);
 }

@@ -145,6 +145,7 @@ struct Lds {
   int32_t red32[PWAVES + 1];
   ull redu[PWAVES + 1];
   int32_t flag;
+  int32_t ackbad;  // workgroup 0: a hand-off acknowledgement wait failed
   int64_t bcast[4];
   int32_t start[MAXL];  // iteration at which each lane was admitted
   // team mode: this member's share of the frontier (vertex, first edge, end
@@ -802,20 +803,28 @@ __global__ __launch_bounds__(PB) void msbfs_persistent(MsParams P) {
           MsCtl* c = P.ctl;
           // every waiter of the previous hand-back has read it (on a
           // timeout the abort flag is set and every wait ends)
-          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
-          c->pub_it = S.it;
-          c->pub_qsel = S.qsel;
-          c->pub_fsel = S.fsel;
-          c->pub_levels = nl;
-          c->pub_force = hb;
-          c->pub_tqlen = S.qlen;
-          c->pub_tlive = S.live;
-          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          ack_need += gridDim.x - (uint32_t)P.team;
+          L.ackbad = !fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
+          // a failed wait has set the abort flag: publish nothing (a slow
+          // waiter may still be reading the previous hand-off); the waiters
+          // see the flag and leave
+          if (!L.ackbad) {
+            c->pub_it = S.it;
+            c->pub_qsel = S.qsel;
+            c->pub_fsel = S.fsel;
+            c->pub_levels = nl;
+            c->pub_force = hb;
+            c->pub_tqlen = S.qlen;
+            c->pub_tlive = S.live;
+            __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ack_need += gridDim.x - (uint32_t)P.team;
+          }
         }
         force_full = hb;
         __syncthreads();
-        if (!ok) break;
+        if (!ok || (blockIdx.x == 0 && L.ackbad)) {
+          ok = false;
+          break;
+        }
       } else {
         if (threadIdx.x == 0) {
           const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);

@@ -158,6 +158,7 @@ struct Lds {
   uint32_t Tnext[MAXL];
   uint32_t minl[MAXL];
   int32_t flag;
+  int32_t ackbad;  // workgroup 0: a hand-off acknowledgement wait failed
   // team mode: this member's share of the frontier (vertex, first edge, end
   // edge) for the current and the next level, counters over three slots,
   // block scan-gather arrays, exchange results
@@ -846,23 +847,31 @@ __global__ __launch_bounds__(PB) void mssp_persistent(MpParams P) {
           if (blockIdx.x == 0 && threadIdx.x == 0) {
             // every waiter of the previous hand-back has read it (on a
             // timeout the abort flag is set and every wait ends)
-            fg_wait_geq(&C->sm_ack, ack_need, C->bar + FG_BAR_STRIDE, 1);
-            C->tp_it = it;
-            C->tp_qsel = qsel;
-            C->tp_fsel = fsel;
-            C->tp_levels = nl;
-            C->tp_force = hb;
-            C->tp_swait = swait;
-            C->tp_qlen = qlen;
-            C->tp_plen = plen;
-            C->tp_live = live;
-            C->tp_nearl = nearl;
-            __hip_atomic_fetch_add(&C->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            ack_need += gridDim.x - (uint32_t)P.team;
+            L.ackbad = !fg_wait_geq(&C->sm_ack, ack_need, C->bar + FG_BAR_STRIDE, 1);
+            // a failed wait has set the abort flag: publish nothing (a slow
+            // waiter may still be reading the previous hand-off); the waiters
+            // see the flag and leave
+            if (!L.ackbad) {
+              C->tp_it = it;
+              C->tp_qsel = qsel;
+              C->tp_fsel = fsel;
+              C->tp_levels = nl;
+              C->tp_force = hb;
+              C->tp_swait = swait;
+              C->tp_qlen = qlen;
+              C->tp_plen = plen;
+              C->tp_live = live;
+              C->tp_nearl = nearl;
+              __hip_atomic_fetch_add(&C->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+              ack_need += gridDim.x - (uint32_t)P.team;
+            }
           }
           force_full = hb;
           __syncthreads();
-          if (!ok) break;
+          if (!ok || (blockIdx.x == 0 && L.ackbad)) {
+            ok = false;
+            break;
+          }
         } else {
           if (threadIdx.x == 0) {
             const int bad = !fg_wait_geq(&C->sm_signal, sm_seen, C->bar + FG_BAR_STRIDE, 4096);

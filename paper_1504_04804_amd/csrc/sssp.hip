@@ -222,6 +222,7 @@ struct Lds {
   int32_t red32[PWAVES + 1];
   int32_t newcnt;
   int32_t flag;
+  int32_t ackbad;  // workgroup 0: a hand-off acknowledgement wait failed
   int64_t bcast[8];
   uint32_t bcast2[2];
   // team mode: this member's share of the frontier, (vertex, first edge,
@@ -1086,23 +1087,31 @@ __global__ __launch_bounds__(PB) void sssp_persistent(SsspParams P) {
           SsspCtl* c = P.ctl;
           // every waiter of the previous hand-back has read it (on a
           // timeout the abort flag is set and every wait ends)
-          fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
-          c->pub_k = S.k;
-          c->pub_qsel = S.qsel;
-          c->pub_force = ff;
-          c->pub_qlen = S.qlen;
-          c->pub_insp_sum = S.insp_sum;
-          c->pub_fsel = S.fsel;
-          c->pub_flen = S.flen;
-          c->pub_fbase = S.fbase;
-          c->pub_T = S.T;
-          c->pub_Tnext = S.Tnext;
-          __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          ack_need += gridDim.x - (small ? 1u : (uint32_t)P.team);
+          L.ackbad = !fg_wait_geq(&c->sm_ack, ack_need, c->bar + FG_BAR_STRIDE, 1);
+          // a failed wait has set the abort flag: publish nothing (a slow
+          // waiter may still be reading the previous hand-off); the waiters
+          // see the flag and leave
+          if (!L.ackbad) {
+            c->pub_k = S.k;
+            c->pub_qsel = S.qsel;
+            c->pub_force = ff;
+            c->pub_qlen = S.qlen;
+            c->pub_insp_sum = S.insp_sum;
+            c->pub_fsel = S.fsel;
+            c->pub_flen = S.flen;
+            c->pub_fbase = S.fbase;
+            c->pub_T = S.T;
+            c->pub_Tnext = S.Tnext;
+            __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ack_need += gridDim.x - (small ? 1u : (uint32_t)P.team);
+          }
         }
         force_full = ff;
         __syncthreads();
-        if (!ok) break;
+        if (!ok || (blockIdx.x == 0 && L.ackbad)) {
+          ok = false;
+          break;
+        }
       } else {
         if (threadIdx.x == 0) {
           const int bad = !fg_wait_geq(&P.ctl->sm_signal, sm_seen, P.ctl->bar + FG_BAR_STRIDE, 4096);
