@@ -72,6 +72,7 @@ class _Kind:
         self.free = list(range(LANES - 1, -1, -1))
         self.single_ws = None
         self.single_bytes = 0
+        self.single_out = None
         self.cost = None
         self.it_ms = None  # running estimate of the batch's time per iteration
         self.it_seen = 0   # the batch's iteration count after its last step
@@ -121,6 +122,17 @@ class Server:
         self.counts = collections.Counter()
         self.bfs_opts = fg.bfs_opts(mode=fg.FG_MODE_DO)
         self.stats = None
+
+    def close(self):
+        """Close every batch and drop the workspaces (waits for the device)."""
+        self.stream.synchronize()
+        for k in self.kinds.values():
+            if k.batch is not None:
+                self._close_batch(k)
+            k.single_ws = None
+            k.single_out = None
+            self.used -= k.single_bytes
+            k.single_bytes = 0
 
     # ---------------------------------------------------------- memory
     def _reserve(self, nbytes, keep=None):
@@ -221,7 +233,12 @@ class Server:
         r.start = now_fn()
         r.path = "single"
         g = k.g
-        out = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+        if self.keep or k.single_out is None:
+            out = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+            if not self.keep:
+                k.single_out = out  # results are dropped: one buffer per kind
+        else:
+            out = k.single_out
         if self.stats is None:
             self.stats = fg.new_stats(g.off.device)
         if k.kind == BFS:
@@ -367,12 +384,14 @@ def serve_stream(server, reqs, time_limit=600.0):
     return server.finished
 
 
-def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None):
+def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None, keep_results=True):
     """The one-at-a-time plain path: each request runs alone (fg_bfs /
-    fg_sssp) in arrival order, on the same stream and device."""
+    fg_sssp) in arrival order, on the same stream and device.  Without
+    keep_results the outputs go to one buffer per graph and are dropped."""
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
     out = []
+    bufs = {}
     o = fg.bfs_opts(mode=fg.FG_MODE_DO)
     for r in reqs:
         while True:
@@ -382,7 +401,12 @@ def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None):
             time.sleep(min(dt, 0.002))
         r.start = now()
         g = graphs[r.graph]
-        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        if keep_results:
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        else:
+            d = bufs.get(r.graph)
+            if d is None:
+                d = bufs[r.graph] = torch.empty(g.n, dtype=torch.int32, device="cuda")
         if r.kind == BFS:
             ws = bfs_ws[r.graph] if bfs_ws else None
             fg.bfs_into(g, r.src, d, None, o if g.symmetric else fg.bfs_opts(mode=fg.FG_MODE_PUSH),
@@ -391,7 +415,7 @@ def serve_fifo(graphs, reqs, sssp_ws, time_limit=600.0, bfs_ws=None):
             fg.sssp_into(g, r.src, d, None, ws=sssp_ws[r.graph])
         torch.cuda.current_stream().synchronize()
         r.done = now()
-        r.result = d
+        r.result = d if keep_results else None
         r.path = "single"
         out.append(r)
         if now() > time_limit:
