@@ -6,7 +6,8 @@ the C source ``oracle.c`` is built with gcc into ``oracle/liborc.so`` and
 wrapped here with ctypes over numpy arrays.
 
 Pins (what fixes each function independently of itself) are listed in the
-test module ``tests/test_oracle_pins.py``.  Parity unpinned: none of the
+test modules ``tests/test_oracle_pins.py`` and ``tests/test_oracle_pins_next.py``.
+Parity unpinned: none of the
 functions below; the R-MAT generator that feeds them (``synth``) is pinned
 only by determinism and a dedup-survival sanity bound.
 """
@@ -61,6 +62,12 @@ def load(path=None):
     lib.orc_package.argtypes = [i32, P, i32, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
     lib.orc_bfs_partitioned.restype = i32
     lib.orc_bfs_partitioned.argtypes = [i32, P, P, P, i32, i32, P]
+    lib.orc_dobfs_dupall.restype = i32
+    lib.orc_dobfs_dupall.argtypes = [i32, P, P, P, i32, i32, u32, u32, u32, u32, P, P]
+    lib.orc_cc.restype = i32
+    lib.orc_cc.argtypes = [i32, P, P, P]
+    lib.orc_pagerank.restype = i32
+    lib.orc_pagerank.argtypes = [i32, P, P, ctypes.c_double, ctypes.c_double, i32, P]
     if path is None:
         _lib = lib
     return lib
@@ -221,6 +228,39 @@ class Oracle:
         self.lib.orc_bfs_partitioned(n, self._p(off), self._p(col), self._p(owner),
                                      nparts, int(src), self._p(depth))
         return depth
+
+
+    def dobfs_dupall(self, off, col, owner, nparts, src, do_a=(1, 100), do_b=(1, 10)):
+        """O11: returns (depth, direction trace, iterations); raises if the
+        partitions' labels disagree."""
+        off, col = _csr(off, col)
+        n = len(off) - 1
+        depth = np.empty(n, np.int32)
+        dirs = np.zeros(max(n, 1), np.int8)
+        owner = np.ascontiguousarray(owner, np.uint8)
+        it = self.lib.orc_dobfs_dupall(n, self._p(off), self._p(col), self._p(owner), nparts,
+                                       int(src), do_a[0], do_a[1], do_b[0], do_b[1],
+                                       self._p(depth), self._p(dirs))
+        if it < 0:
+            raise AssertionError("partitions disagree on the labels")
+        return depth, dirs[:it].copy(), it
+
+    def cc(self, off, col):
+        """O12: (label = smallest vertex id of the component, number of components)."""
+        off, col = _csr(off, col)
+        n = len(off) - 1
+        label = np.empty(n, np.int32)
+        c = self.lib.orc_cc(n, self._p(off), self._p(col), self._p(label))
+        return label, int(c)
+
+    def pagerank(self, off, col, damping=0.85, tol=0.0, max_iter=20):
+        """O13: (rank float64[n], iterations run)."""
+        off, col = _csr(off, col)
+        n = len(off) - 1
+        rank = np.empty(n, np.float64)
+        it = self.lib.orc_pagerank(n, self._p(off), self._p(col), float(damping), float(tol),
+                                   int(max_iter), self._p(rank))
+        return rank, int(it)
 
 
 _default = None

@@ -25,6 +25,15 @@
  *   O9 orc_bfs_partitioned   serial BSP emulation of multi-GPU BFS (Alg. 1):
  *                            per-partition advance+filter, selective
  *                            communication, combine.
+ *  O11 orc_dobfs_dupall      serial BSP emulation of multi-GPU DOBFS (Alg. 2):
+ *                            duplicate-all vertices, per-partition forward or
+ *                            backward step, broadcast, combine.
+ *  O12 orc_cc                connected components, each vertex labelled with
+ *                            the smallest vertex id of its component.
+ *  O13 orc_pagerank          PageRank power iteration in double precision
+ *                            (Alg. 3 computation: rank update, then
+ *                            accumulation over edges), threshold-ratio or
+ *                            iteration-count convergence.
  *
  * Conventions: depth -1 and parent -1 for unreached vertices, parent[src] =
  * src, SSSP distance UINT32_MAX for unreached vertices.
@@ -592,4 +601,199 @@ int32_t orc_bfs_partitioned(int32_t n, const int32_t* off, const int32_t* col,
   }
   free(P); free(fr); free(nx); free(frl); free(nxl); free(rid); free(rlab); free(rcnt);
   return iter;
+}
+
+/* ----------------------------------------------------------------- O11 */
+
+/*
+ * Multi-GPU direction-optimizing BFS (Alg. 2) with duplicate-all vertices
+ * and broadcast communication (Sec. III-C), emulated serially.  Partition p
+ * holds every vertex (ids unchanged) but only the rows of the vertices it
+ * hosts (owner[v] == p); the other rows are empty on p.  Each partition
+ * keeps its own labels.  Iteration k starts from the frontier of level k,
+ * which is the same on every partition:
+ *   direction   the rule of Sec. VI-A, FV = |Q| |E| / |V| against
+ *               BV = |U| |V| / |P|, from the global counts (|E| the sum of
+ *               the partitions' |E_i|, |V_i| = |V| under duplicate-all), so
+ *               that every partition takes the same direction; forward
+ *               first, forward->backward at most once, strict comparisons,
+ *               do = num / den compared exactly in integers;
+ *   computation forward: each frontier vertex's local row is scanned and
+ *               every neighbour without a label takes k + 1 and joins the
+ *               partition's newly-discovered list N_p; backward: each hosted
+ *               vertex without a label scans its row in order and stops at
+ *               the first neighbour labelled k, taking k + 1 and joining N_p;
+ *   broadcast   every N_p is sent to every other partition;
+ *   combine     a received vertex without a label takes k + 1;
+ *   convergence the union of the N_p (the next frontier) is empty.
+ * depth_out receives partition 0's labels and dir (room for n entries) the
+ * direction of each iteration (0 forward, 1 backward).  Returns the number
+ * of iterations, or -1 if the partitions' labels disagree at the end.
+ */
+int32_t orc_dobfs_dupall(int32_t n, const int32_t* off, const int32_t* col,
+                         const uint8_t* owner, int32_t nparts, int32_t src,
+                         uint32_t a_num, uint32_t a_den, uint32_t b_num, uint32_t b_den,
+                         int32_t* depth_out, int8_t* dir) {
+  const int64_t m = off[n];
+  int32_t** label = (int32_t**)calloc((size_t)nparts, sizeof(int32_t*));
+  int32_t** nl = (int32_t**)calloc((size_t)nparts, sizeof(int32_t*));
+  int32_t* nlen = (int32_t*)calloc((size_t)nparts, sizeof(int32_t));
+  for (int32_t p = 0; p < nparts; ++p) {
+    label[p] = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    nl[p] = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    for (int32_t v = 0; v < n; ++v) label[p][v] = -1;
+    label[p][src] = 0;
+  }
+  /* the frontier of the current level (identical on every partition) */
+  int32_t* q = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* qn = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t qlen = 1;
+  q[0] = src;
+  int64_t pcount = 1;  /* |P|: vertices with a label, frontier included */
+  int cur = 0, switched = 0;
+  int32_t k = 0;
+  while (qlen > 0) {
+    if (k > 0) {
+      unsigned __int128 lhs = (unsigned __int128)(uint64_t)qlen * (uint64_t)m;
+      lhs *= (uint64_t)pcount;
+      unsigned __int128 rhs = (unsigned __int128)(uint64_t)(n - pcount) * (uint64_t)n;
+      rhs *= (uint64_t)n;
+      if (cur == 0) {
+        if (!switched && lhs * a_den > rhs * a_num) {
+          cur = 1;
+          switched = 1;
+        }
+      } else if (lhs * b_den < rhs * b_num) {
+        cur = 0;
+      }
+    }
+    dir[k] = (int8_t)cur;
+    /* computation on every partition, local rows only */
+    for (int32_t p = 0; p < nparts; ++p) {
+      int32_t* L = label[p];
+      nlen[p] = 0;
+      if (cur == 0) {
+        for (int32_t i = 0; i < qlen; ++i) {
+          int32_t u = q[i];
+          if (owner[u] != p) continue; /* remote rows are empty on p */
+          for (int32_t e = off[u]; e < off[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (L[v] == -1) {
+              L[v] = k + 1;
+              nl[p][nlen[p]++] = v;
+            }
+          }
+        }
+      } else {
+        for (int32_t v = 0; v < n; ++v) {
+          if (owner[v] != p || L[v] != -1) continue;
+          for (int32_t e = off[v]; e < off[v + 1]; ++e) {
+            if (L[col[e]] == k) {
+              L[v] = k + 1;
+              nl[p][nlen[p]++] = v;
+              break;
+            }
+          }
+        }
+      }
+    }
+    /* broadcast + combine: every partition takes every other's list */
+    for (int32_t p = 0; p < nparts; ++p)
+      for (int32_t r = 0; r < nparts; ++r) {
+        if (r == p) continue;
+        for (int32_t i = 0; i < nlen[r]; ++i) {
+          int32_t v = nl[r][i];
+          if (label[p][v] == -1) label[p][v] = k + 1;
+        }
+      }
+    /* next frontier: the vertices labelled k + 1 (partition 0's view) */
+    int32_t nq = 0;
+    for (int32_t v = 0; v < n; ++v)
+      if (label[0][v] == k + 1) qn[nq++] = v;
+    int32_t* t = q; q = qn; qn = t;
+    qlen = nq;
+    pcount += nq;
+    k++;
+  }
+  int32_t agree = 1;
+  for (int32_t p = 1; p < nparts; ++p)
+    for (int32_t v = 0; v < n; ++v)
+      if (label[p][v] != label[0][v]) agree = 0;
+  for (int32_t v = 0; v < n; ++v) depth_out[v] = label[0][v];
+  for (int32_t p = 0; p < nparts; ++p) { free(label[p]); free(nl[p]); }
+  free(label); free(nl); free(nlen); free(q); free(qn);
+  return agree ? k : -1;
+}
+
+/* ----------------------------------------------------------------- O12 */
+
+/*
+ * Connected components (Table I's CC primitive): label[v] = the smallest
+ * vertex id in v's component.  Vertices are taken in ascending order; an
+ * unlabelled vertex is the smallest of a new component and labels every
+ * vertex it reaches (FIFO queue).  Returns the number of components.
+ */
+int32_t orc_cc(int32_t n, const int32_t* off, const int32_t* col, int32_t* label) {
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t v = 0; v < n; ++v) label[v] = -1;
+  int32_t comps = 0;
+  for (int32_t s = 0; s < n; ++s) {
+    if (label[s] != -1) continue;
+    comps++;
+    int64_t head = 0, tail = 0;
+    label[s] = s;
+    queue[tail++] = s;
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int32_t e = off[u]; e < off[u + 1]; ++e) {
+        int32_t v = col[e];
+        if (label[v] == -1) {
+          label[v] = s;
+          queue[tail++] = v;
+        }
+      }
+    }
+  }
+  free(queue);
+  return comps;
+}
+
+/* ----------------------------------------------------------------- O13 */
+
+/*
+ * PageRank (Alg. 3's computation, on an undirected CSR where each edge
+ * carries rank both ways), in double precision.  rank_0(v) = 1 / n.  Each
+ * iteration first accumulates over the edges, acc(v) = sum over neighbours
+ * u of rank(u) / deg(u) (the advance step), then updates every vertex,
+ * rank'(v) = (1 - d) / n + d acc(v) (the filter step); rank that reaches a
+ * vertex of degree 0 is not passed on.  Convergence: stop after an
+ * iteration in which every update satisfies |rank' - rank| <= tol * rank
+ * (the threshold ratio; tol = 0 never stops early), or after max_iter
+ * iterations.  Returns the number of iterations run.
+ */
+int32_t orc_pagerank(int32_t n, const int32_t* off, const int32_t* col, double d, double tol,
+                     int32_t max_iter, double* rank) {
+  double* acc = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int32_t v = 0; v < n; ++v) rank[v] = 1.0 / (double)n;
+  int32_t it = 0;
+  while (it < max_iter) {
+    for (int32_t v = 0; v < n; ++v) acc[v] = 0.0;
+    for (int32_t u = 0; u < n; ++u) {
+      int32_t deg = off[u + 1] - off[u];
+      if (deg == 0) continue;
+      double share = rank[u] / (double)deg;
+      for (int32_t e = off[u]; e < off[u + 1]; ++e) acc[col[e]] += share;
+    }
+    int converged = 1;
+    for (int32_t v = 0; v < n; ++v) {
+      double nr = (1.0 - d) / (double)n + d * acc[v];
+      double diff = nr > rank[v] ? nr - rank[v] : rank[v] - nr;
+      if (diff > tol * rank[v]) converged = 0;
+      rank[v] = nr;
+    }
+    it++;
+    if (converged && tol > 0) break;
+  }
+  free(acc);
+  return it;
 }

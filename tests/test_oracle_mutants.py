@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_pins_next as nxt
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -26,7 +27,8 @@ MUTANTS = [
     ("do: P excludes Q", "lhs_common *= (uint64_t)p;", "lhs_common *= (uint64_t)(p - q);"),
     ("do: non-strict switch", "if (!switched && lhs_common * a_den > rhs_common * a_num)",
      "if (!switched && lhs_common * a_den >= rhs_common * a_num)"),
-    ("do: switch allowed twice", "switched = 1;", "switched = 0;"),
+    ("do: switch allowed twice", "switched = 1;\n        }\n      } else {\n        if (lhs_common",
+     "switched = 0;\n        }\n      } else {\n        if (lhs_common"),
     ("do: num/den swapped", "lhs_common * a_den > rhs_common * a_num",
      "lhs_common * a_num > rhs_common * a_den"),
     ("do: pull tie switches", "if (lhs_common * b_den < rhs_common * b_num) cur = 0;",
@@ -46,6 +48,28 @@ MUTANTS = [
     ("share conv is local id", "lconv[g2l[v]] = rank[v];", "lconv[g2l[v]] = g2l[v];"),
     ("partitioned combine drops new", "if (S->label[v] == -1 || rlab[q][i] < S->label[v])",
      "if (rlab[q][i] < S->label[v])"),
+    ("dupall backward tests level k-1", "if (L[col[e]] == k) {", "if (L[col[e]] == k - 1) {"),
+    ("dupall backward keeps scanning", "              nl[p][nlen[p]++] = v;\n              break;",
+     "              nl[p][nlen[p]++] = v;"),
+    ("dupall forward skips hosted rows", "if (owner[u] != p) continue;",
+     "if (owner[u] == p) continue;"),
+    ("dupall no broadcast", "if (label[p][v] == -1) label[p][v] = k + 1;", "(void)0;"),
+    ("dupall per-partition edge count", "unsigned __int128 lhs = (unsigned __int128)(uint64_t)qlen * (uint64_t)m;",
+     "unsigned __int128 lhs = (unsigned __int128)(uint64_t)qlen * (uint64_t)(m / nparts);"),
+    ("dupall pull twice", "          cur = 1;\n          switched = 1;\n        }\n      } else if (lhs * b_den",
+     "          cur = 1;\n        }\n      } else if (lhs * b_den"),
+    ("cc labels with the last vertex", "label[v] = s;\n          queue[tail++] = v;",
+     "label[v] = v > s ? v : s;\n          queue[tail++] = v;"),
+    ("cc scans descending", "for (int32_t s = 0; s < n; ++s) {\n    if (label[s] != -1) continue;",
+     "for (int32_t s = n - 1; s >= 0; --s) {\n    if (label[s] != -1) continue;"),
+    ("pagerank divides by receiver degree", "double share = rank[u] / (double)deg;",
+     "double share = rank[u] / (double)(off[u + 2 < n + 1 ? u + 2 : n] - off[u + 1] + 1);"),
+    ("pagerank teleport not divided by n", "double nr = (1.0 - d) / (double)n + d * acc[v];",
+     "double nr = (1.0 - d) + d * acc[v];"),
+    ("pagerank undamped accumulation", "double nr = (1.0 - d) / (double)n + d * acc[v];",
+     "double nr = (1.0 - d) / (double)n + acc[v];"),
+    ("pagerank threshold on new rank", "if (diff > tol * rank[v]) converged = 0;",
+     "if (diff > tol) converged = 0;"),
 ]
 
 
@@ -66,6 +90,17 @@ def battery(orc):
     pins.test_share_build_golden(orc)
     pins.test_package_golden(orc)
     pins.test_partitioned_bfs_equals_bfs(orc, 4)
+    nxt.test_dupall_golden(orc)
+    nxt.test_dupall_equals_bfs_and_schedule(orc, 1)
+    nxt.test_dupall_equals_bfs_and_schedule(orc, 3)
+    nxt.test_dupall_closed_forms(orc)
+    nxt.test_cc_golden_and_isolated(orc)
+    nxt.test_cc_matches_scipy_and_reachability(orc, 1)
+    nxt.test_cc_rmat_and_grid(orc)
+    nxt.test_pagerank_regular_graphs_stay_uniform(orc)
+    nxt.test_pagerank_star_closed_form(orc)
+    nxt.test_pagerank_matches_dense_iteration_and_solve(orc, 0)
+    nxt.test_pagerank_threshold_stops_when_all_updates_small(orc)
 
 
 def test_battery_passes_on_real_oracle(orc):
