@@ -194,6 +194,24 @@ fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
                  void* ws, size_t ws_bytes, int32_t* depth, int32_t* parent,
                  fg_run_stats* stats, void* stream);
 
+/*
+ * fg_bfs without allocations, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same search, arguments, outputs and errors as fg_bfs
+ * in modes FG_MODE_DO and FG_MODE_PUSH, but the workspace is a static
+ * device array of FG_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends; the call itself allocates
+ * nothing.  Graphs whose workspace (fg_workspace_bytes(g, FG_PRIM_BFS, 0))
+ * exceeds that size get FG_ENOMEM; FG_MODE_PUSH_UNFUSED gets
+ * FG_EUNSUPPORTED.  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (other streams, other threads) race and
+ * give wrong results; calls ordered on one stream are safe.
+ */
+#define FG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+fg_status fg_bfs_noalloc(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
+                         int32_t* depth, int32_t* parent, fg_run_stats* stats, void* stream);
+
 /* -------------------------------------------------------------------- SSSP */
 
 typedef struct {

@@ -164,6 +164,7 @@ SIGNATURES = {
     "fg_stats_read": (_I32, [_P, ctypes.POINTER(RunStats), _P]),
     "fg_bfs_opts_default": (None, [ctypes.POINTER(BfsOpts)]),
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_bfs_noalloc": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _P, _P, _P]),
     "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
     "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_msbfs_opts_default": (None, [ctypes.POINTER(MsOpts)]),
@@ -330,6 +331,16 @@ def bfs_into(g, src, depth, parent=None, opts=None, ws=None, stats=None, stream=
     _check(lib().fg_bfs(g.handle, int(src), ctypes.byref(opts) if opts is not None else None,
                         _ptr(ws), ws.numel(), _ptr(depth), _ptr(parent), _ptr(stats),
                         _stream(stream)))
+
+
+FG_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def bfs_noalloc_into(g, src, depth, parent=None, opts=None, stats=None, stream=None):
+    """Enqueue fg_bfs_noalloc (workspace in the library's static device
+    array, no allocation) on `stream`."""
+    _check(lib().fg_bfs_noalloc(g.handle, int(src), ctypes.byref(opts) if opts is not None else None,
+                                _ptr(depth), _ptr(parent), _ptr(stats), _stream(stream)))
 
 
 def bfs(g, src, mode=FG_MODE_DO, parents=True, opts=None, **kw):

@@ -23,6 +23,8 @@
 //   control   barrier, counters, hand-back state of the small-frontier mode
 #include <string.h>
 
+#include <mutex>
+
 #include "frontier.h"
 
 namespace {
@@ -1567,4 +1569,72 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
     return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);
   return bfs_launch(g, src, o, lay, depth, parent, stats, (hipStream_t)stream);
+}
+
+// ------------------------------------------------ BFS without allocations
+//
+// The workspace of fg_bfs_noalloc lives in this file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address of each GPU's copy is looked up once per
+// device with hipGetSymbolAddress and used from then on.
+static __device__ __align__(256) unsigned char scratch[FG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEV];
+
+// Zeroes `words` 32-bit words (a fill kernel rather than a memset node, so
+// the call can also be recorded into a graph).
+__global__ void zero_words_kernel(uint32_t* p, int32_t words) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+}  // namespace
+
+static fg_status scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEV)
+    return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fg_set_error(FG_EDEVICE, "fg_bfs_noalloc: hipGetSymbolAddress failed: %s",
+                          hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FG_OK;
+}
+
+extern "C" fg_status fg_bfs_noalloc(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
+                                    int32_t* depth, int32_t* parent, fg_run_stats* stats,
+                                    void* stream) {
+  fg_bfs_opts o;
+  fg_status rc = bfs_check("fg_bfs_noalloc", g, src, opts, depth, &o);
+  if (rc != FG_OK) return rc;
+  if (o.mode == FG_MODE_PUSH_UNFUSED)
+    return fg_set_error(FG_EUNSUPPORTED,
+                        "fg_bfs_noalloc: FG_MODE_PUSH_UNFUSED needs a caller workspace (fg_bfs)");
+  const size_t need = bfs_layout(g, nullptr).bytes;
+  if (need > (size_t)FG_NOALLOC_SCRATCH_BYTES)
+    return fg_set_error(FG_ENOMEM,
+                        "fg_bfs_noalloc: the graph needs %zu bytes of workspace, more than the "
+                        "%zu-byte static scratch; use fg_bfs with a caller workspace",
+                        need, (size_t)FG_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  void* ws = nullptr;
+  rc = scratch_ptr(dev, &ws);
+  if (rc != FG_OK) return rc;
+  BfsLayout lay = bfs_layout(g, ws);
+  hipStream_t s = (hipStream_t)stream;
+  // the scratch keeps whatever the previous call on this GPU left: the
+  // control block must start at zero (the rest is written before it is read)
+  const int32_t ctl_words = (int32_t)(sizeof(BfsCtl) / 4);
+  zero_words_kernel<<<(ctl_words + 255) / 256, 256, 0, s>>>((uint32_t*)lay.ctl, ctl_words);
+  FG_HIP_TRY(hipGetLastError());
+  return bfs_launch(g, src, o, lay, depth, parent, stats, s);
 }

@@ -75,6 +75,7 @@ def test_new_entry_points_argument_errors(fg):
     assert L.fg_combine(None, None, None, None, 0, None, None, None, None, None, None,
                         None) == fg.FG_EINVAL
     assert L.fg_share_seed(None, 0, None, None, None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_bfs_noalloc(None, 0, None, None, None, None, None) == fg.FG_EINVAL
     assert L.fg_package_workspace_bytes(None, 10) == 0
     # sssp / batched BFS
     assert L.fg_sssp(None, 0, None, None, 0, None, None, None, None) == fg.FG_EINVAL
