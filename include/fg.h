@@ -573,6 +573,100 @@ fg_status fg_combine(const fg_graph* g, const int32_t* ids, const int32_t* label
                      uint32_t* visited, int32_t* depth, int32_t* parent, int32_t* out_q,
                      int32_t* out_len, void* stream);
 
+/* ------------------------------- duplicate-all + broadcast DOBFS (Alg. 2) */
+
+/*
+ * One partition of a multi-GPU direction-optimizing BFS under the
+ * duplicate-all vertex model with broadcast communication (Sec. III-C; the
+ * BFS of Alg. 2 with the direction rule of Sec. VI-A; the newly-discovered
+ * set as the direction-independent view of Sec. VI-A).  The partition
+ * keeps every one of the n vertices under its global id but only the rows
+ * of the vertices it hosts (owner[v] == part); one GPU would hold one
+ * fg_dup, and on a single GPU several fg_dup objects emulate the
+ * partitions, with device copies standing in for the transfers.
+ *
+ * Per iteration, on every partition: fg_dup_step (direction from the
+ * global counts, identical on every partition; forward: the hosted
+ * frontier vertices' rows are expanded and unlabelled neighbours take the
+ * next depth; backward: every hosted unlabelled vertex scans its row in
+ * order and stops at the first labelled neighbour), then fg_dup_send from
+ * every partition to every other one (the broadcast: the newly-discovered
+ * set as an id list after a forward step, as an n-bit bitmap after a
+ * backward step), then fg_dup_combine (received vertices not yet labelled
+ * take the next depth; the union is the next frontier; the iteration's
+ * counters, direction state and trace advance on the device).  Nothing is
+ * read back between iterations; fg_dup_poll reads the stop flag.
+ *
+ * The same rule as fg_bfs decides directions (do_a / do_b of `opts`, NULL =
+ * 1/100 and 1/10; other fields of opts are ignored), with |E| = m, the edge
+ * count of the whole graph, and |V| = n.  Depths equal fg_bfs's on the whole
+ * graph.  Parents: each partition writes parent[v] for the vertices it
+ * discovers itself (global ids; parent[src] = src); the partitions may
+ * share one parent array, and a vertex discovered by several partitions in
+ * the same forward step then keeps one of their (valid) parents.
+ */
+typedef struct fg_dup fg_dup;
+
+typedef struct {
+  int32_t n;              /* vertices (global)                          */
+  int32_t nparts;
+  int32_t part;
+  int32_t hosted;         /* vertices this partition hosts              */
+  int64_t m_local;        /* CSR entries of the hosted rows             */
+  int64_t m_total;        /* CSR entries of the whole graph             */
+  int64_t resident_bytes; /* device bytes held by the object            */
+} fg_dup_info_t;
+
+/*
+ * Builds partition `part` of `nparts` (1..16) from the whole graph's host
+ * CSR (row_offsets int32[n+1], col_idx int32[m]) and the host owner map
+ * (uint8[n], values < nparts).  The object owns its device copy of the
+ * hosted rows and its traversal state (about 4n (3 + nparts) + n/8 (3 +
+ * nparts) bytes besides the rows).  Errors: FG_EINVAL (bad CSR or owner
+ * map), FG_ENOMEM, FG_EDEVICE.
+ */
+fg_status fg_dup_create(int32_t n, int64_t m, const int32_t* row_offsets,
+                        const int32_t* col_idx, const uint8_t* owner, int32_t nparts,
+                        int32_t part, const fg_bfs_opts* opts, void* stream, fg_dup** out);
+fg_status fg_dup_destroy(fg_dup* d);
+fg_status fg_dup_info(const fg_dup* d, fg_dup_info_t* info);
+/* The partition's CSR (n vertices, only hosted rows non-empty; owned). */
+const fg_graph* fg_dup_graph(const fg_dup* d);
+
+/*
+ * Source setting: depth (device int32[n]) = -1 except depth[src] = 0,
+ * parent (device int32[n] or NULL) = -1 except parent[src] = src, visited =
+ * {src}, frontier = {src}; `stats` (device fg_run_stats or NULL) receives the
+ * iteration trace (dir, frontier = |Q| of the whole graph, inspected = CSR
+ * entries read by this partition).  depth / parent / stats stay bound to
+ * the object until the next seed.  Errors: FG_EINVAL.
+ */
+fg_status fg_dup_seed(fg_dup* d, int32_t src, int32_t* depth, int32_t* parent,
+                      fg_run_stats* stats, void* stream);
+/* The local computation of one iteration (writes the outgoing message). */
+fg_status fg_dup_step(fg_dup* d, void* stream);
+/* The broadcast leg from -> to: copies from's message of this iteration into
+ * to's receive slot for from's partition.  Errors: FG_EINVAL (same object,
+ * or partitions of different graphs / counts). */
+fg_status fg_dup_send(const fg_dup* from, fg_dup* to, void* stream);
+/* Merges the received messages with the partition's own and advances the
+ * iteration (device-side). */
+fg_status fg_dup_combine(fg_dup* d, void* stream);
+/* Synchronises `stream` and reads the stop flag and the iterations run. */
+fg_status fg_dup_poll(const fg_dup* d, int32_t* done, int32_t* iterations, void* stream);
+
+/*
+ * The whole traversal from `src` over parts[0..nparts) (parts[p] must be
+ * partition p of nparts, all of one graph): seeds every partition, then
+ * enqueues step / send / combine rounds, reading the stop flag every
+ * `poll_every` iterations (< 1: 4).  depth[p] / parent[p] / stats[p] are
+ * partition p's outputs (parent and stats may be NULL, or hold NULL
+ * entries).  Errors: FG_EINVAL, FG_EDEVICE.
+ */
+fg_status fg_dup_run(fg_dup* const* parts, int32_t nparts, int32_t src,
+                     int32_t* const* depth, int32_t* const* parent,
+                     fg_run_stats* const* stats, int32_t poll_every, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -137,6 +137,18 @@ class ShareInfo(ctypes.Structure):
     ]
 
 
+class DupInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("nparts", ctypes.c_int32),
+        ("part", ctypes.c_int32),
+        ("hosted", ctypes.c_int32),
+        ("m_local", ctypes.c_int64),
+        ("m_total", ctypes.c_int64),
+        ("resident_bytes", ctypes.c_int64),
+    ]
+
+
 class PeerBufs(ctypes.Structure):
     _fields_ = [
         ("ids", ctypes.c_void_p),
@@ -200,6 +212,18 @@ SIGNATURES = {
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "fg_queue_to_bitmap": (_I32, [_P, _P, _I32, _P, _P]),
     "fg_bitmap_to_queue": (_I32, [_P, _P, _P, _P, _P, _SZ, _P]),
+    "fg_dup_create": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I32, ctypes.POINTER(BfsOpts), _P,
+                             ctypes.POINTER(_P)]),
+    "fg_dup_destroy": (_I32, [_P]),
+    "fg_dup_info": (_I32, [_P, ctypes.POINTER(DupInfo)]),
+    "fg_dup_graph": (_P, [_P]),
+    "fg_dup_seed": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "fg_dup_step": (_I32, [_P, _P]),
+    "fg_dup_send": (_I32, [_P, _P, _P]),
+    "fg_dup_combine": (_I32, [_P, _P]),
+    "fg_dup_poll": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _P]),
+    "fg_dup_run": (_I32, [ctypes.POINTER(_P), _I32, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                          ctypes.POINTER(_P), _I32, _P]),
 }
 
 
@@ -692,3 +716,84 @@ def combine(graph_handle, ids, labels, parents, length, visited, depth, parent, 
 
 def _op_handle(g):
     return g.handle if isinstance(g, Graph) else g
+
+
+class DupBfs:
+    """Direction-optimizing BFS over `nparts` duplicate-all partitions with
+    broadcast communication (fg_dup_*), all on the current GPU: one fg_dup
+    per partition, each with its own depth array and trace; the partitions
+    share one parent array."""
+
+    def __init__(self, row_offsets, col_idx, owner, nparts, do_a=(1, 100), do_b=(1, 10),
+                 stream=None):
+        import numpy as np
+        L = lib()
+        off = np.ascontiguousarray(row_offsets, dtype=np.int32)
+        col = np.ascontiguousarray(col_idx, dtype=np.int32)
+        own = np.ascontiguousarray(owner, dtype=np.uint8)
+        o = bfs_opts(mode=FG_MODE_DO, do_a=do_a, do_b=do_b)
+        self.n = len(off) - 1
+        self.nparts = nparts
+        self.handles = []
+        for p in range(nparts):
+            h = ctypes.c_void_p()
+            _check(L.fg_dup_create(self.n, len(col), off.ctypes.data,
+                                   col.ctypes.data if len(col) else None, own.ctypes.data,
+                                   nparts, p, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+            self.handles.append(h)
+        self.depth = [torch.empty(self.n, dtype=torch.int32, device="cuda") for _ in range(nparts)]
+        self.parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.stats = [new_stats() for _ in range(nparts)]
+
+    def info(self, p):
+        i = DupInfo()
+        _check(lib().fg_dup_info(self.handles[p], ctypes.byref(i)))
+        return i
+
+    def run(self, src, poll_every=4, stream=None):
+        """The whole traversal (fg_dup_run); enqueued on `stream`, whose
+        stop-flag reads synchronise it."""
+        P = self.nparts
+        hs = (_P * P)(*[h.value for h in self.handles])
+        ds = (_P * P)(*[d.data_ptr() for d in self.depth])
+        ps = (_P * P)(*([self.parent.data_ptr()] * P))
+        ss = (_P * P)(*[s.data_ptr() for s in self.stats])
+        _check(lib().fg_dup_run(hs, P, int(src), ds, ps, ss, int(poll_every), _stream(stream)))
+
+    # the per-iteration calls, for callers that drive the rounds themselves
+    def seed(self, src, stream=None):
+        for p in range(self.nparts):
+            _check(lib().fg_dup_seed(self.handles[p], int(src), _ptr(self.depth[p]),
+                                     _ptr(self.parent), _ptr(self.stats[p]), _stream(stream)))
+
+    def round(self, stream=None):
+        L, sp = lib(), _stream(stream)
+        for h in self.handles:
+            _check(L.fg_dup_step(h, sp))
+        for p, hp in enumerate(self.handles):
+            for q, hq in enumerate(self.handles):
+                if p != q:
+                    _check(L.fg_dup_send(hp, hq, sp))
+        for h in self.handles:
+            _check(L.fg_dup_combine(h, sp))
+
+    def poll(self, p=0, stream=None):
+        done, it = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fg_dup_poll(self.handles[p], ctypes.byref(done), ctypes.byref(it),
+                                 _stream(stream)))
+        return bool(done.value), int(it.value)
+
+    def read_stats(self, p, stream=None):
+        return read_stats(self.stats[p], stream)
+
+    def close(self):
+        for h in getattr(self, "handles", []):
+            if h:
+                lib().fg_dup_destroy(h)
+        self.handles = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,3 +86,32 @@ def test_new_entry_points_argument_errors(fg):
     assert L.fg_msbfs_close(None) == fg.FG_OK
     assert L.fg_graph_csr(None, None, None, None) == fg.FG_EINVAL
     assert L.fg_share_graph(None) is None
+
+
+def test_dup_argument_errors_without_gpu(fg):
+    import numpy as np
+    L = fg.lib()
+    h = ctypes.c_void_p()
+    off = np.array([0, 1, 2], np.int32)
+    col = np.array([1, 0], np.int32)
+    own = np.array([0, 1], np.uint8)
+    p = lambda a: a.ctypes.data  # noqa: E731
+    assert L.fg_dup_create(2, 2, p(off), p(col), p(own), 0, 0, None, None,
+                           ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_dup_create(2, 2, p(off), p(col), p(own), 2, 2, None, None,
+                           ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_dup_create(2, 2, p(off), p(col), p(own), 1, 0, None, None,
+                           ctypes.byref(h)) == fg.FG_EINVAL
+    assert "owner" in fg.last_error()
+    bad = np.array([0, 2, 1], np.int32)
+    assert L.fg_dup_create(2, 2, p(bad), p(col), p(own), 2, 0, None, None,
+                           ctypes.byref(h)) == fg.FG_EINVAL
+    assert L.fg_dup_create(2, 2, p(off), p(col), p(own), 2, 0, None, None, None) == fg.FG_EINVAL
+    assert L.fg_dup_step(None, None) == fg.FG_EINVAL
+    assert L.fg_dup_send(None, None, None) == fg.FG_EINVAL
+    assert L.fg_dup_combine(None, None) == fg.FG_EINVAL
+    assert L.fg_dup_seed(None, 0, None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_dup_poll(None, None, None, None) == fg.FG_EINVAL
+    assert L.fg_dup_info(None, None) == fg.FG_EINVAL
+    assert L.fg_dup_run(None, 0, 0, None, None, None, 0, None) == fg.FG_EINVAL
+    assert L.fg_dup_destroy(None) == fg.FG_OK
