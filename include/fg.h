@@ -113,6 +113,7 @@ fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets, const int
 #define FG_PRIM_SSSP 2         /* fg_sssp                                      */
 #define FG_PRIM_MSBFS 3        /* fg_msbfs_* with `lanes` <= 64                */
 #define FG_PRIM_MSSSP 4        /* fg_mssp_* (any `lanes` <= 64)                */
+#define FG_PRIM_PR 5           /* fg_pagerank                                  */
 
 /*
  * Bytes of device workspace a call needs (just-enough sizing, Sec. VI-B:
@@ -666,6 +667,43 @@ fg_status fg_dup_poll(const fg_dup* d, int32_t* done, int32_t* iterations, void*
 fg_status fg_dup_run(fg_dup* const* parts, int32_t nparts, int32_t src,
                      int32_t* const* depth, int32_t* const* parent,
                      fg_run_stats* const* stats, int32_t poll_every, void* stream);
+
+/* ------------------------------------------------- connected components */
+
+/*
+ * Connected components (Table I's CC primitive, computed by hooking and
+ * pointer jumping): label[v] = the smallest vertex id of v's component, so
+ * the labelling is unique.  label: device int32[n], also the working
+ * forest while the call runs (no workspace).  components: device int64 or
+ * NULL; receives the number of components.  Needs an undirected graph
+ * (FG_SYMMETRIC), else FG_EUNSUPPORTED.  Errors: FG_EINVAL, FG_EDEVICE.
+ */
+fg_status fg_cc(const fg_graph* g, int32_t* label, int64_t* components, void* stream);
+
+/* ---------------------------------------------------------------- PageRank */
+
+/*
+ * PageRank by power iteration in double precision (Table I's PR primitive:
+ * the rank update and the accumulation over edges of Alg. 3) on an
+ * undirected graph, each edge carrying rank both ways.  rank_0 = 1/n; an
+ * iteration sets rank'(v) = (1 - damping)/n + damping * sum over the
+ * neighbours u of v of rank(u)/deg(u) (rank reaching a vertex of degree 0
+ * is not passed on).  The run stops after an iteration in which every
+ * vertex changed by at most tol times its previous rank (tol > 0), or
+ * after max_iter iterations (tol = 0 runs exactly max_iter).  rank: device
+ * double[n], the output.  ws: fg_workspace_bytes(g, FG_PRIM_PR, 0) bytes
+ * (any contents).  stats (device, may be NULL): iterations run, and per
+ * iteration frontier[i] = vertices whose change exceeded the threshold,
+ * inspected[i] = m.  Nothing is read back: every one of the max_iter
+ * iterations is enqueued and those after convergence return at once.
+ * Sums over long rows are taken in a different order than a serial loop,
+ * so ranks agree with a serial evaluation to rounding, not bit for bit.
+ * Errors: FG_EINVAL (damping outside [0, 1], tol < 0, max_iter outside
+ * [0, 100000]), FG_ENOMEM (workspace), FG_EUNSUPPORTED (directed graph).
+ */
+fg_status fg_pagerank(const fg_graph* g, double damping, double tol, int32_t max_iter,
+                      void* ws, size_t ws_bytes, double* rank, fg_run_stats* stats,
+                      void* stream);
 
 #ifdef __cplusplus
 }

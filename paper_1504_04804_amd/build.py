@@ -9,7 +9,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfg.so")
 
 SOURCES = ["abi.cpp", "graph.hip", "bfs.hip", "ops.hip", "sssp.hip", "package.hip", "msbfs.hip",
-           "dupall.hip",
+           "dupall.hip", "cc.hip", "pagerank.hip",
            "mssp.hip"]
 
 HIPCC_FLAGS = [

@@ -347,6 +347,7 @@ extern "C" size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32
     case FG_PRIM_MSSSP:
       if (lanes < 1 || lanes > 64) return 0;
       return fg_mssp_workspace_bytes(g);
+    case FG_PRIM_PR: return fg_pr_workspace_bytes(g);
     default: return 0;
   }
 }
