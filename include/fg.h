@@ -114,6 +114,7 @@ fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets, const int
 #define FG_PRIM_MSBFS 3        /* fg_msbfs_* with `lanes` <= 64                */
 #define FG_PRIM_MSSSP 4        /* fg_mssp_* (any `lanes` <= 64)                */
 #define FG_PRIM_PR 5           /* fg_pagerank                                  */
+#define FG_PRIM_CC 6           /* fg_cc                                        */
 
 /*
  * Bytes of device workspace a call needs (just-enough sizing, Sec. VI-B:
@@ -674,11 +675,13 @@ fg_status fg_dup_run(fg_dup* const* parts, int32_t nparts, int32_t src,
  * Connected components (Table I's CC primitive, computed by hooking and
  * pointer jumping): label[v] = the smallest vertex id of v's component, so
  * the labelling is unique.  label: device int32[n], also the working
- * forest while the call runs (no workspace).  components: device int64 or
- * NULL; receives the number of components.  Needs an undirected graph
- * (FG_SYMMETRIC), else FG_EUNSUPPORTED.  Errors: FG_EINVAL, FG_EDEVICE.
+ * forest while the call runs.  components: device int64 or NULL; receives
+ * the number of components.  ws: fg_workspace_bytes(g, FG_PRIM_CC, 0)
+ * bytes (any contents).  Needs an undirected graph (FG_SYMMETRIC), else
+ * FG_EUNSUPPORTED.  Errors: FG_EINVAL, FG_ENOMEM (workspace), FG_EDEVICE.
  */
-fg_status fg_cc(const fg_graph* g, int32_t* label, int64_t* components, void* stream);
+fg_status fg_cc(const fg_graph* g, int32_t* label, int64_t* components, void* ws,
+                size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- PageRank */
 

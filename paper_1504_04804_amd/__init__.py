@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libfg.so")
 
 FG_OK, FG_EINVAL, FG_ENOMEM, FG_EDEVICE, FG_EOVERFLOW, FG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FG_DEVICE_PTRS, FG_BORROW, FG_VALIDATE, FG_SYMMETRIC = 1, 2, 4, 8
-FG_PRIM_BFS, FG_PRIM_BFS_UNFUSED, FG_PRIM_SSSP, FG_PRIM_MSBFS, FG_PRIM_MSSSP, FG_PRIM_PR = 0, 1, 2, 3, 4, 5
+FG_PRIM_BFS, FG_PRIM_BFS_UNFUSED, FG_PRIM_SSSP, FG_PRIM_MSBFS, FG_PRIM_MSSSP = 0, 1, 2, 3, 4
+FG_PRIM_PR, FG_PRIM_CC = 5, 6
 FG_MODE_DO, FG_MODE_PUSH, FG_MODE_PUSH_UNFUSED = 0, 1, 2
 FG_TRACE_MAX = 64
 PUSH, PULL = 0, 1
@@ -212,7 +213,7 @@ SIGNATURES = {
     "fg_pull_step": (_I32, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "fg_queue_to_bitmap": (_I32, [_P, _P, _I32, _P, _P]),
     "fg_bitmap_to_queue": (_I32, [_P, _P, _P, _P, _P, _SZ, _P]),
-    "fg_cc": (_I32, [_P, _P, _P, _P]),
+    "fg_cc": (_I32, [_P, _P, _P, _P, _SZ, _P]),
     "fg_pagerank": (_I32, [_P, ctypes.c_double, ctypes.c_double, _I32, _P, _SZ, _P, _P, _P]),
     "fg_dup_create": (_I32, [_I32, _I64, _P, _P, _P, _I32, _I32, ctypes.POINTER(BfsOpts), _P,
                              ctypes.POINTER(_P)]),
@@ -720,11 +721,13 @@ def _op_handle(g):
     return g.handle if isinstance(g, Graph) else g
 
 
-def cc_into(g, label, components=None, stream=None):
+def cc_into(g, label, components=None, ws=None, stream=None):
     """Enqueue fg_cc: label (device int32[n]) receives the smallest vertex id
     of each vertex's component; components (device int64[1] or None) the
     number of components."""
-    _check(lib().fg_cc(g.handle, _ptr(label), _ptr(components), _stream(stream)))
+    ws = ws if ws is not None else g.workspace(FG_PRIM_CC)
+    _check(lib().fg_cc(g.handle, _ptr(label), _ptr(components), _ptr(ws), ws.numel(),
+                       _stream(stream)))
 
 
 def cc(g):

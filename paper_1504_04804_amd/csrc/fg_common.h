@@ -46,6 +46,7 @@ size_t fg_sssp_workspace_bytes(const fg_graph* g);
 size_t fg_msbfs_workspace_bytes(const fg_graph* g, int32_t lanes);
 size_t fg_mssp_workspace_bytes(const fg_graph* g);
 size_t fg_pr_workspace_bytes(const fg_graph* g);
+size_t fg_cc_workspace_bytes(const fg_graph* g);
 void fg_bfs_launch_init(const fg_graph* g, int32_t src, int32_t* depth, int32_t* parent,
                         uint64_t* vis0, int32_t* q0, fg_run_stats* stats, hipStream_t s,
                         void* ctl, int32_t ctl_bytes);

@@ -348,6 +348,7 @@ extern "C" size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32
       if (lanes < 1 || lanes > 64) return 0;
       return fg_mssp_workspace_bytes(g);
     case FG_PRIM_PR: return fg_pr_workspace_bytes(g);
+    case FG_PRIM_CC: return fg_cc_workspace_bytes(g);
     default: return 0;
   }
 }
