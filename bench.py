@@ -56,6 +56,11 @@ def parse():
     ap.add_argument("--cpu-sources", type=int, default=8)
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the per-config side measurements (SSSP, package, batched, serving)")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated side measurements to run (sssp, package, batched, "
+                         "batched_sssp, dupall, cc, pagerank, serving); the others are skipped")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the duplicate-all DOBFS, CC and PageRank measurements")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving sweep (the other side measurements still run)")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -536,6 +541,202 @@ def side_batched_sssp(fg, torch, stream, rmat22, cpu):
     return res
 
 
+# ------------------------------------------- widened rows: dup-all, CC, PR
+
+def dup_alg_bytes(sts, n, nparts, hosted_nz):
+    """Algorithmic bytes of one duplicate-all DOBFS traversal over all
+    partitions, from their traces (identical dir / frontier, per-partition
+    inspected).  Per iteration and partition:
+      forward : 12 B per hosted frontier vertex (id, 2 offsets), 4 B per
+                row entry read, the visited word of each target (at most
+                n/8), 12 B per vertex it discovers (depth, parent, message
+                entry); the message (4 B per id) is read once and written
+                to each of the nparts - 1 peers; the combine reads each
+                received id and labels the new ones (4 B);
+      backward: nonzero mask + visited (2 n/8), 8 B per hosted candidate,
+                4 B per row entry read, the visited bitmap as frontier (n/8),
+                8 B per discovered vertex, the n/8 message written and copied
+                to every peer; the combine reads the nparts messages and
+                writes visited + frontier bitmaps (n/8 each) and 4 B per
+                vertex labelled from a message."""
+    st0 = sts[0]
+    k = min(st0.iterations, 64)
+    dirs = list(st0.dir[:k])
+    fr = list(st0.frontier[:k])
+    total = float(nparts * (4 * n + 4 * n + n / 8))  # seeds: depth, parent, visited
+    labelled = 0
+    for i in range(k):
+        new = fr[i + 1] if i + 1 < k else 0
+        insp = [st.inspected[i] for st in sts]
+        if dirs[i] == 0:
+            for p in range(nparts):
+                total += 12 * fr[i] / nparts + 4 * insp[p] + min(n / 8, 4 * insp[p])
+            total += 12 * new + 4 * new * (nparts - 1) * 2 + 4 * new * (nparts - 1)
+        else:
+            u = max(sum(hosted_nz) - labelled - fr[i], 0)
+            for p in range(nparts):
+                total += 3 * n / 8 + 4 * insp[p]
+            total += 8 * u + 8 * new
+            total += nparts * (n / 8) * (nparts - 1) * 2          # sends
+            total += nparts * ((nparts + 2) * n / 8) + 4 * new * (nparts - 1)
+        labelled += fr[i]
+    return total
+
+
+def side_dupall(fg, torch, stream, off, col, srcs, cpu):
+    """Duplicate-all + broadcast DOBFS (Alg. 2) on R-MAT 22 over 4 random
+    owners, the 4 partitions emulated on this GPU, 16 of the 64 sources with
+    the DOBFS workload's thresholds."""
+    import synth
+    from paper_1504_04804_amd import autotune
+    P = 4
+    owner = synth.owners(len(off) - 1, P)
+    g0 = fg.Graph(off, col, symmetric=True, validate=False)
+    _, kw = autotune.workload_opts("rmat22_dobfs", g0)
+    g0.close()
+    t0 = time.time()
+    dup = fg.DupBfs(off, col, owner, P, do_a=kw["do_a"], do_b=kw["do_b"], stream=stream)
+    build_s = time.time() - t0
+    n = len(off) - 1
+    deg = np.diff(off)
+    hosted_nz = [int(((owner == p) & (deg > 0)).sum()) for p in range(P)]
+    srcs = [int(x) for x in srcs[:16]]
+    lat, byts, m_comp, iters = [], [], [], []
+    degd = torch.from_numpy(deg).to("cuda")
+    dup.run(srcs[0], stream=stream)
+    for s_ in srcs:
+        a, b = _ev(), _ev()
+        a.record(stream)
+        dup.run(s_, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+        sts = [dup.read_stats(p) for p in range(P)]
+        assert all(st.status == 0 for st in sts)
+        byts.append(dup_alg_bytes(sts, n, P, hosted_nz))
+        d0 = dup.depth[0]
+        m_comp.append(int(degd[d0 >= 0].sum().item()))
+        iters.append(sts[0].iterations)
+    ms = float(np.mean(lat))
+    gbs = float(np.mean(byts)) / (ms * 1e-3) / 1e9
+    info = [dup.info(p) for p in range(P)]
+    out = {
+        "workload": "duplicate-all + broadcast DOBFS, rmat22 ef16, 4 random owners emulated on one "
+                    "GPU (each partition's step, broadcast copies and combine run back to back), "
+                    f"16 of the 64 sources, do_a={kw['do_a'][0]}/{kw['do_a'][1]} "
+                    f"do_b={kw['do_b'][0]}/{kw['do_b'][1]}",
+        "partitions": P, "m_local": [int(i.m_local) for i in info],
+        "build_s": round(build_s, 2),
+        "ms_per_traversal": round(ms, 4), "ms_p50": round(float(np.percentile(lat, 50)), 4),
+        "iterations_mean": round(float(np.mean(iters)), 2),
+        "us_per_iteration_all_partitions": round(ms * 1e3 / float(np.mean(iters)), 2),
+        "gteps_emulated": round(sum(m_comp) / (sum(lat) * 1e-3) / 1e9, 3),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                     "alg_bytes_per_traversal": round(float(np.mean(byts))),
+                     "note": "all partitions' step, send and combine kernels and the host's "
+                             "stop-flag reads in the timed region"},
+    }
+    dup.close()
+    if cpu:
+        import oracle
+        orc = oracle.oracle()
+        t0 = time.perf_counter()
+        orc.dobfs_dupall(off, col, owner, P, srcs[0], kw["do_a"], kw["do_b"])
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(m_comp[0] / t / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle", "sample": f"oracle duplicate-all emulation "
+                                                           f"from the first source, {t:.1f}s"}
+    return out
+
+
+def side_cc(fg, torch, stream, graphs, cpu):
+    """Connected components (min-id labels) on R-MAT 22 and the 4096 x 4096
+    grid."""
+    res = {}
+    for name, (off, col) in graphs.items():
+        g = fg.Graph(off, col, symmetric=True, validate=False)
+        n, m = g.n, int(g.m)
+        label = torch.empty(n, dtype=torch.int32, device="cuda")
+        comps = torch.zeros(1, dtype=torch.int64, device="cuda")
+        fg.cc_into(g, label, comps, stream=stream)
+        lat = []
+        for _ in range(5):
+            a, b = _ev(), _ev()
+            a.record(stream)
+            fg.cc_into(g, label, comps, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            lat.append(a.elapsed_time(b))
+        ms = float(np.median(lat))
+        # column indices once, offsets once, first neighbour, label written
+        # at init, read and written at compress
+        alg = 4.0 * m + 20.0 * n
+        gbs = alg / (ms * 1e-3) / 1e9
+        res[name] = {"n": n, "m": m, "components": int(comps.item()),
+                     "ms": round(ms, 4), "statistic": "median of 5",
+                     "gteps": round(m / (ms * 1e-3) / 1e9, 3),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                                  "alg_bytes_per_call": round(alg),
+                                  "note": "4 B per CSR entry + 20 B per vertex"}}
+        g.close()
+        if cpu:
+            import oracle
+            orc = oracle.oracle()
+            t0 = time.perf_counter()
+            orc.cc(off, col)
+            t = time.perf_counter() - t0
+            res[name]["cpu_baseline"] = {"value": round(m / t / 1e9, 4), "unit": "GTEPS",
+                                         "cores": 1, "kind": "oracle",
+                                         "sample": f"oracle BFS labelling, one call, {t:.1f}s"}
+    return res
+
+
+def side_pagerank(fg, torch, stream, off, col, cpu):
+    """PageRank, 20 fp64 power iterations (damping 0.85) on R-MAT 22."""
+    g = fg.Graph(off, col, symmetric=True, validate=False)
+    n, m = g.n, int(g.m)
+    rank = torch.empty(n, dtype=torch.float64, device="cuda")
+    ws = g.workspace(fg.FG_PRIM_PR)
+    st = fg.new_stats()
+    iters = 20
+    fg.pagerank_into(g, rank, 0.85, 0.0, iters, ws=ws, stats=st, stream=stream)
+    lat = []
+    for _ in range(3):
+        a, b = _ev(), _ev()
+        a.record(stream)
+        fg.pagerank_into(g, rank, 0.85, 0.0, iters, ws=ws, stats=st, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+    ms = float(np.median(lat))
+    per_it = ms / iters
+    # per iteration: column index (4) and neighbour contribution (8) per CSR
+    # entry; 2 offsets, rank read + written, contribution written per vertex
+    alg = 12.0 * m + 32.0 * n
+    gbs = alg / (per_it * 1e-3) / 1e9
+    out = {"workload": "PageRank rmat22 ef16, damping 0.85, 20 iterations (no early stop), fp64",
+           "n": n, "m": m, "ms_total": round(ms, 4), "ms_per_iteration": round(per_it, 4),
+           "statistic": "median of 3",
+           "gteps_per_iteration": round(m / (per_it * 1e-3) / 1e9, 3),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                        "alg_bytes_per_iteration": round(alg),
+                        "note": "12 B per CSR entry + 32 B per vertex per iteration"}}
+    g.close()
+    if cpu:
+        import oracle
+        orc = oracle.oracle()
+        t0 = time.perf_counter()
+        orc.pagerank(off, col, 0.85, 0.0, 2)
+        t = (time.perf_counter() - t0) / 2
+        out["cpu_baseline"] = {"value": round(m / t / 1e9, 4), "unit": "GTEPS per iteration",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"oracle power iteration, 2 iterations, {2 * t:.1f}s"}
+    return out
+
+
 SERVE_QPS = (25, 50, 100, 150, 200, 300)
 SERVE_SECONDS = 8.0          # arrivals span about this long per load ...
 SERVE_NREQ = (300, 1600)     # ... with at least / at most this many requests
@@ -873,19 +1074,42 @@ def main():
     if not args.headline_only:
         # per-config side measurements (outside the step)
         del depth, parent, gdepth, gparent, ws, gws
-        out["sssp"] = side_sssp(fg, torch, off, col, srcs, stream, not args.no_cpu)
-        print(f"[bench] sssp done", file=sys.stderr, flush=True)
-        t0 = time.time()
-        off24, col24 = synth.rmat_csr(24, EDGE_FACTOR)
-        print(f"[bench] rmat24 generated in {time.time() - t0:.1f}s, m={len(col24)}",
-              file=sys.stderr, flush=True)
-        out["package"] = side_package(fg, torch, stream, not args.no_cpu, off24, col24)
-        print(f"[bench] package done", file=sys.stderr, flush=True)
-        out["batched_c4"] = side_batched(fg, torch, stream, do_kw, not args.no_cpu)
-        print(f"[bench] batched done", file=sys.stderr, flush=True)
-        out["batched_sssp"] = side_batched_sssp(fg, torch, stream, (off, col), not args.no_cpu)
-        print(f"[bench] batched sssp done", file=sys.stderr, flush=True)
-        if not args.no_serving:
+        only = set(args.only.split(",")) if args.only else None
+
+        def want(name):
+            return only is None or name in only
+
+        if want("sssp"):
+            out["sssp"] = side_sssp(fg, torch, off, col, srcs, stream, not args.no_cpu)
+            print(f"[bench] sssp done", file=sys.stderr, flush=True)
+        off24 = col24 = None
+        if want("package") or (want("serving") and not args.no_serving):
+            t0 = time.time()
+            off24, col24 = synth.rmat_csr(24, EDGE_FACTOR)
+            print(f"[bench] rmat24 generated in {time.time() - t0:.1f}s, m={len(col24)}",
+                  file=sys.stderr, flush=True)
+        if want("package"):
+            out["package"] = side_package(fg, torch, stream, not args.no_cpu, off24, col24)
+            print(f"[bench] package done", file=sys.stderr, flush=True)
+        if want("batched"):
+            out["batched_c4"] = side_batched(fg, torch, stream, do_kw, not args.no_cpu)
+            print(f"[bench] batched done", file=sys.stderr, flush=True)
+        if want("batched_sssp"):
+            out["batched_sssp"] = side_batched_sssp(fg, torch, stream, (off, col), not args.no_cpu)
+            print(f"[bench] batched sssp done", file=sys.stderr, flush=True)
+        if not args.no_widened:
+            if want("dupall"):
+                out["dupall"] = side_dupall(fg, torch, stream, off, col, srcs, not args.no_cpu)
+                print(f"[bench] dupall done", file=sys.stderr, flush=True)
+            if want("cc"):
+                out["cc"] = side_cc(fg, torch, stream,
+                                    {"rmat22": (off, col), "grid4096": (goff, gcol)},
+                                    not args.no_cpu)
+                print(f"[bench] cc done", file=sys.stderr, flush=True)
+            if want("pagerank"):
+                out["pagerank"] = side_pagerank(fg, torch, stream, off, col, not args.no_cpu)
+                print(f"[bench] pagerank done", file=sys.stderr, flush=True)
+        if want("serving") and not args.no_serving:
             out["serving"] = side_serving(fg, torch, {"rmat22": (off, col),
                                                       "grid4096": (goff, gcol),
                                                       "rmat24": (off24, col24)})

@@ -541,10 +541,101 @@ __device__ __forceinline__ int32_t probe4(const BfsParams& P, const uint64_t* Vi
 // neighbour has depth exactly k, so the visited bitmap is the frontier
 // test.  Each wave takes bitmap words with a static stride, 64 at a time:
 // it loads the 64 words at once, lists their unvisited vertices of nonzero
-// degree, and runs them 64 per round.  A vertex probes its first four
-// entries itself; up to 16 entries it goes on four at a time, longer lists
-// are scanned by the whole wave, 64 entries per step.  Writes the next
-// visited bitmap Vout = Vin | found (whole words, no atomics).
+// degree, and runs them two per lane and round, probing each vertex's first
+// four entries from the head table.  Vertices with more entries and no hit
+// among the first four are set aside in an LDS list and resumed together
+// once the batch's rounds are done: lists of up to 16 entries four at a
+// time, lane by lane, longer ones by the whole wave, 64 entries per step.
+// (Resumed inside the rounds, the few such lanes held their whole wave for
+// up to three more probe steps per round.)  Writes the next visited bitmap
+// Vout = Vin | found (whole words, no atomics).
+constexpr int PULL_DEFER = STAGE;  // set-aside vertices per wave
+
+// The found vertex v (bit `bit` of batch word jw): depth, parent, next bit.
+__device__ __forceinline__ void pull_found(const BfsParams& P, uint64_t* nbw, int32_t v,
+                                           int32_t pu, int32_t d_new, int32_t jw, int32_t bit) {
+  P.depth[v] = d_new;
+  if (P.parent) P.parent[v] = pu;
+  atomicOr((unsigned long long*)&nbw[jw], 1ull << bit);
+}
+
+// Resumes the set-aside vertices dv[0..cnt) (entries from the fifth on);
+// dj holds jw << 6 | bit.  Every lane of the wave must take part.
+__device__ void pull_resume(const BfsParams& P, const uint64_t* Vin, uint64_t* nbw,
+                            const int32_t* dv, const uint16_t* dj, int32_t cnt, int32_t d_new,
+                            int32_t& insp, int32_t& ndeg, int32_t& nnew) {
+  const int lane = fg_lane();
+  for (int32_t a0 = 0; a0 < cnt; a0 += FG_WAVE) {
+    const int32_t a = a0 + lane;
+    const bool mine = a < cnt;
+    int32_t v = 0, b = 0, e = 0, pu = -1, ins = 0;
+    if (mine) {
+      v = dv[a];
+      b = P.off[v];
+      e = P.off[v + 1];
+    }
+    bool found = false;
+    // lists of up to 16 entries: four at a time, lane by lane
+    bool shortl = mine && e - b <= 16;
+    for (int32_t i0 = 4; i0 < 16 && __ballot(shortl); i0 += 4) {
+      if (shortl) {
+        if (b + i0 < e) {
+          const int32_t h = probe4(P, Vin, b + i0, e, pu);
+          if (h >= 0) {
+            found = true;
+            shortl = false;
+            ins += h + 1;
+          } else {
+            ins += min(4, e - b - i0);
+          }
+        } else {
+          shortl = false;
+        }
+      }
+    }
+    // longer lists: the whole wave scans one at a time
+    uint64_t pend = __ballot(mine && e - b > 16);
+    while (pend) {
+      const int l = __builtin_ctzll(pend);
+      pend &= pend - 1;
+      const int32_t lb = __builtin_amdgcn_readlane(b, l) + 4;
+      const int32_t le = __builtin_amdgcn_readlane(e, l);
+      int32_t cnt2 = 0, hu = -1;
+      for (int32_t i0 = lb; i0 < le; i0 += FG_WAVE) {
+        const int32_t i = i0 + lane;
+        int32_t u = 0;
+        bool hb = false;
+        if (i < le) {
+          u = P.col[i];
+          hb = (Vin[u >> 6] >> (u & 63)) & 1ull;
+        }
+        const uint64_t m = __ballot(hb);
+        if (m) {
+          const int f = __builtin_ctzll(m);
+          cnt2 += f + 1;
+          hu = __builtin_amdgcn_readlane(u, f);
+          break;
+        }
+        cnt2 += min(FG_WAVE, le - i0);
+      }
+      if (lane == l) {
+        ins += cnt2;
+        if (hu >= 0) {
+          found = true;
+          pu = hu;
+        }
+      }
+    }
+    insp += ins;
+    if (found) {
+      const int32_t jb = dj[a];
+      pull_found(P, nbw, v, pu, d_new, jb >> 6, jb & 63);
+      ndeg += e - b;
+      nnew++;
+    }
+  }
+}
+
 __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
@@ -556,6 +647,10 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
   int32_t* sc = L.w_sc[wid];
   uint64_t* actw = L.pw_act[wid];
   uint64_t* nbw = L.pw_nb[wid];
+  // the set-aside list lives in this wave's push staging (unused here)
+  int32_t* dv = L.stage[wid];
+  uint16_t* dj = (uint16_t*)L.dstage[wid];
+  static_assert(sizeof(L.dstage[0]) >= PULL_DEFER * sizeof(uint16_t), "set-aside list fits");
   int32_t insp = 0, ndeg = 0, nnew = 0;
   for (int64_t t0 = 0; gw + t0 * W < P.nwords; t0 += FG_WAVE) {
     const int64_t wj = gw + (t0 + lane) * W;  // this lane's word of the batch
@@ -571,99 +666,76 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
     actw[lane] = act;
     nbw[lane] = 0;
     wave_lds_fence();
-    for (int32_t a0 = 0; a0 < tot; a0 += FG_WAVE) {
-      const int32_t a = a0 + lane;
-      int32_t v = 0, b = 0, e = 0, jw = 0, bit = 0;
-      int4 hd = make_int4(0, 0, 0, 0);
-      const bool mine = a < tot;
-      if (mine) {
-        jw = upper_idx(sc, FG_WAVE, a);
-        bit = nth_bit(actw[jw], a - sc[jw]);
-        v = (int32_t)((gw + (t0 + jw) * W) * 64 + bit);
-        // the first four entries come from the head table: one coalesced
-        // 16-byte load issued with the offsets
-        b = P.off[v];
-        e = P.off[v + 1];
-        hd = P.head[v];
+    int32_t ndef = 0;
+    // two candidates per lane and round: the offsets and head entries of
+    // both, then the eight visited words of their first four neighbours,
+    // are in flight together (lanes past the list take candidate 0 again,
+    // a valid vertex, and discard the result)
+    for (int32_t a0 = 0; a0 < tot; a0 += 2 * FG_WAVE) {
+      if (ndef > PULL_DEFER - 2 * FG_WAVE) {
+        // room for a whole round: resume what is set aside now
+        pull_resume(P, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
+        wave_lds_fence();
+        ndef = 0;
       }
-      int32_t pu = -1, ins = 0;
-      bool found = false;
-      if (mine) {
-        const int32_t u[4] = {hd.x, hd.y, hd.z, hd.w};
-        uint64_t wv[4];
+      int32_t v[2], b[2], e[2], jw[2], bit[2];
+      int4 hd[2];
+      bool mine[2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) wv[j] = Vin[u[j] >> 6];
-        int32_t h = -1;
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int32_t a = a0 + s2 * FG_WAVE + lane;
+        mine[s2] = a < tot;
+        const int32_t ac = mine[s2] ? a : 0;
+        jw[s2] = upper_idx(sc, FG_WAVE, ac);
+        bit[s2] = nth_bit(actw[jw[s2]], ac - sc[jw[s2]]);
+        v[s2] = (int32_t)((gw + (t0 + jw[s2]) * W) * 64 + bit[s2]);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        b[s2] = P.off[v[s2]];
+        e[s2] = P.off[v[s2] + 1];
+        hd[s2] = P.head[v[s2]];
+      }
+      uint64_t wv[2][4];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        // a candidate has nonzero degree: its head entries are vertices
+        wv[s2][0] = Vin[hd[s2].x >> 6];
+        wv[s2][1] = Vin[hd[s2].y >> 6];
+        wv[s2][2] = Vin[hd[s2].z >> 6];
+        wv[s2][3] = Vin[hd[s2].w >> 6];
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int32_t u[4] = {hd[s2].x, hd[s2].y, hd[s2].z, hd[s2].w};
+        const int32_t dg = e[s2] - b[s2];
+        int32_t h = -1, pu = -1;
 #pragma unroll
         for (int j = 3; j >= 0; --j) {
-          if (j < e - b && ((wv[j] >> (u[j] & 63)) & 1ull)) {
+          if (j < dg && ((wv[s2][j] >> (u[j] & 63)) & 1ull)) {
             h = j;
             pu = u[j];
           }
         }
-        found = h >= 0;
-        ins = found ? h + 1 : min(4, e - b);
-      }
-      // lists of up to 16 entries: four more at a time, lane by lane
-      bool shortl = mine && !found && e - b > 4 && e - b <= 16;
-      for (int32_t i0 = 4; i0 < 16 && __ballot(shortl); i0 += 4) {
-        if (shortl) {
-          if (b + i0 < e) {
-            const int32_t h = probe4(P, Vin, b + i0, e, pu);
-            if (h >= 0) {
-              found = true;
-              shortl = false;
-              ins += h + 1;
-            } else {
-              ins += min(4, e - b - i0);
-            }
-          } else {
-            shortl = false;
-          }
+        const bool found = mine[s2] && h >= 0;
+        const bool defer = mine[s2] && h < 0 && dg > 4;
+        insp += !mine[s2] ? 0 : (h >= 0 ? h + 1 : min(4, dg));
+        if (found) {
+          pull_found(P, nbw, v[s2], pu, d_new, jw[s2], bit[s2]);
+          ndeg += dg;
+          nnew++;
         }
-      }
-      // longer lists: the whole wave scans one at a time
-      uint64_t pend = __ballot(mine && !found && e - b > 16);
-      while (pend) {
-        const int l = __builtin_ctzll(pend);
-        pend &= pend - 1;
-        const int32_t lb = __builtin_amdgcn_readlane(b, l) + 4;
-        const int32_t le = __builtin_amdgcn_readlane(e, l);
-        int32_t cnt = 0, hu = -1;
-        for (int32_t i0 = lb; i0 < le; i0 += FG_WAVE) {
-          const int32_t i = i0 + lane;
-          int32_t u = 0;
-          bool hb = false;
-          if (i < le) {
-            u = P.col[i];
-            hb = (Vin[u >> 6] >> (u & 63)) & 1ull;
-          }
-          const uint64_t m = __ballot(hb);
-          if (m) {
-            const int f = __builtin_ctzll(m);
-            cnt += f + 1;
-            hu = __builtin_amdgcn_readlane(u, f);
-            break;
-          }
-          cnt += min(FG_WAVE, le - i0);
+        const uint64_t dm = __ballot(defer);
+        if (defer) {
+          const int32_t pos = ndef + fg_mbcnt(dm);
+          dv[pos] = v[s2];
+          dj[pos] = (uint16_t)((jw[s2] << 6) | bit[s2]);
         }
-        if (lane == l) {
-          ins += cnt;
-          if (hu >= 0) {
-            found = true;
-            pu = hu;
-          }
-        }
-      }
-      insp += ins;
-      if (found) {
-        P.depth[v] = d_new;
-        if (P.parent) P.parent[v] = pu;
-        ndeg += e - b;
-        nnew++;
-        atomicOr((unsigned long long*)&nbw[jw], 1ull << bit);
+        ndef += __popcll(dm);
       }
     }
+    wave_lds_fence();
+    if (ndef > 0) pull_resume(P, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
     wave_lds_fence();
     if (wj < P.nwords) fg_st_shared(&Vout[wj], vis | nbw[lane]);
   }
@@ -1005,17 +1077,18 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
         v = ((const int32_t*)&L.lq_h[cur][i])[j];
         // -1: the slot of the vertex's discoverer (visited), skipped
         if (v >= 0) {
+          // what the next level needs (offsets, head entry) is loaded
+          // beside the test-and-set, so its latency hides behind the
+          // atomic's instead of following it; losers drop it
+          vb = P.off[v];
+          ve = P.off[v + 1];
+          vh = P.head[v];
           const uint32_t bit = 1u << (v & 31);
           won = !(atomicOr(&vis32[v >> 5], bit) & bit);
         }
       }
-      // only the winners fetch what the next level needs: most targets of
-      // a low-degree frontier are already visited, and these random line
-      // reads, not the atomics, bound such a level
       if (won) {
-        vb = P.off[v];
-        ve = P.off[v + 1];
-        vh = blank_parent(P.head[v], u);
+        vh = blank_parent(vh, u);
         P.depth[v] = d_new;
         if (P.parent) P.parent[v] = u;
       }
