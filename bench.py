@@ -875,6 +875,8 @@ def main():
     ws = g.workspace(fg.FG_PRIM_BFS)
     gws = gg.workspace(fg.FG_PRIM_BFS)
     stats = [fg.new_stats(dev) for _ in range(NSRC + 1)]
+    srcs_dev = torch.tensor([int(s) for s in srcs], dtype=torch.int32, device=dev)
+    mstats = fg.new_stats_many(NSRC, dev)
     o_do, do_kw = autotune.workload_opts("rmat22_dobfs", g)
     o_push, push_kw = autotune.workload_opts("grid4096_push", gg)
     stream = torch.cuda.current_stream()
@@ -891,20 +893,20 @@ def main():
     edges_step = sum(m_comp) + m_grid
 
     def events():
-        return [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(NSRC + 1)]
+        return [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(2)]
 
     def step(ev):
-        for i, s in enumerate(srcs):
-            if ev:
-                ev[i][0].record(stream)
-            fg.bfs_into(g, int(s), depth, parent, o_do, ws=ws, stats=stats[i], stream=stream)
-            if ev:
-                ev[i][1].record(stream)
+        # the 64 sources one after another in one launch (fg_bfs_many), then
+        # the grid
         if ev:
-            ev[NSRC][0].record(stream)
+            ev[0][0].record(stream)
+        fg.bfs_many_into(g, srcs_dev, depth, parent, o_do, ws=ws, stats=mstats, stream=stream)
+        if ev:
+            ev[0][1].record(stream)
+            ev[1][0].record(stream)
         fg.bfs_into(gg, 0, gdepth, gparent, o_push, ws=gws, stats=stats[NSRC], stream=stream)
         if ev:
-            ev[NSRC][1].record(stream)
+            ev[1][1].record(stream)
 
     for _ in range(args.warmup):
         step(None)
@@ -919,30 +921,48 @@ def main():
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / args.steps
-    lat_do, lat_grid = [], []
-    for ev in step_events:
-        for i in range(NSRC):
-            lat_do.append(ev[i][0].elapsed_time(ev[i][1]))
-        lat_grid.append(ev[NSRC][0].elapsed_time(ev[NSRC][1]))
+    lat_many = [ev[0][0].elapsed_time(ev[0][1]) for ev in step_events]
+    lat_grid = [ev[1][0].elapsed_time(ev[1][1]) for ev in step_events]
     bytes_do, bytes_grid = [], []
     status_bad = 0
 
-    # statistics of the last step (same sources every step)
-    for i in range(NSRC):
-        st = fg.read_stats(stats[i])
+    # statistics of the last step (same sources every step): per-source
+    # spans on the device clock, from one traversal's last level to the
+    # next one's (the next source's init included)
+    recs = fg.read_stats_many(mstats, NSRC)
+    ends = []
+    for st in recs:
         status_bad += st.status != 0
         bytes_do.append(bfs_alg_bytes(st, n, (n + 63) // 64, nnz))
+        ends.append(st.t_end[min(st.iterations, 64) - 1])
+    khz = recs[0].clock_khz
+    lat_do = [(ends[j] - ends[j - 1]) / khz for j in range(1, NSRC)]
     stg = fg.read_stats(stats[NSRC])
     status_bad += stg.status != 0
     bytes_grid.append(bfs_alg_bytes(stg, ng, (ng + 63) // 64, gg.info().nonzero_degree))
 
-    do_ms = float(np.mean(lat_do))
+    # the same 64 sources with one launch each (fg_bfs), outside the step,
+    # for comparison
+    sep = []
+    for rep in range(2):
+        evs = [(_ev(), _ev()) for _ in srcs]
+        for (a, b), s in zip(evs, srcs):
+            a.record(stream)
+            fg.bfs_into(g, int(s), depth, parent, o_do, ws=ws, stats=stats[0], stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            sep = [a.elapsed_time(b) for a, b in evs]
+    fg.bfs_many_into(g, srcs_dev, depth, parent, o_do, ws=ws, stats=mstats, stream=stream)
+    torch.cuda.synchronize()
+
+    do_ms = float(np.mean(lat_many)) / NSRC
     grid_ms = float(np.mean(lat_grid))
     do_bytes = float(np.mean(bytes_do))
     grid_bytes = float(np.mean(bytes_grid))
     # dominant kernel: the one with the larger share of the step
     kernels = {
-        "bfs_persistent<DO>": dict(ms=do_ms, bytes=do_bytes, launches=NSRC),
+        "bfs_persistent<DO,many>": dict(ms=do_ms, bytes=do_bytes, launches=NSRC),
         "bfs_persistent<PUSH>": dict(ms=grid_ms, bytes=grid_bytes, launches=1),
     }
     for k in kernels.values():
@@ -996,12 +1016,22 @@ def main():
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},
         "dobfs": {
-            "gteps_harmonic": round(len(m_comp) / sum((l * 1e-3) / (mc / 1e9)
-                                                      for l, mc in zip(lat_do[-NSRC:], m_comp)), 2),
+            "launch": "the 64 sources one after another in one launch (fg_bfs_many)",
+            "ms_per_source": round(do_ms, 4),
+            "ms_per_launch": round(float(np.mean(lat_many)), 4),
+            "gteps_harmonic": round((NSRC - 1) / sum((l * 1e-3) / (mc / 1e9)
+                                                     for l, mc in zip(lat_do, m_comp[1:])), 2),
             "ms_p50": round(float(np.percentile(lat_do, 50)), 4),
             "ms_p99": round(float(np.percentile(lat_do, 99)), 4),
+            "latency_note": "per source on the device clock, from one traversal's last level "
+                            "to the next one's (sources 2-64 of the last step)",
             "queries_per_s": round(1000.0 / do_ms, 1),
             "bytes_per_traversed_edge": round(do_bytes / (sum(m_comp) / len(m_comp)), 3),
+            "separate_launches": {
+                "ms_mean": round(float(np.mean(sep)), 4),
+                "ms_p50": round(float(np.percentile(sep, 50)), 4),
+                "ms_p99": round(float(np.percentile(sep, 99)), 4),
+                "note": "one fg_bfs launch per source, events around each launch"},
         },
         "grid": {
             "ms": round(grid_ms, 3),

@@ -197,6 +197,22 @@ fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
                  fg_run_stats* stats, void* stream);
 
 /*
+ * Several BFS queries in one launch (the one-source-at-a-time workload of
+ * Sec. VII: each source's traversal is exactly fg_bfs's, run after the
+ * previous one has finished, without returning to the host between them).
+ * srcs: device int32[nsrc]; a source outside [0, n) is skipped and its
+ * record gets status FG_EINVAL.  The traversal of srcs[j] writes
+ * depth + j * out_stride and parent + j * out_stride (out_stride = 0: every
+ * traversal writes the same arrays, the last one's result remains;
+ * otherwise out_stride >= n) and stats + j (device fg_run_stats[nsrc], or
+ * NULL).  opts, ws and errors as for fg_bfs (FG_EUNSUPPORTED for the
+ * unfused mode).  nsrc = 0 does nothing.
+ */
+fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
+                      const fg_bfs_opts* opts, void* ws, size_t ws_bytes, int32_t* depth,
+                      int32_t* parent, int64_t out_stride, fg_run_stats* stats, void* stream);
+
+/*
  * fg_bfs without allocations, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same search, arguments, outputs and errors as fg_bfs

@@ -177,6 +177,7 @@ SIGNATURES = {
     "fg_stats_read": (_I32, [_P, ctypes.POINTER(RunStats), _P]),
     "fg_bfs_opts_default": (None, [ctypes.POINTER(BfsOpts)]),
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
+    "fg_bfs_many": (_I32, [_P, _P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _I64, _P, _P]),
     "fg_bfs_noalloc": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _P, _P, _P]),
     "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
     "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
@@ -358,6 +359,30 @@ def bfs_into(g, src, depth, parent=None, opts=None, ws=None, stats=None, stream=
     _check(lib().fg_bfs(g.handle, int(src), ctypes.byref(opts) if opts is not None else None,
                         _ptr(ws), ws.numel(), _ptr(depth), _ptr(parent), _ptr(stats),
                         _stream(stream)))
+
+
+def bfs_many_into(g, srcs, depth, parent=None, opts=None, ws=None, stats=None, out_stride=0,
+                  stream=None):
+    """Enqueue fg_bfs_many: the sources of `srcs` (device int32 tensor) one
+    after another in one launch; traversal j writes depth / parent +
+    j * out_stride and stats + j (stats: device tensor of len(srcs) records,
+    see new_stats_many)."""
+    ws = ws if ws is not None else g.workspace(FG_PRIM_BFS)
+    _check(lib().fg_bfs_many(g.handle, _ptr(srcs), int(srcs.numel()),
+                             ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                             ws.numel(), _ptr(depth), _ptr(parent), int(out_stride), _ptr(stats),
+                             _stream(stream)))
+
+
+def new_stats_many(k, device="cuda"):
+    """Device records for k traversals (fg_bfs_many)."""
+    return torch.zeros(k * ctypes.sizeof(RunStats), dtype=torch.uint8, device=device)
+
+
+def read_stats_many(stats_dev, k, stream=None):
+    """Host copies of k device records."""
+    sz = ctypes.sizeof(RunStats)
+    return [read_stats(stats_dev[i * sz:(i + 1) * sz], stream) for i in range(k)]
 
 
 FG_NOALLOC_SCRATCH_BYTES = 64 << 20

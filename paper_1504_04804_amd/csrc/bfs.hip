@@ -130,7 +130,31 @@ struct BfsParams {
   int32_t clock_khz;
   int32_t team;     // workgroups of the team mode (0 = off)
   int64_t team_e;   // team mode while the frontier's degree sum <= team_e
+  // several sources one after another in one launch (srcs != NULL): the
+  // traversal of srcs[j] writes depth / parent + j * out_stride and
+  // stats + j
+  const int32_t* srcs;
+  int32_t nsrc;
+  int64_t out_stride;
 };
+
+// What changes from one traversal of a launch to the next: the source and
+// the traversal's index, from which its outputs and record follow (kept as
+// two scalars, so that the kernel arguments stay in place).
+struct BfsJob {
+  int32_t job;
+  int32_t src;
+};
+
+__device__ __forceinline__ int32_t* J_depth(const BfsParams& P, const BfsJob& J) {
+  return P.depth + (int64_t)J.job * P.out_stride;
+}
+__device__ __forceinline__ int32_t* J_parent(const BfsParams& P, const BfsJob& J) {
+  return P.parent ? P.parent + (int64_t)J.job * P.out_stride : nullptr;
+}
+__device__ __forceinline__ fg_run_stats* J_stats(const BfsParams& P, const BfsJob& J) {
+  return P.stats ? P.stats + J.job : nullptr;
+}
 
 // Per-iteration state, identical in every workgroup.
 struct St {
@@ -155,6 +179,7 @@ struct St {
 struct Bases {
   ull q, desc, insp, deg;
 };
+
 
 __device__ __forceinline__ ull sel(bool odd, ull a1, ull a0) {
   // branch-free select on a wave-uniform parity
@@ -205,38 +230,26 @@ __device__ __forceinline__ void decide(St& S, const BfsParams& P) {
   }
 }
 
-__device__ __forceinline__ void trace_iter(const St& S, const BfsParams& P) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && S.k < FG_TRACE_MAX) {
-    P.stats->dir[S.k] = (int8_t)S.dir;
-    P.stats->frontier[S.k] = S.qlen;
+__device__ __forceinline__ void trace_iter(const St& S, const BfsParams& P, const BfsJob& J) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J) && S.k < FG_TRACE_MAX) {
+    J_stats(P, J)->dir[S.k] = (int8_t)S.dir;
+    J_stats(P, J)->frontier[S.k] = S.qlen;
   }
 }
 
-__device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const BfsParams& P) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats && k < FG_TRACE_MAX) {
-    P.stats->inspected[k] = insp;
-    P.stats->t_end[k] = (int64_t)wall_clock64();
+__device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const BfsParams& P,
+                                           const BfsJob& J) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J) && k < FG_TRACE_MAX) {
+    J_stats(P, J)->inspected[k] = insp;
+    J_stats(P, J)->t_end[k] = (int64_t)wall_clock64();
   }
-}
-
-// Filter step fused into the advance: test-and-set of the visited bit.
-__device__ __forceinline__ bool try_visit(int32_t v, int32_t src, int32_t d,
-                                          uint32_t* vis32, const BfsParams& P) {
-  const uint32_t bit = 1u << (v & 31);
-  uint32_t* wp = vis32 + (v >> 5);
-  if (*wp & bit) return false;  // plain pre-check; a stale 0 only costs the atomic
-  const uint32_t old = atomicOr(wp, bit);
-  if (old & bit) return false;
-  P.depth[v] = d;
-  if (P.parent) P.parent[v] = src;
-  return true;
 }
 
 // Filter step for up to four edges per lane, all in flight together: plain
 // visited pre-check of the four targets, then the test-and-sets of the
 // candidates, then depth / parent of the winners.  v[r] must be a vertex id
 // even where ok[r] is false.
-__device__ __forceinline__ void visit4(const BfsParams& P, uint32_t* vis32, int32_t d,
+__device__ __forceinline__ void visit4(const BfsParams& P, const BfsJob& J, uint32_t* vis32, int32_t d,
                                        const int32_t (&v)[4], const int32_t (&pu)[4],
                                        const bool (&ok)[4], bool (&won)[4]) {
   uint32_t w[4], old[4];
@@ -254,8 +267,8 @@ __device__ __forceinline__ void visit4(const BfsParams& P, uint32_t* vis32, int3
   for (int r = 0; r < 4; ++r) {
     won[r] = cand[r] && !((old[r] >> (v[r] & 31)) & 1u);
     if (won[r]) {
-      P.depth[v[r]] = d;
-      if (P.parent) P.parent[v[r]] = pu[r];
+      J_depth(P, J)[v[r]] = d;
+      if (J_parent(P, J)) J_parent(P, J)[v[r]] = pu[r];
     }
   }
 }
@@ -310,7 +323,8 @@ struct Lds {
 // ---- push, full grid, phase A: each wave takes 64-entry chunks of the
 // frontier (static stride).  Vertices below big_deg are expanded by a
 // wave-level scan-gather; the others become CH-edge descriptors.
-__device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t nblocks) {
+__device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, Lds& L,
+                             uint32_t nblocks) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int32_t* Qin = P.q[S.qsel];
@@ -382,7 +396,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
         pu[r] = su[j];
         v[r] = P.col[sb[j] + ((ok[r] ? t : T - 1) - sc[j])];
       }
-      visit4(P, vis32, d_new, v, pu, ok, won);
+      visit4(P, J, vis32, d_new, v, pu, ok, won);
 #pragma unroll
       for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
     }
@@ -397,7 +411,7 @@ __device__ void push_phase_a(const BfsParams& P, const St& S, Lds& L, uint32_t n
 // ---- push, full grid, phase B: waves take descriptors in turn; the CH
 // edges of a descriptor are contiguous, so each round is one coalesced read
 // of 64 column indices and no search is needed.
-__device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds& L,
+__device__ void push_phase_b(const BfsParams& P, const BfsJob& J, const St& S, int64_t ndesc, Lds& L,
                              uint32_t nblocks) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
@@ -428,7 +442,7 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
       v[r] = P.col[ok[r] ? e : e1 - 1];
       pu[r] = u;
     }
-    visit4(P, vis32, d_new, v, pu, ok, won);
+    visit4(P, J, vis32, d_new, v, pu, ok, won);
 #pragma unroll
     for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
   }
@@ -439,7 +453,7 @@ __device__ void push_phase_b(const BfsParams& P, const St& S, int64_t ndesc, Lds
 // source reaches first): every wave lists the frontier's CH-edge chunks
 // itself (one lane per vertex, a wave scan of the chunk counts) and takes
 // chunks gw, gw + W, ...; no descriptors in memory, one grid barrier.
-__device__ void push_tiny(const BfsParams& P, const St& S, Lds& L) {
+__device__ void push_tiny(const BfsParams& P, const BfsJob& J, const St& S, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int32_t* Qin = P.q[S.qsel];
@@ -486,7 +500,7 @@ __device__ void push_tiny(const BfsParams& P, const St& S, Lds& L) {
       v[r] = P.col[ok[r] ? e : e1 - 1];
       pu[r] = su[j];
     }
-    visit4(P, vis32, d_new, v, pu, ok, won);
+    visit4(P, J, vis32, d_new, v, pu, ok, won);
 #pragma unroll
     for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
   }
@@ -552,16 +566,16 @@ __device__ __forceinline__ int32_t probe4(const BfsParams& P, const uint64_t* Vi
 constexpr int PULL_DEFER = STAGE;  // set-aside vertices per wave
 
 // The found vertex v (bit `bit` of batch word jw): depth, parent, next bit.
-__device__ __forceinline__ void pull_found(const BfsParams& P, uint64_t* nbw, int32_t v,
+__device__ __forceinline__ void pull_found(const BfsParams& P, const BfsJob& J, uint64_t* nbw, int32_t v,
                                            int32_t pu, int32_t d_new, int32_t jw, int32_t bit) {
-  P.depth[v] = d_new;
-  if (P.parent) P.parent[v] = pu;
+  J_depth(P, J)[v] = d_new;
+  if (J_parent(P, J)) J_parent(P, J)[v] = pu;
   atomicOr((unsigned long long*)&nbw[jw], 1ull << bit);
 }
 
 // Resumes the set-aside vertices dv[0..cnt) (entries from the fifth on);
 // dj holds jw << 6 | bit.  Every lane of the wave must take part.
-__device__ void pull_resume(const BfsParams& P, const uint64_t* Vin, uint64_t* nbw,
+__device__ void pull_resume(const BfsParams& P, const BfsJob& J, const uint64_t* Vin, uint64_t* nbw,
                             const int32_t* dv, const uint16_t* dj, int32_t cnt, int32_t d_new,
                             int32_t& insp, int32_t& ndeg, int32_t& nnew) {
   const int lane = fg_lane();
@@ -629,14 +643,14 @@ __device__ void pull_resume(const BfsParams& P, const uint64_t* Vin, uint64_t* n
     insp += ins;
     if (found) {
       const int32_t jb = dj[a];
-      pull_found(P, nbw, v, pu, d_new, jb >> 6, jb & 63);
+      pull_found(P, J, nbw, v, pu, d_new, jb >> 6, jb & 63);
       ndeg += e - b;
       nnew++;
     }
   }
 }
 
-__device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
+__device__ void pull_phase(const BfsParams& P, const BfsJob& J, const St& S, Lds& L) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
@@ -674,7 +688,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
     for (int32_t a0 = 0; a0 < tot; a0 += 2 * FG_WAVE) {
       if (ndef > PULL_DEFER - 2 * FG_WAVE) {
         // room for a whole round: resume what is set aside now
-        pull_resume(P, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
+        pull_resume(P, J, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
         wave_lds_fence();
         ndef = 0;
       }
@@ -721,7 +735,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
         const bool defer = mine[s2] && h < 0 && dg > 4;
         insp += !mine[s2] ? 0 : (h >= 0 ? h + 1 : min(4, dg));
         if (found) {
-          pull_found(P, nbw, v[s2], pu, d_new, jw[s2], bit[s2]);
+          pull_found(P, J, nbw, v[s2], pu, d_new, jw[s2], bit[s2]);
           ndeg += dg;
           nnew++;
         }
@@ -735,7 +749,7 @@ __device__ void pull_phase(const BfsParams& P, const St& S, Lds& L) {
       }
     }
     wave_lds_fence();
-    if (ndef > 0) pull_resume(P, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
+    if (ndef > 0) pull_resume(P, J, Vin, nbw, dv, dj, ndef, d_new, insp, ndeg, nnew);
     wave_lds_fence();
     if (wj < P.nwords) fg_st_shared(&Vout[wj], vis | nbw[lane]);
   }
@@ -992,7 +1006,7 @@ __device__ __forceinline__ void wave_put(Lds& L, int nxt, bool won, int32_t pos,
 }
 
 template <int MODE>
-__device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync& ts,
+__device__ bool lds_mode(const BfsParams& P, const BfsJob& J, St& S, Lds& L, uint32_t T, TeamSync& ts,
                          TeamBases& tb) {
   const int tid = threadIdx.x;
   const int lane = fg_lane();
@@ -1089,8 +1103,8 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       }
       if (won) {
         vh = blank_parent(vh, u);
-        P.depth[v] = d_new;
-        if (P.parent) P.parent[v] = u;
+        J_depth(P, J)[v] = d_new;
+        if (J_parent(P, J)) J_parent(P, J)[v] = u;
       }
       const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
       const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
@@ -1133,8 +1147,8 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
             vb = P.off[v];
             ve = P.off[v + 1];
             vh = blank_parent(P.head[v], pu);
-            P.depth[v] = d_new;
-            if (P.parent) P.parent[v] = pu;
+            J_depth(P, J)[v] = d_new;
+            if (J_parent(P, J)) J_parent(P, J)[v] = pu;
           }
           const int32_t pos = wave_reserve(won ? 1 : 0, &L.lq_cnt[ni]);
           const int32_t wdeg = fg_wave_sum(won ? ve - vb : 0);
@@ -1167,14 +1181,14 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
       nflag = fg_uni(L.tsum[2]);
     }
     // a push level reads every CSR entry of its frontier: the degree sum
-    trace_insp(S.k, S.qdeg, P);
+    trace_insp(S.k, S.qdeg, P, J);
     S.insp_sum += S.qdeg;
     S.k++;
     S.qlen = nq;
     S.qdeg = nqdeg;
     S.p += nq;
     decide<MODE>(S, P);
-    trace_iter(S, P);
+    trace_iter(S, P, J);
     bool stay = nq > 0 && S.dir == DIR_PUSH && nqdeg <= LDS_MEAN_DEG * nq &&
                 (solo ? (nq <= P.small_q && nqdeg <= P.small_e)
                       : (nqdeg <= P.team_e && !(nq <= P.small_q && nqdeg <= P.small_e)));
@@ -1218,10 +1232,44 @@ __device__ bool lds_mode(const BfsParams& P, St& S, Lds& L, uint32_t T, TeamSync
 }
 
 // MODE is FG_MODE_DO or FG_MODE_PUSH (one kernel per mode).
-template <int MODE>
+template <int MODE, bool MULTI>
 __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   __shared__ Lds L;
   fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
+  bool ok = true;
+  // one traversal, or (MULTI, a build of its own: the loop around the
+  // traversal raises the register pressure) P.nsrc traversals in turn
+  const int32_t njobs = MULTI ? P.nsrc : 1;
+  for (int32_t job = 0; job < njobs && ok; ++job) {
+  BfsJob J{job, P.src};
+  if (MULTI) {
+    if (job > 0) {
+      // every workgroup has left the previous traversal: workgroup 0 clears
+      // the control block for the next one, all but the grid barrier (in
+      // use; its counters are monotone); the init barrier below publishes
+      // the clear
+      if (!gs.sync(&L.flag)) {
+        ok = false;
+        break;
+      }
+      if (blockIdx.x == 0) {
+        uint32_t* w = (uint32_t*)P.ctl;
+        for (int i = FG_BAR_WORDS + threadIdx.x; i < (int)(sizeof(BfsCtl) / 4); i += PB) w[i] = 0u;
+      }
+    }
+    J.src = P.srcs[job];
+    if (J.src < 0 || J.src >= P.n) {
+      // every workgroup reads the same entry and skips the traversal
+      if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J)) {
+        fg_run_stats* st = J_stats(P, J);
+        st->status = FG_EINVAL;
+        st->iterations = 0;
+        st->reached = 0;
+        st->edges_inspected = 0;
+      }
+      continue;
+    }
+  }
   St S = {};
   S.dir = DIR_PUSH;
   S.prevdir = DIR_PUSH;
@@ -1229,23 +1277,22 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   S.p = 1;
   uint32_t sm_seen = 0;
   uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
-  bool ok = true;
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
   TeamBases tb = {};
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
   {
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * PB;
-    const int32_t src = P.src;
-    if (blockIdx.x == 0 && P.stats) {
-      uint32_t* sw = (uint32_t*)P.stats;
+    const int32_t src = J.src;
+    if (blockIdx.x == 0 && J_stats(P, J)) {
+      uint32_t* sw = (uint32_t*)J_stats(P, J);
       for (int i = threadIdx.x; i < (int)(sizeof(fg_run_stats) / 4); i += PB) sw[i] = 0u;
     }
-    const bool vec = ((((uintptr_t)P.depth) | ((uintptr_t)(P.parent ? P.parent : P.depth))) & 15) == 0;
+    const bool vec = ((((uintptr_t)J_depth(P, J)) | ((uintptr_t)(J_parent(P, J) ? J_parent(P, J) : J_depth(P, J)))) & 15) == 0;
     if (vec) {
       const int64_t n4 = P.n / 4;
-      int4* d4 = (int4*)P.depth;
-      int4* p4 = (int4*)P.parent;
+      int4* d4 = (int4*)J_depth(P, J);
+      int4* p4 = (int4*)J_parent(P, J);
       for (int64_t i = tid; i < n4; i += nth) {
         const bool hit = (src >> 2) == i;
         const int r = src & 3;
@@ -1254,16 +1301,16 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         const int4 pp = make_int4(hit && r == 0 ? src : -1, hit && r == 1 ? src : -1,
                                   hit && r == 2 ? src : -1, hit && r == 3 ? src : -1);
         d4[i] = d;
-        if (P.parent) p4[i] = pp;
+        if (J_parent(P, J)) p4[i] = pp;
       }
       for (int64_t i = n4 * 4 + tid; i < P.n; i += nth) {
-        P.depth[i] = i == src ? 0 : -1;
-        if (P.parent) P.parent[i] = i == src ? src : -1;
+        J_depth(P, J)[i] = i == src ? 0 : -1;
+        if (J_parent(P, J)) J_parent(P, J)[i] = i == src ? src : -1;
       }
     } else {
       for (int64_t i = tid; i < P.n; i += nth) {
-        P.depth[i] = i == src ? 0 : -1;
-        if (P.parent) P.parent[i] = i == src ? src : -1;
+        J_depth(P, J)[i] = i == src ? 0 : -1;
+        if (J_parent(P, J)) J_parent(P, J)[i] = i == src ? src : -1;
       }
     }
     uint64_t* v0 = P.vis[0];
@@ -1272,12 +1319,12 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     if (tid == 0) P.q[0][0] = src;
     if (!gs.sync(&L.flag)) ok = false;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
-    P.stats->t_start = (int64_t)wall_clock64();
-    P.stats->clock_khz = P.clock_khz;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J)) {
+    J_stats(P, J)->t_start = (int64_t)wall_clock64();
+    J_stats(P, J)->clock_khz = P.clock_khz;
   }
-  S.qdeg = fg_uni((int32_t)(P.off[P.src + 1] - P.off[P.src]));
-  trace_iter(S, P);
+  S.qdeg = fg_uni((int32_t)(P.off[J.src + 1] - P.off[J.src]));
+  trace_iter(S, P, J);
   while (ok && S.qlen > 0) {
     // backward -> forward: list the last pull's discoveries first
     if (MODE == FG_MODE_DO && S.dir == DIR_PUSH && S.prevdir == DIR_PULL) {
@@ -1297,7 +1344,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       sm_seen++;
       const bool member = small_ep ? blockIdx.x == 0 : blockIdx.x < (uint32_t)P.team;
       if (member) {
-        if (!lds_mode<MODE>(P, S, L, small_ep ? 1u : (uint32_t)P.team, ts, tb)) ok = false;
+        if (!lds_mode<MODE>(P, J, S, L, small_ep ? 1u : (uint32_t)P.team, ts, tb)) ok = false;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
           BfsCtl* c = P.ctl;
           // every waiter of the previous hand-back has read it (on a
@@ -1384,22 +1431,22 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     CtrSlot& C = P.ctl->slot[S.k & 1];
     Bases B = get_bases(S);
     if ((MODE != FG_MODE_DO || S.dir == DIR_PUSH) && S.qlen <= FG_WAVE) {
-      push_tiny(P, S, L);
+      push_tiny(P, J, S, L);
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       S.qsel ^= 1;
     } else if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
-      push_phase_a(P, S, L, gridDim.x);
+      push_phase_a(P, J, S, L, gridDim.x);
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - B.desc);
       if (ndesc > 0) {
-        push_phase_b(P, S, ndesc, L, gridDim.x);
+        push_phase_b(P, J, S, ndesc, L, gridDim.x);
         if (!(ok = gs.sync_acquire(&L.flag))) break;
       }
       B.desc = dt;
       S.qsel ^= 1;
     } else {
-      pull_phase(P, S, L);
+      pull_phase(P, J, S, L);
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       S.cur ^= 1;
     }
@@ -1414,16 +1461,16 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     S.qdeg = S.dir == DIR_PULL ? (int64_t)(gt - B.deg) : -1;
     B.deg = gt;
     set_bases(S, B);
-    trace_insp(S.k, insp, P);
+    trace_insp(S.k, insp, P, J);
     S.insp_sum += insp;
     S.k++;
     S.qlen = nq;
     S.p += nq;
     decide<MODE>(S, P);
-    trace_iter(S, P);
+    trace_iter(S, P, J);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && P.stats) {
-    fg_run_stats* st = P.stats;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J)) {
+    fg_run_stats* st = J_stats(P, J);
     // a wait that failed in any workgroup has set the abort flag
     const uint32_t aborted = __hip_atomic_load(P.ctl->bar + FG_BAR_STRIDE, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
@@ -1434,6 +1481,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     st->direction_switches = S.switches;
     st->grid_blocks = (int32_t)gridDim.x;
   }
+  }  // jobs
   // the last workgroup out clears the control block for the next launch
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1523,7 +1571,7 @@ int persistent_blocks_per_cu(int device) {
   int& occ = g_occupancy[MODE == FG_MODE_DO ? 0 : 1][device];
   if (occ == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_persistent<MODE>, PB, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_persistent<MODE, false>, PB, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
@@ -1573,7 +1621,8 @@ static fg_status bfs_check(const char* fn, const fg_graph* g, int32_t src, const
 // (whose control block is zero).
 static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o,
                             const BfsLayout& lay, int32_t* depth, int32_t* parent,
-                            fg_run_stats* stats, hipStream_t s) {
+                            fg_run_stats* stats, hipStream_t s, const int32_t* srcs = nullptr,
+                            int32_t nsrc = 0, int64_t out_stride = 0) {
   int dev = 0;
   FG_HIP_TRY(hipGetDevice(&dev));
   fg_device_props pr = fg_props(dev);
@@ -1621,9 +1670,18 @@ static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o
   if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
   if (P.small_e > TW_CAP - 1) P.small_e = TW_CAP - 1;
 
+  P.srcs = srcs;
+  P.nsrc = nsrc;
+  P.out_stride = out_stride;
+
   void* args[] = {&P};
-  const void* fn = o.mode == FG_MODE_DO ? (const void*)bfs_persistent<FG_MODE_DO>
-                                        : (const void*)bfs_persistent<FG_MODE_PUSH>;
+  const void* fn;
+  if (srcs)
+    fn = o.mode == FG_MODE_DO ? (const void*)bfs_persistent<FG_MODE_DO, true>
+                              : (const void*)bfs_persistent<FG_MODE_PUSH, true>;
+  else
+    fn = o.mode == FG_MODE_DO ? (const void*)bfs_persistent<FG_MODE_DO, false>
+                              : (const void*)bfs_persistent<FG_MODE_PUSH, false>;
   FG_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PB), args, 0, s));
   return FG_OK;
 }
@@ -1642,6 +1700,32 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
     return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);
   return bfs_launch(g, src, o, lay, depth, parent, stats, (hipStream_t)stream);
+}
+
+extern "C" fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
+                                 const fg_bfs_opts* opts, void* ws, size_t ws_bytes,
+                                 int32_t* depth, int32_t* parent, int64_t out_stride,
+                                 fg_run_stats* stats, void* stream) {
+  if (!g) return fg_set_error(FG_EINVAL, "fg_bfs_many: graph is NULL");
+  if (nsrc < 0) return fg_set_error(FG_EINVAL, "fg_bfs_many: nsrc=%d < 0", nsrc);
+  if (nsrc == 0) return FG_OK;
+  if (!srcs) return fg_set_error(FG_EINVAL, "fg_bfs_many: srcs is NULL");
+  if (out_stride != 0 && out_stride < g->n)
+    return fg_set_error(FG_EINVAL, "fg_bfs_many: out_stride=%lld is neither 0 nor >= n=%d",
+                        (long long)out_stride, g->n);
+  fg_bfs_opts o;
+  // the sources are device data, checked on the device: src 0 stands in here
+  fg_status rc = bfs_check("fg_bfs_many", g, 0, opts, depth, &o);
+  if (rc != FG_OK) return rc;
+  if (!ws) return fg_set_error(FG_EINVAL, "fg_bfs_many: workspace is NULL");
+  if (o.mode == FG_MODE_PUSH_UNFUSED)
+    return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_many: the unfused mode runs one source per call");
+  BfsLayout lay = bfs_layout(g, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_bfs_many: workspace of %zu bytes < required %zu", ws_bytes,
+                        lay.bytes);
+  return bfs_launch(g, 0, o, lay, depth, parent, stats, (hipStream_t)stream, srcs, nsrc,
+                    out_stride);
 }
 
 // ------------------------------------------------ BFS without allocations
