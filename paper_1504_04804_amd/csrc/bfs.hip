@@ -320,6 +320,37 @@ struct Lds {
   int32_t tsum[6];
 };
 
+// The final flush of every wave's staged entries with one global atomic
+// per workgroup: the waves' counts meet in LDS, thread 0 reserves the
+// workgroup's total behind `*total`, and each wave stores its entries at
+// its prefix.  (One atomic per wave put some 4096 same-address atomics on
+// the counter at the end of every push level.)  Every thread of the
+// workgroup must take part.
+template <class T, int CAP>
+__device__ __forceinline__ void block_flush(WaveStage<T, CAP>& st, ull* total, ull base, T* out,
+                                            Lds& L) {
+  const int lane = fg_lane();
+  const int wid = threadIdx.x / FG_WAVE;
+  __syncthreads();
+  if (lane == 0) L.red32[wid] = st.cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t sum = 0;
+    for (int w = 0; w < PWAVES; ++w) {
+      const int32_t c = L.red32[w];
+      L.red32[w] = sum;
+      sum += c;
+    }
+    L.bcast[0] = sum ? (int64_t)atomicAdd(total, (ull)sum) : 0;
+  }
+  __syncthreads();
+  const ull pos = (ull)L.bcast[0] + (ull)L.red32[wid] - base;
+  // written through: read by other workgroups after the next barrier
+  for (int i = lane; i < st.cnt; i += FG_WAVE) fg_st_shared(&out[pos + i], st.buf[i]);
+  st.cnt = 0;
+  __syncthreads();
+}
+
 // ---- push, full grid, phase A: each wave takes 64-entry chunks of the
 // frontier (static stride).  Vertices below big_deg are expanded by a
 // wave-level scan-gather; the others become CH-edge descriptors.
@@ -339,7 +370,10 @@ __device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, L
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
   WaveStage<int4, DSTAGE> dst{L.dstage[wid], 0};
   int32_t* se = L.w_e[wid];
-  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  // work items are dealt wave-major over the workgroups (item i to
+  // workgroup i mod G): a level with few items spreads them over as many
+  // CUs instead of filling the first workgroups' waves
+  const int64_t gw = (int64_t)wid * nblocks + blockIdx.x;
   const int64_t W = (int64_t)nblocks * PWAVES;
   int64_t insp = 0;
   for (int64_t base = gw * FG_WAVE; base < S.qlen; base += W * FG_WAVE) {
@@ -401,8 +435,8 @@ __device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, L
       for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
     }
   }
-  st.flush(&C.q.v, B.q, Qout);
-  dst.flush(&C.desc.v, B.desc, P.desc);
+  block_flush(st, &C.q.v, B.q, Qout, L);
+  block_flush(dst, &C.desc.v, B.desc, P.desc, L);
   // per workgroup and level the sum is at most m < 2^31
   const int32_t tot = fg_block_sum<PB>((int32_t)insp, L.red32);
   if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
@@ -415,7 +449,10 @@ __device__ void push_phase_b(const BfsParams& P, const BfsJob& J, const St& S, i
                              uint32_t nblocks) {
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
-  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  // work items are dealt wave-major over the workgroups (item i to
+  // workgroup i mod G): a level with few items spreads them over as many
+  // CUs instead of filling the first workgroups' waves
+  const int64_t gw = (int64_t)wid * nblocks + blockIdx.x;
   const int64_t W = (int64_t)nblocks * PWAVES;
   int32_t* Qout = P.q[S.qsel ^ 1];
   uint32_t* vis32 = (uint32_t*)P.vis[S.cur];
@@ -446,7 +483,7 @@ __device__ void push_phase_b(const BfsParams& P, const BfsJob& J, const St& S, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
   }
-  st.flush(&C.q.v, B.q, Qout);
+  block_flush(st, &C.q.v, B.q, Qout, L);
 }
 
 // ---- push, full grid, frontier of at most 64 vertices (the hubs an R-MAT
@@ -482,7 +519,10 @@ __device__ void push_tiny(const BfsParams& P, const BfsJob& J, const St& S, Lds&
   sb[lane] = b;
   se[lane] = b + deg;
   wave_lds_fence();
-  const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
+  // work items are dealt wave-major over the workgroups (item i to
+  // workgroup i mod G): a level with few items spreads them over as many
+  // CUs instead of filling the first workgroups' waves
+  const int64_t gw = (int64_t)wid * gridDim.x + blockIdx.x;
   const int64_t W = (int64_t)gridDim.x * PWAVES;
   static_assert(CH == 4 * FG_WAVE, "one visit4 per chunk");
   for (int64_t c = gw; c < NC; c += W) {
@@ -504,7 +544,7 @@ __device__ void push_tiny(const BfsParams& P, const BfsJob& J, const St& S, Lds&
 #pragma unroll
     for (int r = 0; r < 4; ++r) st.push(won[r], v[r], &C.q.v, B.q, Qout);
   }
-  st.flush(&C.q.v, B.q, Qout);
+  block_flush(st, &C.q.v, B.q, Qout, L);
   // the frontier's degree sum, once
   const int32_t tot = fg_wave_sum(deg);
   if (blockIdx.x == 0 && threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
