@@ -963,7 +963,8 @@ def main():
     # dominant kernel: the one with the larger share of the step
     kernels = {
         "bfs_persistent<DO,many>": dict(ms=do_ms, bytes=do_bytes, launches=NSRC),
-        "bfs_persistent<PUSH>": dict(ms=grid_ms, bytes=grid_bytes, launches=1),
+        ("bfs_async" if push_kw.get("async_levels", 0) > 1 else "bfs_persistent<PUSH>"):
+            dict(ms=grid_ms, bytes=grid_bytes, launches=1),
     }
     for k in kernels.values():
         k["share_ms"] = k["ms"] * k["launches"]

@@ -175,6 +175,14 @@ typedef struct {
                              levels alone (0 = default, < 0 = off)          */
   int32_t team_edges;     /* team mode while the frontier's degree sum is at
                              most this (0 = default)                         */
+  int32_t async_levels;   /* FG_MODE_PUSH, one source per call: > 1 runs the
+                             traversal on a team of team_blocks workgroups
+                             that synchronise every async_levels levels
+                             (label-correcting keys; same depths, parents the
+                             smallest-id neighbour one level closer); the
+                             level-synchronous kernel takes over if a
+                             member's frontier outgrows its LDS room
+                             (0 = level-synchronous; at most 1024)            */
 } fg_bfs_opts;
 
 /* Fill *opts with the defaults (DO mode, do_a = 1/100, do_b = 1/10). */

@@ -3,7 +3,9 @@
 Sweeps the direction-optimizing thresholds do_a / do_b (Sec. VI-A: good
 values are consistent within a graph type, e.g. 0.01 / 0.1 for social
 graphs on the paper's GPUs), the high-degree cut of the push load balance,
-the team-mode width, and for batched BFS the push/pull switch points.  Every
+the team-mode width, for push BFS the asynchronous team (levels between
+synchronisations, team width), and for batched BFS the push/pull switch
+points.  Every
 candidate runs on the device on a sample of sources; the fastest mean time
 wins.  Results never change depths (the schedule only affects speed), which
 the test suite checks separately.
@@ -29,6 +31,8 @@ DO_A = [(1, 10), (1, 100), (1, 1000), (1, 10000), (1, 100000)]
 DO_B = [(1, 10), (1, 1), (10, 1)]
 BIG_DEG = [32, 64, 256]
 TEAM = [-1, 8, 16, 24, 32]
+ASYNC = [16, 32, 64, 128, 256]
+ASYNC_TEAM = [32, 48, 64]
 PULL_DIV = [4, 8, 16, 64, 256]
 PUSH_DIV = [64, 512, 4096]
 
@@ -58,7 +62,7 @@ def _time_bfs(g, srcs, opts, reps=2):
 
 
 def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None, do_a=None, do_b=None, big_deg=None,
-             team=None):
+             team=None, async_levels=None, async_team=None):
     """Returns (best kwargs for fg.bfs_opts, ms per traversal).  The search
     spaces default to the module lists; tests pass smaller ones."""
     best = None
@@ -83,6 +87,16 @@ def tune_bfs(g, srcs, mode=fg.FG_MODE_DO, log=None, do_a=None, do_b=None, big_de
             log(f"bfs {kw}: {ms:.4f} ms")
         if ms < best[1]:
             best = (kw, ms)
+    # stage 3 (push, one source per call): the asynchronous team
+    if mode == fg.FG_MODE_PUSH:
+        for k, tm in itertools.product(ASYNC if async_levels is None else async_levels,
+                                       ASYNC_TEAM if async_team is None else async_team):
+            kw = dict(best[0], async_levels=k, team_blocks=tm)
+            ms = _time_bfs(g, srcs, fg.bfs_opts(**kw))
+            if log:
+                log(f"bfs {kw}: {ms:.4f} ms")
+            if ms < best[1]:
+                best = (kw, ms)
     return best
 
 

@@ -104,6 +104,20 @@ struct alignas(256) BfsCtl {
   int32_t pub_switches;
   int64_t pub_qdeg;
   ull pub_b[8];
+  // asynchronous push mode (bfs_async and its finalising kernels; cleared
+  // by async_init_kernel at the start of each such traversal):
+  uint32_t as_arrive;          // team barrier arrivals
+  uint32_t pad5[63];
+  uint32_t as_state;           // 1: a member ran out of queue room, the
+  uint32_t pad6[63];           //   level-synchronous kernel behind runs instead
+  uint32_t as_exit;            // members that left
+  uint32_t pad7[63];
+  ull as_rec[TEAM_MAX];        // per member: its queue length (exchange)
+  ull as_hist_cnt[FG_TRACE_MAX];  // vertices per depth (first depths)
+  ull as_hist_deg[FG_TRACE_MAX];  // ... their degree sums
+  ull as_reached;              // vertices reached
+  ull as_insp;                 // CSR entries read by the team
+  uint32_t as_maxd;            // largest depth
 };
 
 struct BfsParams {
@@ -136,6 +150,11 @@ struct BfsParams {
   const int32_t* srcs;
   int32_t nsrc;
   int64_t out_stride;
+  // asynchronous push mode: levels per super-step (bfs_async), and the flag
+  // of the level-synchronous launch queued behind it, which runs only if
+  // the asynchronous traversal ran out of queue room
+  int32_t async_k;
+  int32_t async_fallback;
 };
 
 // What changes from one traversal of a launch to the next: the source and
@@ -1280,6 +1299,10 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   // one traversal, or (MULTI, a build of its own: the loop around the
   // traversal raises the register pressure) P.nsrc traversals in turn
   const int32_t njobs = MULTI ? P.nsrc : 1;
+  // queued behind an asynchronous traversal: run only if that one gave up
+  if (P.async_fallback &&
+      __hip_atomic_load(&P.ctl->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    return;
   for (int32_t job = 0; job < njobs && ok; ++job) {
   BfsJob J{job, P.src};
   if (MULTI) {
@@ -1536,6 +1559,373 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   }
 }
 
+// ---- asynchronous push mode (high-diameter graphs) ----------------------
+//
+// A team of T workgroups (the whole launch) runs K push levels between two
+// synchronisations instead of one: each member expands its own LDS queue
+// level after level and keeps what it discovers, without waiting for the
+// others.  Members run at different speeds, so a vertex may first be
+// reached over a longer path than its shortest; the visited test-and-set is
+// therefore replaced by a 64-bit atomicMin on a key (depth << 32 | parent)
+// per vertex, and a vertex joins the discoverer's next queue whenever its
+// depth decreases (label correcting: the queues empty only when every key
+// holds its shortest depth).  A decrease is won by exactly one relaxation,
+// so each improvement queues the vertex once; equal depths from a smaller
+// parent only lower the key.  At the end every key holds the BFS depth and
+// the smallest-id neighbour one level closer to the source (a valid
+// parent).  After K levels the members exchange queue lengths, stop when
+// all are empty, and otherwise even out their queues through global memory.
+// On grids and road-like graphs the members' regions advance as one front,
+// so corrections are rare and K - 1 of every K level barriers disappear.
+// If a member's queue overflows its LDS room, the traversal stops and the
+// level-synchronous kernel launched behind it runs instead.
+
+constexpr int AQ = QCAP;  // LDS queue entries per member
+
+struct AsLds {
+  int32_t qv[2][AQ];
+  int32_t qb[2][AQ];
+  int32_t qe[2][AQ];
+  int4 qh[2][AQ];
+  int32_t cnt[2];
+  int32_t ovf;
+  int32_t big;
+  int32_t flag;
+  int32_t tot;
+  int32_t pre;
+  int32_t stop;
+  int32_t b_sc[PB];
+  int32_t b_u[PB];
+  int32_t b_b[PB];
+  int32_t red32[PWAVES + 1];
+  int64_t red64[PWAVES + 1];
+};
+
+// Relaxation of v from u at depth d1 (= depth(u) + 1): true if it lowered
+// v's depth (then the caller queues v).
+__device__ __forceinline__ bool as_relax(ull* key, int32_t v, int32_t u, int32_t d1) {
+  const ull kn = ((ull)(uint32_t)d1 << 32) | (uint32_t)u;
+  const ull old = atomicMin(&key[v], kn);
+  return (uint32_t)(old >> 32) > (uint32_t)d1;
+}
+
+// Queues the winners of a relaxation round in the next LDS queue (room
+// permitting; an overflow stops the traversal).  Every lane must take part.
+__device__ __forceinline__ void as_put(AsLds& L, int nxt, bool won, int32_t v, int32_t vb,
+                                      int32_t ve, int4 vh) {
+  const int32_t pos = wave_reserve(won ? 1 : 0, &L.cnt[nxt]);
+  if (won) {
+    if (pos < AQ) {
+      L.qv[nxt][pos] = v;
+      L.qb[nxt][pos] = vb;
+      L.qe[nxt][pos] = ve;
+      L.qh[nxt][pos] = vh;
+    } else {
+      L.ovf = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
+  __shared__ AsLds L;
+  const int tid = threadIdx.x;
+  const int lane = fg_lane();
+  const uint32_t T = gridDim.x;
+  BfsCtl* C = P.ctl;
+  uint32_t* abort_flag = C->bar + FG_BAR_STRIDE;
+  TeamSync ts{&C->as_arrive, abort_flag, T, 0u};
+  ull* key = (ull*)P.desc;  // the key array lives in the descriptor region
+  int32_t* G = P.q[0];      // exchange buffer
+  const int32_t K = P.async_k;
+  int64_t insp = 0;
+  if (tid == 0) {
+    L.cnt[0] = blockIdx.x == 0 ? 1 : 0;
+    L.cnt[1] = 0;
+    L.ovf = 0;
+    L.stop = 0;
+    if (blockIdx.x == 0) {
+      L.qv[0][0] = P.src;
+      L.qb[0][0] = P.off[P.src];
+      L.qe[0][0] = P.off[P.src + 1];
+      L.qh[0][0] = P.head[P.src];
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  int32_t base = 0;  // depth of the entries of queue `cur` at a super-step start
+  bool ok = true;
+  // every super-step advances the queued depths by K, and no shortest
+  // depth exceeds n - 1: past this many the team gives up (the
+  // level-synchronous kernel behind it then answers)
+  const uint32_t max_steps = (uint32_t)(P.n / K) + 2;
+  for (uint32_t step = 0; ok; ++step) {
+    if (step > max_steps) {
+      if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(&C->as_state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    for (int32_t t = 0; t < K; ++t) {
+      const int nxt = cur ^ 1;
+      const int32_t cnt = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
+      const int32_t d1 = base + t + 1;
+      __syncthreads();
+      if (tid == 0) {
+        L.cnt[nxt] = 0;
+        L.big = 0;
+      }
+      __syncthreads();
+      // vertices of degree <= TPV: TPV lanes each, neighbours from the head
+      // entry in LDS (the discoverer's slot blanked)
+      bool big = false;
+      for (int32_t c0 = 0; c0 < cnt; c0 += PB / TPV) {
+        const int32_t i = c0 + tid / TPV;
+        const int32_t j = tid % TPV;
+        int32_t u = 0, b = 0, d = 0;
+        if (i < cnt) {
+          u = L.qv[cur][i];
+          b = L.qb[cur][i];
+          d = L.qe[cur][i] - b;
+        }
+        big |= d > TPV;
+        bool won = false;
+        int32_t v = 0, vb = 0, ve = 0;
+        int4 vh = make_int4(0, 0, 0, 0);
+        if (d <= TPV && j < d) {
+          v = ((const int32_t*)&L.qh[cur][i])[j];
+          if (v >= 0) {
+            vb = P.off[v];
+            ve = P.off[v + 1];
+            vh = P.head[v];
+            won = as_relax(key, v, u, d1);
+            insp++;
+          }
+        }
+        if (won) vh = blank_parent(vh, u);
+        as_put(L, nxt, won, v, vb, ve, vh);
+      }
+      if (big) L.big = 1;
+      __syncthreads();
+      if (L.big) {
+        // vertices of degree > TPV: block scan-gather over their rows
+        for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
+          const int32_t i = c0 + tid;
+          int32_t u = 0, b = 0, d = 0;
+          if (i < cnt) {
+            u = L.qv[cur][i];
+            b = L.qb[cur][i];
+            d = L.qe[cur][i] - b;
+          }
+          if (d <= TPV) d = 0;
+          int32_t Tn = 0;
+          const int32_t ex = fg_block_excl_scan<PB>(d, L.red32, &Tn);
+          L.b_sc[tid] = ex;
+          L.b_u[tid] = u;
+          L.b_b[tid] = b;
+          __syncthreads();
+          const int32_t nc = cnt - c0 < PB ? cnt - c0 : PB;
+          for (int32_t t0 = 0; t0 < Tn; t0 += PB) {
+            const int32_t tt = t0 + tid;
+            bool won = false;
+            int32_t v = 0, vb = 0, ve = 0, pu = 0;
+            int4 vh = make_int4(0, 0, 0, 0);
+            if (tt < Tn) {
+              const int32_t jj = upper_idx(L.b_sc, nc, tt);
+              pu = L.b_u[jj];
+              v = P.col[L.b_b[jj] + (tt - L.b_sc[jj])];
+              vb = P.off[v];
+              ve = P.off[v + 1];
+              vh = P.head[v];
+              won = as_relax(key, v, pu, d1);
+              insp++;
+            }
+            if (won) vh = blank_parent(vh, pu);
+            as_put(L, nxt, won, v, vb, ve, vh);
+          }
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+      cur = nxt;
+      if (L.ovf) break;  // LDS flag: every thread sees the same value here
+    }
+    base += K;
+    // exchange: queue lengths (and an overflow) to the team
+    if (tid == 0) {
+      const int32_t c = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
+      fg_st_shared(&C->as_rec[blockIdx.x], ((ull)(L.ovf ? 1 : 0) << 63) | (ull)(uint32_t)c);
+    }
+    if (!ts.sync_acquire(&L.flag)) {
+      ok = false;
+      break;
+    }
+    if (tid < FG_WAVE) {
+      ull r = 0;
+      if ((uint32_t)tid < T)
+        r = __hip_atomic_load(&C->as_rec[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t c = (int32_t)(uint32_t)r;
+      const int32_t o = (int32_t)(r >> 63);
+      const int32_t incl = fg_wave_incl_scan(c);
+      const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+      const int32_t pre = __builtin_amdgcn_readlane(incl - c, blockIdx.x);
+      const int32_t anyo = fg_wave_sum(o);
+      if (tid == 0) {
+        L.tot = tot;
+        L.pre = pre;
+        // stop: done (nothing queued), or out of room (an LDS queue, or the
+        // exchange buffer)
+        L.stop = anyo ? 2 : (tot == 0 ? 1 : ((int64_t)tot > (int64_t)P.n ? 2 : 0));
+      }
+    }
+    __syncthreads();
+    if (L.stop) {
+      if (L.stop == 2 && blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(&C->as_state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    // even shares: every member writes its queue to the exchange buffer at
+    // its prefix, then loads an equal slice (offsets and head entries
+    // reloaded)
+    const int32_t mine = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
+    for (int32_t i = tid; i < mine; i += PB) fg_st_shared(&G[L.pre + i], L.qv[cur][i]);
+    if (!ts.sync_acquire(&L.flag)) {
+      ok = false;
+      break;
+    }
+    const int64_t tot = L.tot;
+    const int32_t lo = (int32_t)(tot * blockIdx.x / T), hi = (int32_t)(tot * (blockIdx.x + 1) / T);
+    for (int32_t i = tid; i < hi - lo; i += PB) {
+      const int32_t v = G[lo + i];
+      L.qv[cur][i] = v;
+      L.qb[cur][i] = P.off[v];
+      L.qe[cur][i] = P.off[v + 1];
+      L.qh[cur][i] = P.head[v];
+    }
+    __syncthreads();
+    if (tid == 0) L.cnt[cur] = hi - lo;
+    __syncthreads();
+  }
+  // totals; the last member out clears the team's barrier and records
+  insp = fg_block_sum<PB>(insp, L.red64);
+  if (tid == 0) {
+    if (insp) atomicAdd(&C->as_insp, (ull)insp);
+    if (!ok) __hip_atomic_store(&C->as_state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t done = __hip_atomic_fetch_add(&C->as_exit, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done == T - 1) {
+      C->as_arrive = 0;
+      C->as_exit = 0;
+      for (uint32_t i = 0; i < T; ++i) C->as_rec[i] = 0;
+    }
+  }
+}
+
+// Start of an asynchronous traversal: every key "unreached" but the
+// source's (depth 0, parent itself); the asynchronous fields of the control
+// block cleared; the record cleared.
+__global__ void async_init_kernel(BfsParams P) {
+  ull* key = (ull*)P.desc;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = tid; v < P.n; v += nth)
+    key[v] = v == P.src ? (ull)(uint32_t)P.src : ~0ull;
+  if (blockIdx.x == 0) {
+    BfsCtl* C = P.ctl;
+    for (int i = threadIdx.x; i < FG_TRACE_MAX; i += blockDim.x) {
+      C->as_hist_cnt[i] = 0;
+      C->as_hist_deg[i] = 0;
+    }
+    for (int i = threadIdx.x; i < TEAM_MAX; i += blockDim.x) C->as_rec[i] = 0;
+    if (threadIdx.x == 0) {
+      C->as_arrive = 0;
+      C->as_state = 0;
+      C->as_exit = 0;
+      C->as_reached = 0;
+      C->as_insp = 0;
+      C->as_maxd = 0;
+    }
+    if (P.stats) {
+      uint32_t* sw = (uint32_t*)P.stats;
+      for (int i = threadIdx.x; i < (int)(sizeof(fg_run_stats) / 4); i += blockDim.x) sw[i] = 0u;
+    }
+  }
+  if (tid == 0 && P.stats) {
+    P.stats->t_start = (int64_t)wall_clock64();
+    P.stats->clock_khz = P.clock_khz;
+  }
+}
+
+// Outputs from the keys: depth = key >> 32, parent = low word (-1 / -1 if
+// unreached), plus the level sizes and their degree sums for the record.
+__global__ __launch_bounds__(256) void async_finalize_kernel(BfsParams P) {
+  __shared__ ull s_cnt[FG_TRACE_MAX], s_deg[FG_TRACE_MAX];
+  BfsCtl* C = P.ctl;
+  if (__hip_atomic_load(&C->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  for (int i = threadIdx.x; i < FG_TRACE_MAX; i += blockDim.x) {
+    s_cnt[i] = 0;
+    s_deg[i] = 0;
+  }
+  __syncthreads();
+  const ull* key = (const ull*)P.desc;
+  ull reached = 0;
+  uint32_t maxd = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < P.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const ull k = key[v];
+    if (k == ~0ull) {
+      P.depth[v] = -1;
+      if (P.parent) P.parent[v] = -1;
+    } else {
+      const uint32_t d = (uint32_t)(k >> 32);
+      P.depth[v] = (int32_t)d;
+      if (P.parent) P.parent[v] = (int32_t)(uint32_t)k;
+      reached++;
+      maxd = d > maxd ? d : maxd;
+      if (d < FG_TRACE_MAX) {
+        atomicAdd(&s_cnt[d], 1ull);
+        atomicAdd(&s_deg[d], (ull)(P.off[v + 1] - P.off[v]));
+      }
+    }
+  }
+  reached = fg_wave_sum(reached);
+  for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_xor(maxd, d, FG_WAVE);
+    maxd = o > maxd ? o : maxd;
+  }
+  if (fg_lane() == 0) {
+    if (reached) atomicAdd(&C->as_reached, reached);
+    atomicMax(&C->as_maxd, maxd);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < FG_TRACE_MAX; i += blockDim.x) {
+    if (s_cnt[i]) atomicAdd(&C->as_hist_cnt[i], s_cnt[i]);
+    if (s_deg[i]) atomicAdd(&C->as_hist_deg[i], s_deg[i]);
+  }
+}
+
+// The record of an asynchronous traversal: levels = largest depth + 1, the
+// per-level trace from the level sizes (the entries a level-synchronous
+// push reads: the frontier's degree sum), the entries the team read.
+__global__ void async_stats_kernel(BfsParams P, int32_t team) {
+  BfsCtl* C = P.ctl;
+  if (threadIdx.x != 0 || blockIdx.x != 0 || !P.stats) return;
+  if (__hip_atomic_load(&C->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  fg_run_stats* st = P.stats;
+  const int32_t L = (int32_t)C->as_maxd + 1;
+  const int64_t now = (int64_t)wall_clock64();
+  for (int32_t k = 0; k < L && k < FG_TRACE_MAX; ++k) {
+    st->dir[k] = 0;
+    st->frontier[k] = (int64_t)C->as_hist_cnt[k];
+    st->inspected[k] = (int64_t)C->as_hist_deg[k];
+    st->t_end[k] = now;
+  }
+  st->status = FG_OK;
+  st->iterations = L;
+  st->reached = (int64_t)C->as_reached;
+  st->edges_inspected = (int64_t)C->as_insp;
+  st->direction_switches = 0;
+  st->grid_blocks = team;
+}
+
 // a1: depth = -1 / parent = -1 except at the source, visited = {src},
 // queue 0 = {src}, control block and stats cleared.
 __global__ void bfs_init_kernel(int32_t n, int32_t nwords, int32_t src, int32_t* depth,
@@ -1713,6 +2103,25 @@ static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o
   P.srcs = srcs;
   P.nsrc = nsrc;
   P.out_stride = out_stride;
+
+  if (o.mode == FG_MODE_PUSH && o.async_levels > 1 && !srcs) {
+    // asynchronous push: keys, the team's launch, outputs and record, and
+    // the level-synchronous launch that runs only if the team gave up
+    P.async_k = o.async_levels > 1024 ? 1024 : o.async_levels;
+    int T = o.team_blocks > 0 ? o.team_blocks : DEF_TEAM;
+    if (T > pr.cus) T = pr.cus;
+    if (T > TEAM_MAX) T = TEAM_MAX;
+    if (T < 1) T = 1;
+    int fb = (int)((g->n + 4095) / 4096);
+    if (fb > 2048) fb = 2048;
+    if (fb < 1) fb = 1;
+    async_init_kernel<<<fb, 256, 0, s>>>(P);
+    void* aargs[] = {&P};
+    FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_async, dim3(T), dim3(PB), aargs, 0, s));
+    async_finalize_kernel<<<fb, 256, 0, s>>>(P);
+    async_stats_kernel<<<1, 64, 0, s>>>(P, T);
+    P.async_fallback = 1;
+  }
 
   void* args[] = {&P};
   const void* fn;

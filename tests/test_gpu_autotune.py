@@ -47,6 +47,23 @@ def test_tune_bfs_small(env, orc, tmp_path):
         assert orc.check_bfs(off, col, s, to_np(d), to_np(p)) is None
 
 
+def test_tune_push_async_small(env, orc):
+    """Push tuning includes the asynchronous team; the winner's options give
+    the oracle's depths (Manhattan distances on a grid)."""
+    fg, at = env
+    off, col = synth.grid_csr(300, 200)
+    g = fg.Graph(off, col)
+    announce("autotune push grid300x200")
+    kw, ms = at.tune_bfs(g, [0], fg.FG_MODE_PUSH, print, big_deg=[32], team=[16],
+                         async_levels=[8, 32], async_team=[8, 16])
+    assert kw["mode"] == fg.FG_MODE_PUSH and ms > 0
+    d, p, st = fg.bfs(g, 0, opts=fg.bfs_opts(**kw))
+    assert st.status == 0
+    assert to_np(d).tolist() == [r + c for r in range(300) for c in range(200)]
+    assert orc.check_bfs(off, col, 0, to_np(d), to_np(p)) is None
+    g.close()
+
+
 def test_tune_msbfs_small(env, orc):
     fg, at = env
     off, col = synth.rmat_csr(13)
