@@ -58,7 +58,8 @@ def parse():
                     help="skip the per-config side measurements (SSSP, package, batched, serving)")
     ap.add_argument("--only", default=None,
                     help="comma-separated side measurements to run (sssp, package, batched, "
-                         "batched_sssp, dupall, cc, pagerank, serving); the others are skipped")
+                         "batched_sssp, overhead, dupall, cc, pagerank, serving); the others "
+                         "are skipped")
     ap.add_argument("--no-widened", action="store_true",
                     help="skip the duplicate-all DOBFS, CC and PageRank measurements")
     ap.add_argument("--no-serving", action="store_true",
@@ -74,7 +75,10 @@ def parse():
 def bfs_alg_bytes(st, n, nwords, nnz, parents=True):
     """Compulsory HBM bytes of one traversal from its device statistics.
 
-    init      : depth (+ parent) written once, visited bitmap cleared
+    outputs   : depth (+ parent) written once per vertex: by the level that
+                reaches it (counted below) or, -1, after the last level
+                (unreached vertices, with one read of the visited bitmap)
+    init      : visited bitmap cleared
     push k    : queue + 2 offsets per frontier vertex (12|Q|), one column
                 index per inspected edge (4 insp), the target's visited word
                 (min(n/8, 4 insp): the bitmap is read at most once per
@@ -86,7 +90,7 @@ def bfs_alg_bytes(st, n, nwords, nnz, parents=True):
     pull->push: two bitmaps read, the new queue written
     """
     pb = 8 if parents else 4
-    total = pb * n + 8 * nwords
+    total = 8 * nwords + 8 * nwords + pb * max(n - st.reached, 0)
     k_tr = min(st.iterations, 64)
     fr = list(st.frontier[:k_tr])
     ins = list(st.inspected[:k_tr])
@@ -774,6 +778,75 @@ def max_sustained_at(sweep, path, target):
     return max(ok) if ok else (None, None)
 
 
+def level_table(recs):
+    """Per-level device time of the multi-source DOBFS launch, by level
+    index over the sources that reach it (from each record's clock stamps):
+    mean / max microseconds, share of pull levels, mean frontier and entries
+    read; `init_us` is the gap from one traversal's last level to the next
+    one's first stamp (outputs and bitmap cleared, source seeded)."""
+    khz = recs[0].clock_khz
+    rows, init = {}, []
+    for j, st in enumerate(recs):
+        us = st.iteration_us()
+        dirs, fr, ins = st.trace()
+        if j:
+            prev = recs[j - 1]
+            init.append((st.t_start - prev.t_end[min(prev.iterations, 64) - 1]) * 1000.0 / khz)
+        for k, row in enumerate(zip(us, dirs, fr, ins)):
+            rows.setdefault(k, []).append(row)
+    table = []
+    for k in sorted(rows):
+        a = np.array(rows[k], dtype=np.float64)
+        table.append({"level": k, "sources": len(a), "us_mean": round(float(a[:, 0].mean()), 2),
+                      "us_max": round(float(a[:, 0].max()), 2),
+                      "pull_share": round(float(a[:, 1].mean()), 3),
+                      "frontier_mean": round(float(a[:, 2].mean()), 1),
+                      "inspected_mean": round(float(a[:, 3].mean()), 1)})
+    per_src = sum(r["us_mean"] * r["sources"] for r in table) / len(recs)
+    return {"init_us_mean": round(float(np.mean(init)), 2) if init else None,
+            "levels_us_per_source": round(per_src, 2), "table": table}
+
+
+def side_overhead(fg, torch, stream):
+    """Per-iteration overhead (the paper's l, Sec. V): BFS on a path, one
+    vertex and one edge per level, so a level's time is all overhead.  The
+    persistent kernel (one workgroup runs such levels from LDS), the
+    asynchronous team (one member) and the unfused host loop of advance +
+    filter launches (the paper's baseline structure)."""
+    import synth
+    res = {}
+    for what, n, opts in (("persistent push", 1 << 16, fg.bfs_opts(mode=fg.FG_MODE_PUSH)),
+                          ("asynchronous push, 1 member, K = 128", 1 << 16,
+                           fg.bfs_opts(mode=fg.FG_MODE_PUSH, async_levels=128, team_blocks=1)),
+                          ("unfused host loop", 1 << 12,
+                           fg.bfs_opts(mode=fg.FG_MODE_PUSH_UNFUSED))):
+        off, col = synth.grid_csr(1, n)
+        g = fg.Graph(off, col, symmetric=True, validate=False)
+        depth = torch.empty(n, dtype=torch.int32, device="cuda")
+        parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        ws = g.workspace(fg.FG_PRIM_BFS_UNFUSED if opts.mode == fg.FG_MODE_PUSH_UNFUSED
+                         else fg.FG_PRIM_BFS)
+        st = fg.new_stats("cuda")
+        ts = []
+        for rep in range(3):
+            a, b = _ev(), _ev()
+            a.record(stream)
+            fg.bfs_into(g, 0, depth, parent, opts, ws=ws, stats=st, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        r = fg.read_stats(st)
+        ok = r.status == 0 and r.iterations == n and int(depth[-1].item()) == n - 1
+        ms = float(min(ts))
+        res[what] = {"vertices": n, "levels": int(r.iterations), "ms": round(ms, 3),
+                     "us_per_level": round(ms * 1e3 / max(r.iterations, 1), 3), "ok": bool(ok)}
+        del ws, depth, parent
+        g.close()
+    res["note"] = ("path graph 0-1-...-(n-1) from vertex 0: every level has one vertex and "
+                   "one new edge; fastest of 3 runs, launch included")
+    return res
+
+
 def side_serving(fg, torch, cpu_graphs):
     """C5: Poisson streams of BFS / SSSP queries over 8 resident graphs of
     mixed size at a sweep of offered loads, served with HBM-budget admission
@@ -1030,6 +1103,7 @@ def main():
                             "to the next one's (sources 2-64 of the last step)",
             "queries_per_s": round(1000.0 / do_ms, 1),
             "bytes_per_traversed_edge": round(do_bytes / (sum(m_comp) / len(m_comp)), 3),
+            "levels": level_table(recs),
             "separate_launches": {
                 "ms_mean": round(float(np.mean(sep)), 4),
                 "ms_p50": round(float(np.percentile(sep, 50)), 4),
@@ -1130,6 +1204,9 @@ def main():
         if want("batched_sssp"):
             out["batched_sssp"] = side_batched_sssp(fg, torch, stream, (off, col), not args.no_cpu)
             print(f"[bench] batched sssp done", file=sys.stderr, flush=True)
+        if want("overhead"):
+            out["overhead_l"] = side_overhead(fg, torch, stream)
+            print(f"[bench] overhead done", file=sys.stderr, flush=True)
         if not args.no_widened:
             if want("dupall"):
                 out["dupall"] = side_dupall(fg, torch, stream, off, col, srcs, not args.no_cpu)

@@ -27,7 +27,8 @@ import torch
 
 import paper_1504_04804_amd as fg
 
-DO_A = [(1, 10), (1, 100), (1, 1000), (1, 10000), (1, 100000)]
+DO_A = [(1, 10), (1, 100), (1, 1000), (1, 10000), (1, 100000), (1, 10**6), (1, 10**7),
+        (1, 10**8), (1, 10**9)]
 DO_B = [(1, 10), (1, 1), (10, 1)]
 BIG_DEG = [32, 64, 256]
 TEAM = [-1, 8, 16, 24, 32]
@@ -45,17 +46,29 @@ def signature(g):
 
 
 def _time_bfs(g, srcs, opts, reps=2):
-    depth = torch.empty(g.n, dtype=torch.int32, device=g.off.device)
+    """Mean time per source, with parents, run as the benchmark runs them:
+    the sources one after another in one launch (fg_bfs_many, shared
+    outputs), or one launch each in the asynchronous push mode."""
+    dev = g.off.device
+    depth = torch.empty(g.n, dtype=torch.int32, device=dev)
+    parent = torch.empty(g.n, dtype=torch.int32, device=dev)
     ws = g.workspace(fg.FG_PRIM_BFS)
-    for s in srcs[:1]:
-        fg.bfs_into(g, int(s), depth, None, opts, ws=ws)
+    if opts.async_levels <= 1:
+        sd = torch.tensor([int(s) for s in srcs], dtype=torch.int32, device=dev)
+
+        def run():
+            fg.bfs_many_into(g, sd, depth, parent, opts, ws=ws)
+    else:
+        def run():
+            for s in srcs:
+                fg.bfs_into(g, int(s), depth, parent, opts, ws=ws)
+    run()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
-        for s in srcs:
-            fg.bfs_into(g, int(s), depth, None, opts, ws=ws)
+        run()
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / (reps * len(srcs))

@@ -133,6 +133,7 @@ struct BfsParams {
   int32_t* depth;
   int32_t* parent;
   uint64_t* vis[2];
+  uint64_t* reached;  // see BfsLayout::reached
   int32_t* q[2];
   int4* desc;
   BfsCtl* ctl;
@@ -271,20 +272,55 @@ __device__ __forceinline__ void trace_insp(int32_t k, int64_t insp, const BfsPar
 __device__ __forceinline__ void visit4(const BfsParams& P, const BfsJob& J, uint32_t* vis32, int32_t d,
                                        const int32_t (&v)[4], const int32_t (&pu)[4],
                                        const bool (&ok)[4], bool (&won)[4]) {
-  uint32_t w[4], old[4];
-  bool cand[4];
+  const int lane = fg_lane();
+  uint32_t w[4], old[4], excl[4];
+  uint64_t tails[4];
+  bool cand[4], lead[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) w[r] = vis32[v[r] >> 5];
+  // Lanes of one round that test bits of the same visited word in a run of
+  // adjacent lanes (a sorted adjacency list's consecutive entries) combine
+  // them: the run's last lane sets all of the run's bits with one atomic,
+  // and each lane reads its own bit's previous value from that atomic's
+  // result.  A hub's list of consecutive small ids would otherwise send up
+  // to 64 atomics to one word from one instruction.
 #pragma unroll
-  for (int r = 0; r < 4; ++r) cand[r] = ok[r] && !((w[r] >> (v[r] & 31)) & 1u);
-  // old is only set and read where cand[r]: no merge with a default value,
+  for (int r = 0; r < 4; ++r) {
+    cand[r] = ok[r] && !((w[r] >> (v[r] & 31)) & 1u);
+    const int32_t key = cand[r] ? (v[r] >> 5) : ~lane;  // non-candidates: runs of their own
+    const uint32_t bm = cand[r] ? 1u << (v[r] & 31) : 0u;
+    const int32_t kp = __shfl_up(key, 1, FG_WAVE);
+    const int32_t kn = __shfl_down(key, 1, FG_WAVE);
+    const bool head = lane == 0 || kp != key;
+    const bool tl = lane == FG_WAVE - 1 || kn != key;
+    const uint64_t H = __ballot(head);
+    tails[r] = __ballot(tl);
+    const uint64_t upto = lane == FG_WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    const int32_t start = 63 - __builtin_clzll(H & upto);
+    // segmented inclusive OR over the lanes of the run up to this one
+    uint32_t x = bm;
+#pragma unroll
+    for (int dd = 1; dd < FG_WAVE; dd <<= 1) {
+      const uint32_t y = __shfl_up(x, dd, FG_WAVE);
+      if (lane - dd >= start) x |= y;
+    }
+    // the bits of the run's earlier lanes (a target listed twice in a run
+    // is won by its first lane only)
+    const uint32_t xp = __shfl_up(x, 1, FG_WAVE);
+    excl[r] = lane > start ? xp : 0u;
+    lead[r] = tl && cand[r];
+  }
+  // old is only set and read where lead[r]: no merge with a default value,
   // so the compiler need not wait inside each branch
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    if (cand[r]) old[r] = atomicOr(vis32 + (v[r] >> 5), 1u << (v[r] & 31));
+    if (lead[r]) old[r] = atomicOr(vis32 + (v[r] >> 5), excl[r] | (1u << (v[r] & 31)));
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    won[r] = cand[r] && !((old[r] >> (v[r] & 31)) & 1u);
+    const int tail = lane + __builtin_ctzll(tails[r] >> lane);
+    const uint32_t o = __shfl(lead[r] ? old[r] : 0u, tail, FG_WAVE);
+    // bits set before the run's atomic, or claimed by an earlier lane of it
+    won[r] = cand[r] && !(((o | excl[r]) >> (v[r] & 31)) & 1u);
     if (won[r]) {
       J_depth(P, J)[v[r]] = d;
       if (J_parent(P, J)) J_parent(P, J)[v[r]] = pu[r];
@@ -293,7 +329,7 @@ __device__ __forceinline__ void visit4(const BfsParams& P, const BfsJob& J, uint
 }
 
 constexpr int STAGE = 512;   // per-wave LDS staging of discovered vertices
-constexpr int DSTAGE = 64;   // per-wave LDS staging of descriptors
+constexpr int DSTAGE = 64;   // per-wave LDS room of 16-byte entries (pull: set-aside list)
 
 struct Lds {
   // LDS-queue mode: frontier share of this workgroup as (vertex, first edge,
@@ -387,7 +423,6 @@ __device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, L
   CtrSlot& C = P.ctl->slot[S.k & 1];
   const Bases B = get_bases(S);
   WaveStage<int32_t, STAGE> st{L.stage[wid], 0};
-  WaveStage<int4, DSTAGE> dst{L.dstage[wid], 0};
   int32_t* se = L.w_e[wid];
   // work items are dealt wave-major over the workgroups (item i to
   // workgroup i mod G): a level with few items spreads them over as many
@@ -416,15 +451,20 @@ __device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, L
       sb[lane] = b;
       se[lane] = b + deg;
       wave_lds_fence();
+      // one reservation for all of the wave's descriptors, then 64 written
+      // per step (a wave holding an R-MAT source's hubs writes thousands)
+      ull pos = 0;
+      if (lane == 0) pos = atomicAdd(&C.desc.v, (ull)ND);
+      pos = __shfl(pos, 0, FG_WAVE) - B.desc;
       for (int32_t t0 = 0; t0 < ND; t0 += FG_WAVE) {
         const int32_t t = t0 + lane;
-        int4 dsc = make_int4(0, 0, 0, 0);
         if (t < ND) {
           const int32_t j = upper_idx(sc, FG_WAVE, t);
           const int32_t first = sb[j] + (t - sc[j]) * CH;
-          dsc = make_int4(su[j], first, first + CH < se[j] ? first + CH : se[j], 0);
+          // written through: read by other workgroups after the barrier
+          fg_st_shared(&P.desc[pos + t],
+                       make_int4(su[j], first, first + CH < se[j] ? first + CH : se[j], 0));
         }
-        dst.push(t < ND, dsc, &C.desc.v, B.desc, P.desc);
       }
     }
     // scan-gather of the low-degree lanes
@@ -455,7 +495,6 @@ __device__ void push_phase_a(const BfsParams& P, const BfsJob& J, const St& S, L
     }
   }
   block_flush(st, &C.q.v, B.q, Qout, L);
-  block_flush(dst, &C.desc.v, B.desc, P.desc, L);
   // per workgroup and level the sum is at most m < 2^31
   const int32_t tot = fg_block_sum<PB>((int32_t)insp, L.red32);
   if (threadIdx.x == 0 && tot) atomicAdd(&C.insp.v, (ull)tot);
@@ -1303,21 +1342,29 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   if (P.async_fallback &&
       __hip_atomic_load(&P.ctl->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
     return;
+  // shared outputs (fg_bfs_many, out_stride 0): once one traversal of this
+  // launch has completed, the outputs hold -1 exactly outside its visited
+  // set (kept in P.reached), so the next traversal writes only what it
+  // reaches and afterwards resets the vertices the previous one reached and
+  // it did not, instead of filling 8n bytes first
+  bool have_prev = false;
   for (int32_t job = 0; job < njobs && ok; ++job) {
   BfsJob J{job, P.src};
   if (MULTI) {
     if (job > 0) {
-      // every workgroup has left the previous traversal: workgroup 0 clears
-      // the control block for the next one, all but the grid barrier (in
-      // use; its counters are monotone); the init barrier below publishes
-      // the clear
+      // every workgroup has left the previous traversal: the workgroups
+      // clear the control block for the next one, a share each, all but the
+      // grid barrier (in use; its counters are monotone); the init barrier
+      // below publishes the clear
       if (!gs.sync(&L.flag)) {
         ok = false;
         break;
       }
-      if (blockIdx.x == 0) {
+      {
         uint32_t* w = (uint32_t*)P.ctl;
-        for (int i = FG_BAR_WORDS + threadIdx.x; i < (int)(sizeof(BfsCtl) / 4); i += PB) w[i] = 0u;
+        for (int i = FG_BAR_WORDS + (int)(blockIdx.x * PB + threadIdx.x); i < (int)(sizeof(BfsCtl) / 4);
+             i += (int)(gridDim.x * PB))
+          w[i] = 0u;
       }
     }
     J.src = P.srcs[job];
@@ -1342,6 +1389,8 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   uint32_t ack_need = 0;  // workgroup 0: acknowledgements of the hand-backs so far
   TeamSync ts{&P.ctl->team_arrive, P.ctl->bar + FG_BAR_STRIDE, (uint32_t)P.team, 0u};
   TeamBases tb = {};
+  const bool shared_out = MULTI && P.out_stride == 0;
+  const bool incremental = shared_out && have_prev;
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
   {
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
@@ -1351,7 +1400,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       uint32_t* sw = (uint32_t*)J_stats(P, J);
       for (int i = threadIdx.x; i < (int)(sizeof(fg_run_stats) / 4); i += PB) sw[i] = 0u;
     }
-    const bool vec = ((((uintptr_t)J_depth(P, J)) | ((uintptr_t)(J_parent(P, J) ? J_parent(P, J) : J_depth(P, J)))) & 15) == 0;
+    const bool vec = !incremental && ((((uintptr_t)J_depth(P, J)) | ((uintptr_t)(J_parent(P, J) ? J_parent(P, J) : J_depth(P, J)))) & 15) == 0;
     if (vec) {
       const int64_t n4 = P.n / 4;
       int4* d4 = (int4*)J_depth(P, J);
@@ -1370,11 +1419,14 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
         J_depth(P, J)[i] = i == src ? 0 : -1;
         if (J_parent(P, J)) J_parent(P, J)[i] = i == src ? src : -1;
       }
-    } else {
+    } else if (!incremental) {
       for (int64_t i = tid; i < P.n; i += nth) {
         J_depth(P, J)[i] = i == src ? 0 : -1;
         if (J_parent(P, J)) J_parent(P, J)[i] = i == src ? src : -1;
       }
+    } else if (tid == 0) {
+      J_depth(P, J)[src] = 0;
+      if (J_parent(P, J)) J_parent(P, J)[src] = src;
     }
     uint64_t* v0 = P.vis[0];
     for (int64_t w = tid; w < P.nwords; w += nth)
@@ -1531,6 +1583,34 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     S.p += nq;
     decide<MODE>(S, P);
     trace_iter(S, P, J);
+  }
+  if (shared_out && ok) {
+    // every test-and-set of the traversal has completed (the last level's
+    // grid barrier or team word); one agent-scope acquire per workgroup
+    // drops stale bitmap lines from this CU's and XCD's caches before the
+    // final bitmap is read with plain loads
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    const uint64_t* fin = P.vis[S.cur];
+    const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * PB;
+    for (int64_t w = tid; w < P.nwords; w += nth) {
+      const uint64_t now = fin[w];
+      if (incremental) {
+        // reached by the previous traversal, not by this one: back to -1
+        uint64_t stale = P.reached[w] & ~now;
+        while (stale) {
+          const int64_t v = w * 64 + __builtin_ctzll(stale);
+          stale &= stale - 1;
+          J_depth(P, J)[v] = -1;
+          if (J_parent(P, J)) J_parent(P, J)[v] = -1;
+        }
+      }
+      // read by this same thread after the next traversal
+      P.reached[w] = now;
+    }
+    have_prev = true;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && J_stats(P, J)) {
     fg_run_stats* st = J_stats(P, J);
@@ -1977,6 +2057,7 @@ struct BfsLayout {
   uint64_t* vis[2];
   int32_t* q[2];
   int4* desc;
+  uint64_t* reached;  // fg_bfs_many, shared outputs: the last traversal's visited set
   size_t bytes;
 };
 
@@ -1989,6 +2070,7 @@ BfsLayout bfs_layout(const fg_graph* g, void* ws) {
   L.q[0] = c.take<int32_t>(g->n);
   L.q[1] = c.take<int32_t>(g->n);
   L.desc = c.take<int4>((size_t)(g->m / CH) + (size_t)g->n + 64);
+  L.reached = c.take<uint64_t>(g->nwords);
   L.bytes = c.used;
   return L;
 }
@@ -2078,6 +2160,7 @@ static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o
   P.parent = parent;
   P.vis[0] = lay.vis[0];
   P.vis[1] = lay.vis[1];
+  P.reached = lay.reached;
   P.q[0] = lay.q[0];
   P.q[1] = lay.q[1];
   P.desc = lay.desc;

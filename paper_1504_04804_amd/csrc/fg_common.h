@@ -175,9 +175,10 @@ __device__ __forceinline__ unsigned long long fg_atomic_load_u64(const unsigned 
 // (int32)(*p - target) >= 0, then one agent-scope acquire fence.  Gives up
 // when `abort_flag` is set or after FG_SPIN_LIMIT polls (then sets it), so
 // every workgroup leaves the kernel even if a peer never arrives.
-// `sleep_cycles` sets the pause between polls: >= 4096 (about 4K clocks)
-// for waits expected to be long, which keeps idle workgroups from
-// hammering the counter's memory channel.
+// `sleep_cycles` sets the pause between polls: >= 4096 for waits that may
+// be long (about 500 clocks for the first 64 polls, 2K for the next 192,
+// then 4K), which keeps idle workgroups from hammering the counter's memory
+// channel.
 #define FG_SPIN_LIMIT (1u << 24)
 
 __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
@@ -193,9 +194,18 @@ __device__ __forceinline__ bool fg_wait_geq(const uint32_t* p, uint32_t target,
       __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
-    if (sleep_cycles >= 4096) __builtin_amdgcn_s_sleep(64);
-    else if (sleep_cycles > 8) __builtin_amdgcn_s_sleep(8);
-    else __builtin_amdgcn_s_sleep(1);
+    if (sleep_cycles >= 4096) {
+      // long waits (a hand-off after an episode of any length): short
+      // pauses first, so the end of a short episode is seen within a few
+      // hundred cycles, then ever fewer polls
+      if (spins < 64) __builtin_amdgcn_s_sleep(8);
+      else if (spins < 256) __builtin_amdgcn_s_sleep(32);
+      else __builtin_amdgcn_s_sleep(64);
+    } else if (sleep_cycles > 8) {
+      __builtin_amdgcn_s_sleep(8);
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;

@@ -101,6 +101,39 @@ def test_many_shared_outputs_and_invalid_sources(fg, orc):
     g.close()
 
 
+def test_many_shared_outputs_reset_between_components(fg, orc):
+    """Shared outputs: a traversal after one that reached other vertices
+    leaves exactly its own reach set non-negative (the vertices only the
+    previous traversal reached go back to -1), whatever came before it,
+    invalid sources and a first source that reaches little included."""
+    # an R-MAT graph plus a disjoint grid and an isolated vertex
+    ro, rc = synth.rmat_csr(12)
+    go, gc = synth.grid_csr(30, 40)
+    nr, ng = len(ro) - 1, len(go) - 1
+    off = np.concatenate([ro, go[1:] + ro[-1], [ro[-1] + go[-1]]]).astype(np.int32)
+    col = np.concatenate([rc, gc + nr]).astype(np.int32)
+    n = nr + ng + 1
+    g = fg.Graph(off, col)
+    a = int(synth.sources(ro, 1, seed=5)[0])
+    b = nr + 617
+    iso = n - 1
+    cases = ([a, b], [b, a], [a, b, a], [b, iso], [iso, a, b], [-1, b, a], [a, n, b],
+             [b, a, b, a, iso, b])
+    for mode in (0, 1):
+        opts = fg.bfs_opts(mode=mode)
+        for srcs in cases:
+            announce(f"bfs_many shared outputs mode={mode} sources {srcs}")
+            depth, parent, sts = run_many(fg, g, srcs, opts, stride=False)
+            last = [s for s in srcs if 0 <= s < n][-1]
+            want = orc.bfs(off, col, last)[0]
+            assert np.array_equal(to_np(depth), want), (mode, srcs)
+            assert orc.check_bfs(off, col, last, want, to_np(parent)) is None
+            for j, s in enumerate(srcs):
+                if 0 <= s < n:
+                    assert sts[j].status == 0 and sts[j].reached == int((orc.bfs(off, col, s)[0] >= 0).sum())
+    g.close()
+
+
 def test_many_episodes_across_traversals(fg, orc):
     """Team and single-workgroup episodes forced, on a grid (long, thin
     frontiers) and R-MAT: the hand-off state is reset between traversals."""
