@@ -197,7 +197,9 @@ def main():
     """Tunes the benchmark workloads and writes tuned.json:
     rmat22_dobfs (direction-optimizing BFS, R-MAT 22, the 64 sources),
     grid4096_push (push BFS, 4096 x 4096 grid, vertex 0),
-    rmat23_msbfs and grid2048_msbfs (64-lane batches, their 64 sources)."""
+    rmat23_msbfs and grid2048_msbfs (64-lane batches, their 64 sources),
+    rmat23_dobfs and grid2048_push (the one-at-a-time paths the batches are
+    compared with: R-MAT 23's 64 sources, the grid's first 4)."""
     ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
@@ -205,22 +207,26 @@ def main():
     torch.cuda.set_device(0)
     log = lambda s: print(f"[autotune] {s}", flush=True)
     cache = load(TUNED_PATH)
-    jobs = [("rmat22_dobfs", lambda: synth.rmat_csr(22, 16), "bfs", fg.FG_MODE_DO),
-            ("grid4096_push", lambda: synth.grid_csr(4096, 4096), "bfs", fg.FG_MODE_PUSH),
-            ("rmat23_msbfs", lambda: synth.rmat_csr(23, 16), "msbfs", None),
-            ("grid2048_msbfs", lambda: synth.grid_csr(2048, 2048), "msbfs", None)]
+    every = lambda off: [int(s) for s in synth.sources(off, 64)]
+    jobs = [("rmat22_dobfs", lambda: synth.rmat_csr(22, 16), "bfs", fg.FG_MODE_DO, every),
+            ("grid4096_push", lambda: synth.grid_csr(4096, 4096), "bfs", fg.FG_MODE_PUSH,
+             lambda off: [0]),
+            ("rmat23_msbfs", lambda: synth.rmat_csr(23, 16), "msbfs", None, every),
+            ("grid2048_msbfs", lambda: synth.grid_csr(2048, 2048), "msbfs", None, every),
+            ("rmat23_dobfs", lambda: synth.rmat_csr(23, 16), "bfs", fg.FG_MODE_DO, every),
+            ("grid2048_push", lambda: synth.grid_csr(2048, 2048), "bfs", fg.FG_MODE_PUSH,
+             lambda off: every(off)[:4])]
     only = set(sys.argv[1:])
-    for name, make, kind, mode in jobs:
+    for name, make, kind, mode, pick in jobs:
         if only and name not in only:
             continue
         t0 = time.time()
         off, col = make()
         g = fg.Graph(off, col, symmetric=True, validate=False)
+        srcs = pick(off)
         if kind == "bfs":
-            srcs = [0] if mode == fg.FG_MODE_PUSH else [int(s) for s in synth.sources(off, 64)]
             kw, ms = tune_bfs(g, srcs, mode, log)
         else:
-            srcs = [int(s) for s in synth.sources(off, 64)]
             kw, ms = tune_msbfs(g, srcs, log)
         cache[name] = dict(kind=kind, signature=signature(g), kwargs=_to_json(kw),
                            ms=round(ms, 4), sources=len(srcs),

@@ -85,7 +85,8 @@ def test_workload_cache_entries(env):
     and checked against the graph it was tuned on."""
     fg, at = env
     cache = at.load(at.TUNED_PATH)
-    for name in ("rmat22_dobfs", "grid4096_push", "rmat23_msbfs", "grid2048_msbfs"):
+    for name in ("rmat22_dobfs", "grid4096_push", "rmat23_msbfs", "grid2048_msbfs",
+                 "rmat23_dobfs", "grid2048_push"):
         assert name in cache, name
         ent = cache[name]
         assert ent["kind"] in ("bfs", "msbfs") and "signature" in ent and "kwargs" in ent
