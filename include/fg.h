@@ -121,7 +121,9 @@ fg_status fg_graph_csr(const fg_graph* g, const int32_t** row_offsets, const int
  * frontier queues are bounded by |V_i|; the unfused advance additionally
  * needs an edge frontier bounded by |E_i|).  Returns 0 for bad arguments.
  * A workspace must be zero-filled once before its first use; every call
- * leaves it ready for the next one.
+ * leaves it ready for the next one.  Its start must be 256-byte aligned
+ * (every hipMalloc allocation is): the calls carve it into 256-byte aligned
+ * pieces and return FG_EINVAL for a misaligned one.
  */
 size_t fg_workspace_bytes(const fg_graph* g, int32_t primitive, int32_t lanes);
 
@@ -214,7 +216,13 @@ fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* opts,
  * traversal writes the same arrays, the last one's result remains;
  * otherwise out_stride >= n) and stats + j (device fg_run_stats[nsrc], or
  * NULL).  opts, ws and errors as for fg_bfs (FG_EUNSUPPORTED for the
- * unfused mode).  nsrc = 0 does nothing.
+ * unfused mode; the asynchronous push mode, async_levels > 1, is a
+ * one-source mode, so the sources run level-synchronously here).  With
+ * out_stride = 0 a traversal after the first writes only the vertices it
+ * reaches and resets those the previous one reached alone, which keeps
+ * the outputs exactly fg_bfs's; the workspace holds the visited set in
+ * between, so it must not be used by another call during the launch.
+ * nsrc = 0 does nothing.
  */
 fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
                       const fg_bfs_opts* opts, void* ws, size_t ws_bytes, int32_t* depth,

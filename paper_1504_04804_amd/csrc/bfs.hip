@@ -2228,6 +2228,7 @@ extern "C" fg_status fg_bfs(const fg_graph* g, int32_t src, const fg_bfs_opts* o
   if (o.mode == FG_MODE_PUSH_UNFUSED)
     return fg_bfs_unfused(g, src, ws, ws_bytes, depth, parent, stats, (hipStream_t)stream);
   BfsLayout lay = bfs_layout(g, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_bfs");
   if (ws_bytes < lay.bytes)
     return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);
@@ -2253,6 +2254,7 @@ extern "C" fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t
   if (o.mode == FG_MODE_PUSH_UNFUSED)
     return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_many: the unfused mode runs one source per call");
   BfsLayout lay = bfs_layout(g, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_bfs_many");
   if (ws_bytes < lay.bytes)
     return fg_set_error(FG_ENOMEM, "fg_bfs_many: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);

@@ -229,6 +229,7 @@ extern "C" fg_status fg_cc(const fg_graph* g, int32_t* label, int64_t* component
   if (!g || !label || !ws) return fg_set_error(FG_EINVAL, "fg_cc: NULL argument");
   if (!g->symmetric)
     return fg_set_error(FG_EUNSUPPORTED, "fg_cc: needs an undirected graph (FG_SYMMETRIC)");
+  FG_CHECK_WS_ALIGN(ws, "fg_cc");
   if (ws_bytes < sizeof(CcCtl))
     return fg_set_error(FG_ENOMEM, "fg_cc: workspace of %zu bytes < required %zu", ws_bytes,
                         sizeof(CcCtl));

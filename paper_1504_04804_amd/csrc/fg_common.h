@@ -63,6 +63,14 @@ fg_device_props fg_props(int device);
 
 static inline size_t fg_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspaces are carved into 256-byte aligned pieces from their start, so
+// the start must be 256-byte aligned too (every hipMalloc allocation is).
+#define FG_CHECK_WS_ALIGN(ws, fn)                                                      \
+  do {                                                                                 \
+    if (((uintptr_t)(ws) & 255u) != 0)                                                 \
+      return fg_set_error(FG_EINVAL, fn ": workspace %p is not 256-byte aligned", (ws)); \
+  } while (0)
+
 // Carves a caller workspace into 256-byte aligned pieces.
 struct fg_carver {
   char* base;

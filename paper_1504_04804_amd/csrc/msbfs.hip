@@ -1168,6 +1168,7 @@ extern "C" fg_status fg_msbfs_open(const fg_graph* g, int32_t lanes, void* ws, s
   if (lanes < 1 || lanes > MAXL)
     return fg_set_error(FG_EINVAL, "fg_msbfs_open: lanes=%d outside [1, 64]", lanes);
   MsLayout lay = ms_layout(g, lanes, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_msbfs_open");
   if (ws_bytes < lay.bytes)
     return fg_set_error(FG_ENOMEM, "fg_msbfs_open: workspace of %zu bytes < required %zu",
                         ws_bytes, lay.bytes);

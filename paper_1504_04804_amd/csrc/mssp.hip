@@ -1278,6 +1278,7 @@ extern "C" fg_status fg_mssp_open(const fg_graph* g, int32_t lanes, void* ws, si
   if (lanes < 1 || lanes > MAXL)
     return fg_set_error(FG_EINVAL, "fg_mssp_open: lanes=%d outside [1, 64]", lanes);
   MpLayout lay = mp_layout(g, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_mssp_open");
   if (ws_bytes < lay.bytes)
     return fg_set_error(FG_ENOMEM, "fg_mssp_open: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);

@@ -378,6 +378,7 @@ extern "C" fg_status fg_advance(const fg_graph* g, const int32_t* frontier, int3
   if (len > 0 && !frontier) return fg_set_error(FG_EINVAL, "fg_advance: frontier is NULL");
   if (capacity < 0) return fg_set_error(FG_EINVAL, "fg_advance: negative capacity");
   OpsLayout L = ops_layout(g, ws, false);
+  FG_CHECK_WS_ALIGN(ws, "fg_advance");
   if (ws_bytes < L.bytes)
     return fg_set_error(FG_ENOMEM, "fg_advance: workspace of %zu bytes < required %zu", ws_bytes,
                         L.bytes);
@@ -440,6 +441,7 @@ extern "C" fg_status fg_bitmap_to_queue(const fg_graph* g, const uint64_t* bits,
   if (!g || !bits || !out_q || !out_len || !ws)
     return fg_set_error(FG_EINVAL, "fg_bitmap_to_queue: NULL argument");
   OpsLayout L = ops_layout(g, ws, false);
+  FG_CHECK_WS_ALIGN(ws, "fg_bitmap_to_queue");
   if (ws_bytes < L.bytes)
     return fg_set_error(FG_ENOMEM, "fg_bitmap_to_queue: workspace of %zu bytes < required %zu",
                         ws_bytes, L.bytes);
@@ -459,6 +461,7 @@ extern "C" fg_status fg_bitmap_to_queue(const fg_graph* g, const uint64_t* bits,
 fg_status fg_bfs_unfused(const fg_graph* g, int32_t src, void* ws, size_t ws_bytes,
                          int32_t* depth, int32_t* parent, fg_run_stats* stats, hipStream_t s) {
   OpsLayout L = ops_layout(g, ws, true);
+  FG_CHECK_WS_ALIGN(ws, "fg_bfs_unfused");
   if (ws_bytes < L.bytes)
     return fg_set_error(FG_ENOMEM, "fg_bfs: workspace of %zu bytes < required %zu (unfused)",
                         ws_bytes, L.bytes);

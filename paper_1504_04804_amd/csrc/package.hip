@@ -417,6 +417,7 @@ extern "C" fg_status fg_package(const fg_share* s, const int32_t* frontier, int3
   if (parent && !out->parent)
     return fg_set_error(FG_EINVAL, "fg_package: parent given without an output buffer");
   const size_t need = fg_package_workspace_bytes(s, len);
+  FG_CHECK_WS_ALIGN(ws, "fg_package");
   if (!ws || ws_bytes < need)
     return fg_set_error(FG_ENOMEM, "fg_package: workspace of %zu bytes < required %zu", ws_bytes,
                         need);

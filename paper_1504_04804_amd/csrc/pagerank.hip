@@ -228,6 +228,7 @@ extern "C" fg_status fg_pagerank(const fg_graph* g, double damping, double tol, 
   if (max_iter < 0 || max_iter > 100000)
     return fg_set_error(FG_EINVAL, "fg_pagerank: max_iter %d outside [0, 100000]", max_iter);
   PrLayout L = pr_layout(g, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_pagerank");
   if (ws_bytes < L.bytes)
     return fg_set_error(FG_ENOMEM, "fg_pagerank: workspace of %zu bytes < required %zu",
                         ws_bytes, L.bytes);

@@ -1300,6 +1300,7 @@ extern "C" fg_status fg_sssp(const fg_graph* g, int32_t src, const fg_sssp_opts*
   fg_sssp_opts o;
   if (opts) o = *opts; else fg_sssp_opts_default(&o);
   SsspLayout lay = sssp_layout(g, ws);
+  FG_CHECK_WS_ALIGN(ws, "fg_sssp");
   if (ws_bytes < lay.bytes)
     return fg_set_error(FG_ENOMEM, "fg_sssp: workspace of %zu bytes < required %zu", ws_bytes,
                         lay.bytes);

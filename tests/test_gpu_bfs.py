@@ -192,3 +192,29 @@ def test_config_grid4096_push(fg, orc):
     assert np.array_equal(d.reshape(4096, 4096), r[:, None] + r[None, :])
     assert st.iterations == 8191
     assert orc.check_bfs(off, col, 0, d, to_np(parent)) is None
+
+
+def test_workspace_alignment_checked(fg, orc):
+    """A workspace whose start is not 256-byte aligned is refused with
+    FG_EINVAL before anything runs (every primitive carves its workspace
+    into 256-byte aligned pieces); the aligned one still works."""
+    off, col = synth.rmat_csr(8)
+    g = fg.Graph(off, col)
+    need = g.workspace_bytes(fg.FG_PRIM_BFS)
+    big = torch.zeros(need + 512, dtype=torch.uint8, device="cuda")
+    depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for shift in (16, 128):
+        with pytest.raises(fg.FGError) as e:
+            fg.bfs_into(g, 0, depth, None, fg.bfs_opts(), ws=big[shift:shift + need])
+        assert e.value.status == fg.FG_EINVAL
+        srcs = torch.zeros(2, dtype=torch.int32, device="cuda")
+        with pytest.raises(fg.FGError) as e:
+            fg.bfs_many_into(g, srcs, depth, None, fg.bfs_opts(), ws=big[shift:shift + need])
+        assert e.value.status == fg.FG_EINVAL
+        with pytest.raises(fg.FGError) as e:
+            fg.cc_into(g, torch.empty(g.n, dtype=torch.int32, device="cuda"),
+                       ws=big[shift:shift + 64])
+        assert e.value.status == fg.FG_EINVAL
+    fg.bfs_into(g, 0, depth, None, fg.bfs_opts(), ws=big[256:256 + need])
+    assert np.array_equal(to_np(depth), orc.bfs(off, col, 0)[0])
+    g.close()
