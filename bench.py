@@ -37,8 +37,40 @@ GRID = 4096
 # rmat22x64_grid4096.md).  They hold only for the kernel sources they were
 # taken with: `traffic` is null when these files hash differently.
 TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
-TRAFFIC_SHA256 = "cf75af259cc551b2337fee0932f794579538e73f9ec0acea46e2085fba0cfaca"
-TRAFFIC_BYTES = {"bfs_persistent<DO,many>": 16465487632, "bfs_async": 2280445600}
+TRAFFIC_SHA256 = "a1a9e69dc0eef6f6ded390755ee22fab3a9579e6d0005d910f478bd93c1a4e8b"
+TRAFFIC_BYTES = {"bfs_persistent<DO,many>": 15693448304, "bfs_async": 2282136272}
+# The same for the side workloads' kernels (per launch; PageRank per
+# iteration), from the same two passes
+# (profiles/side_kernels_hbm_counters.md), guarded by a hash of every
+# kernel source.
+SIDE_TRAFFIC_SHA256 = "e2d432a6705ff9ab4ffdc5726431015af7e98a75be198a6b08fa8e0ec44a2e94"
+SIDE_TRAFFIC_BYTES = {"sssp": 12531062513, "c4_rmat23": 21785049024, "c4_grid2048": 519191457408,
+                      "mssp_rmat22": 145310951648, "mssp_grid2048": 515582469712,
+                      "pagerank_iter": 4173879154}
+
+
+def _sources_sha(names):
+    import hashlib
+    h = hashlib.sha256()
+    for f in names:
+        with open(os.path.join(ROOT, "paper_1504_04804_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _all_kernel_sources():
+    d = os.path.join(ROOT, "paper_1504_04804_amd", "csrc")
+    return tuple("csrc/" + f for f in sorted(os.listdir(d)) if f.endswith((".hip", ".h", ".cpp")))
+
+
+def side_traffic(name, seconds):
+    """Counter bytes of a side workload's kernel and the rate they give, or
+    Nones when the kernel sources differ from those the counters were
+    taken on."""
+    if _sources_sha(_all_kernel_sources()) != SIDE_TRAFFIC_SHA256 or name not in SIDE_TRAFFIC_BYTES:
+        return {"traffic": None, "traffic_gbs": None}
+    b = SIDE_TRAFFIC_BYTES[name]
+    return {"traffic": b, "traffic_gbs": round(b / seconds / 1e9, 2)}
 
 # Launch options of every timed workload (DO thresholds do_a / do_b of
 # Sec. VI-A, push load-balance cut, team width, batched push/pull switch
@@ -255,7 +287,8 @@ def side_sssp(fg, torch, off, col, srcs, stream, cpu):
         "gteps": round(sum(m_comp) / (sum(lat) * 1e-3) / 1e9, 3),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 5),
-                     "alg_bytes_per_launch": round(float(np.mean(byts)))},
+                     "alg_bytes_per_launch": round(float(np.mean(byts))),
+                     **side_traffic("sssp", ms * 1e-3)},
     }
     if cpu:
         import oracle
@@ -474,6 +507,7 @@ def side_batched(fg, torch, stream, do_kw, cpu):
                          "alg_bytes_per_launch": round(alg),
                          "alg_bytes_as_run": round(alg_done),
                          "alg_bytes_push_only": round(alg_push),
+                         **side_traffic(f"c4_{name}", ms_b * 1e-3),
                          "note": "12 B per adjacency entry read + 24 B per vertex visit + "
                                  "4 B per (lane, vertex) depth fill + 4 B per depth found, "
                                  "the smaller of the count over the work done and over a "
@@ -551,6 +585,8 @@ def side_batched_sssp(fg, torch, stream, rmat22, cpu):
                          f"source, mean over {len(st)} sources",
             "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                         "alg_bytes_per_launch": round(float(byts[int(np.argmin(bt))])),
+                         **side_traffic(f"mssp_{name}", ms_b * 1e-3),
                          "note": "8 B per edge visit + 8 B per (edge, lane) relaxation"},
         }
         g.close()
@@ -748,6 +784,7 @@ def side_pagerank(fg, torch, stream, off, col, cpu):
            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
                         "alg_bytes_per_iteration": round(alg),
+                        **side_traffic("pagerank_iter", per_it * 1e-3),
                         "note": "12 B per CSR entry + 32 B per vertex per iteration"}}
     g.close()
     if cpu:
@@ -1068,12 +1105,7 @@ def main():
         k["frac"] = k["gbs"] / HBM_PEAK_GBS
     dom = max(kernels, key=lambda k: kernels[k]["share_ms"])
     dk = kernels[dom]
-    import hashlib
-    hsh = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1504_04804_amd", f), "rb") as fh:
-            hsh.update(fh.read())
-    traffic = TRAFFIC_BYTES.get(dom) if hsh.hexdigest() == TRAFFIC_SHA256 else None
+    traffic = TRAFFIC_BYTES.get(dom) if _sources_sha(TRAFFIC_SOURCES) == TRAFFIC_SHA256 else None
     step_ms = ms_per_step
     value = edges_step / (step_ms * 1e-3) / 1e9
 
