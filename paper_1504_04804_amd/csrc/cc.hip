@@ -15,7 +15,10 @@
 // The order of the hooks is free, which the passes use (the neighbour
 // sampling of Sutton, Ben-Nun and Barak's Afforest):
 //   link     every vertex hooks its first two neighbours (the graph's head
-//            table: one coalesced 16-byte load per vertex)
+//            table: one coalesced 16-byte load per vertex); on graphs with
+//            hubs the first one while the labels are initialised, by
+//            pointing the vertex at its first neighbour when that is
+//            smaller (a forest already, no atomics)
 //   compress every label becomes its root
 //   sample   the most frequent root of 1024 sampled vertices, c: on graphs
 //            with a giant component, that component's root
@@ -27,7 +30,8 @@
 // The hook pass is edge-balanced: each task is a fixed range of CSR
 // entries whose rows are found with a binary search over the offsets
 // (staged in LDS), so a row of any length costs its share of the range,
-// and the entries of skipped rows cost no column read.
+// and the entries of skipped rows cost no column read; a task none of whose
+// rows has work is left after one label read per row.
 #include <string.h>
 
 #include "fg_common.h"
@@ -92,29 +96,44 @@ __device__ __forceinline__ int32_t cc_root(const int32_t* p, int32_t x) {
   return cur;
 }
 
-__global__ __launch_bounds__(CC_BT) void cc_init_kernel(int32_t n, int32_t* __restrict__ label,
+// label[v] = v, or v's first neighbour where that one is smaller: already
+// a forest of pointers to smaller vertices of the same component, written
+// without atomics (the first link of the link pass).
+__global__ __launch_bounds__(CC_BT) void cc_init_kernel(int32_t n, const int4* __restrict__ head,
+                                                        const int32_t* __restrict__ off,
+                                                        int32_t* __restrict__ label,
                                                         CcCtl* __restrict__ ctl) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    label[v] = (int32_t)v;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t l = (int32_t)v;
+    if (head && off[v + 1] > off[v]) {
+      const int32_t u = head[v].x;
+      if (u < l) l = u;
+    }
+    label[v] = l;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->giant = -1;
     ctl->comps = 0;
   }
 }
 
-// Hooks entry `k` (0 or 1) of every row, from the head table.
+// Hooks from the head table: the first entry of every row (LINK_FIRST),
+// the second (LINK_SECOND), or the second and, where the init pass did not
+// link it (a first neighbour larger than the vertex), the first
+// (LINK_REST).  After the passes run, both first entries of every row are
+// hooked.
+constexpr int LINK_FIRST = 0, LINK_SECOND = 1, LINK_REST = 2;
 __global__ __launch_bounds__(CC_BT) void cc_link_kernel(int32_t n, const int4* __restrict__ head,
                                                         const int32_t* __restrict__ off,
-                                                        int32_t k, int32_t* __restrict__ label) {
+                                                        int32_t what, int32_t* __restrict__ label) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int4 h = head[v];
     const int32_t deg = off[v + 1] - off[v];
-    if (deg > k) {
-      const int32_t u = k == 0 ? h.x : h.y;
-      if (u != (int32_t)v) cc_unite(label, (int32_t)v, u);
-    }
+    if (what != LINK_SECOND && deg > 0 && (what == LINK_FIRST ? h.x != (int32_t)v : h.x > (int32_t)v))
+      cc_unite(label, (int32_t)v, h.x);
+    if (what != LINK_FIRST && deg > 1 && h.y != (int32_t)v) cc_unite(label, (int32_t)v, h.y);
   }
 }
 
@@ -198,6 +217,16 @@ __global__ __launch_bounds__(CC_BT) void cc_hook_kernel(int32_t n, int64_t m,
     if (staged)
       for (int32_t i = threadIdx.x; i < span; i += CC_BT) s_off[i] = off[u0 + i];
     __syncthreads();
+    // a task whose rows all lie in the sampled tree (or have no entry past
+    // the first two) has nothing to hook: one look at each row's label
+    // instead of a search per entry
+    int todo = 0;
+    for (int32_t i = threadIdx.x; i <= u1 - u0 && !todo; i += CC_BT) {
+      const int32_t u = u0 + i;
+      const int32_t deg = staged ? s_off[i + 1] - s_off[i] : off[u + 1] - off[u];
+      todo = deg > CC_SKIP && label[u] != giant;
+    }
+    if (!__syncthreads_or(todo)) continue;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += CC_BT) {
       int32_t u, first;
       if (staged) {
@@ -237,10 +266,19 @@ extern "C" fg_status fg_cc(const fg_graph* g, int32_t* label, int64_t* component
   CcCtl* ctl = (CcCtl*)ws;
   const int cus = fg_props(g->device).cus;
   const int grid = (cus > 0 ? cus : 256) * 8;
-  cc_init_kernel<<<grid, CC_BT, 0, s>>>(g->n, label, ctl);
+  // On graphs with hubs (mean degree above 8) a vertex's first neighbour is
+  // usually a smaller hub, and the init pass links it for free; on grids
+  // and road-like graphs that would chain every vertex to the one before
+  // it, so they hook both first entries by compare-and-swap.
+  const bool init_link = g->m > 8 * (int64_t)g->n;
+  cc_init_kernel<<<grid, CC_BT, 0, s>>>(g->n, init_link ? g->head : nullptr, g->off, label, ctl);
   if (g->m > 0) {
-    cc_link_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->head, g->off, 0, label);
-    cc_link_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->head, g->off, 1, label);
+    if (init_link) {
+      cc_link_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->head, g->off, LINK_REST, label);
+    } else {
+      cc_link_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->head, g->off, LINK_FIRST, label);
+      cc_link_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->head, g->off, LINK_SECOND, label);
+    }
     cc_compress_kernel<<<grid, CC_BT, 0, s>>>(g->n, label, nullptr);
     cc_sample_kernel<<<1, CC_SAMPLES, 0, s>>>(g->n, label, ctl);
     cc_hook_kernel<<<grid, CC_BT, 0, s>>>(g->n, g->m, g->off, g->col, label, ctl);
