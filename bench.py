@@ -41,12 +41,25 @@ TRAFFIC_SHA256 = "a1a9e69dc0eef6f6ded390755ee22fab3a9579e6d0005d910f478bd93c1a4e
 TRAFFIC_BYTES = {"bfs_persistent<DO,many>": 15693448304, "bfs_async": 2282136272}
 # The same for the side workloads' kernels (per launch; PageRank per
 # iteration), from the same two passes
-# (profiles/side_kernels_hbm_counters.md), guarded by a hash of every
-# kernel source.
-SIDE_TRAFFIC_SHA256 = "e2d432a6705ff9ab4ffdc5726431015af7e98a75be198a6b08fa8e0ec44a2e94"
-SIDE_TRAFFIC_BYTES = {"sssp": 12531062513, "c4_rmat23": 21785049024, "c4_grid2048": 519191457408,
-                      "mssp_rmat22": 145310951648, "mssp_grid2048": 515582469712,
-                      "pagerank_iter": 4173879154}
+# (profiles/side_kernels_hbm_counters.md), each guarded by a hash of the
+# sources its kernel is built from.
+_COMMON = ('csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
+SIDE_TRAFFIC = {
+    "sssp": (('csrc/sssp.hip',) + _COMMON, 12531062513),
+    "c4_rmat23": (('csrc/msbfs.hip',) + _COMMON, 21785049024),
+    "c4_grid2048": (('csrc/msbfs.hip',) + _COMMON, 519191457408),
+    "mssp_rmat22": (('csrc/mssp.hip',) + _COMMON, 145310951648),
+    "mssp_grid2048": (('csrc/mssp.hip',) + _COMMON, 515582469712),
+    "pagerank_iter": (('csrc/pagerank.hip',) + _COMMON, 4173879154),
+}
+SIDE_TRAFFIC_SHA256 = {
+    "sssp": "0c737dc3597a498653df2bc2c3f9d03779fecc203dcf69743c2fda4c247c17f9",
+    "c4_rmat23": "d65b3c254cb6f58ea6a820a3443705ebc8ef5830fea8f8d67622caafa447cc04",
+    "c4_grid2048": "d65b3c254cb6f58ea6a820a3443705ebc8ef5830fea8f8d67622caafa447cc04",
+    "mssp_rmat22": "4e66b1cdc302c4f10bbded066dbb52a4cee6aa8a09bb20686e01b0b33720ea13",
+    "mssp_grid2048": "4e66b1cdc302c4f10bbded066dbb52a4cee6aa8a09bb20686e01b0b33720ea13",
+    "pagerank_iter": "3ed415d713c996a91430276449ef8d0c185ba137a170bde96531cfe61460d2e3",
+}
 
 
 def _sources_sha(names):
@@ -58,18 +71,12 @@ def _sources_sha(names):
     return h.hexdigest()
 
 
-def _all_kernel_sources():
-    d = os.path.join(ROOT, "paper_1504_04804_amd", "csrc")
-    return tuple("csrc/" + f for f in sorted(os.listdir(d)) if f.endswith((".hip", ".h", ".cpp")))
-
-
 def side_traffic(name, seconds):
     """Counter bytes of a side workload's kernel and the rate they give, or
-    Nones when the kernel sources differ from those the counters were
-    taken on."""
-    if _sources_sha(_all_kernel_sources()) != SIDE_TRAFFIC_SHA256 or name not in SIDE_TRAFFIC_BYTES:
+    Nones when its sources differ from those the counters were taken on."""
+    if name not in SIDE_TRAFFIC or _sources_sha(SIDE_TRAFFIC[name][0]) != SIDE_TRAFFIC_SHA256.get(name):
         return {"traffic": None, "traffic_gbs": None}
-    b = SIDE_TRAFFIC_BYTES[name]
+    b = SIDE_TRAFFIC[name][1]
     return {"traffic": b, "traffic_gbs": round(b / seconds / 1e9, 2)}
 
 # Launch options of every timed workload (DO thresholds do_a / do_b of
