@@ -943,7 +943,10 @@ def side_serving(fg, torch, cpu_graphs):
                "fifo": {k: round(v, 3) for k, v in fifo.items()},
                "served_batched_frac": round(nb / len(done), 3),
                "served_steps": srv.counts["steps"], "served_singles": srv.counts["singles"],
-               "served_evictions": srv.counts["evictions"]}
+               "served_evictions": srv.counts["evictions"],
+               "hbm_resident_graphs_bytes": srv.resident_bytes,
+               "hbm_workspace_peak_bytes": srv.peak_used,
+               "hbm_total_peak_bytes": srv.resident_bytes + srv.peak_used}
         sweep.append(row)
         print(f"[bench] serving qps={qps} ({nreq} requests): served p50={served['p50_ms']:.1f} "
               f"p99={served['p99_ms']:.1f} qps={served['qps']:.1f} | fifo p50={fifo['p50_ms']:.1f} "

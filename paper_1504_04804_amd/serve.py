@@ -95,7 +95,8 @@ class Server:
     """Continuous-batching query server over resident graphs.
 
     graphs: dict name -> fg.Graph (SSSP needs weights).  hbm_budget: bytes
-    the server may hold in workspaces.  policy: "auto" (the cost model picks
+    the server may hold in workspaces (the resident graphs' own bytes come on
+    top: `resident_bytes`; `peak_used` is the most the workspaces held).  policy: "auto" (the cost model picks
     batch or single when a batch is idle), "batch" (always batch) or
     "single" (always single runs, oldest first).  costs: dict (name, kind) ->
     Cost, e.g. from calibrate(); missing entries default to batching.
@@ -114,6 +115,10 @@ class Server:
                 self.kinds[key].cost = c
         self.budget = int(hbm_budget)
         self.used = 0
+        self.peak_used = 0
+        # HBM the resident graphs hold (CSR, weights, head table, masks),
+        # outside the workspace budget; reported beside it
+        self.resident_bytes = sum(int(g.info().resident_bytes) for g in graphs.values())
         self.policy = policy
         self.step_ms = float(step_ms)
         self.keep = keep_results
@@ -139,6 +144,7 @@ class Server:
         """Reserve nbytes, closing idle batches (least recently used first)."""
         if self.used + nbytes <= self.budget:
             self.used += nbytes
+            self.peak_used = max(self.peak_used, self.used)
             return True
         idle = sorted((k for k in self.kinds.values()
                        if k.batch is not None and not k.lane_req and k is not keep),
@@ -148,6 +154,7 @@ class Server:
             self.counts["evictions"] += 1
             if self.used + nbytes <= self.budget:
                 self.used += nbytes
+                self.peak_used = max(self.peak_used, self.used)
                 return True
         return False
 

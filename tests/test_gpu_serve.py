@@ -69,6 +69,9 @@ def test_served_mix_equals_alone(env, orc, budget, policy, step_ms):
         assert srv.counts["steps"] == 0 and srv.counts["singles"] == len(reqs)
     st = serve.latency_stats(done)
     assert st["n"] == len(reqs)
+    # workspaces stayed within the budget; the graphs' own bytes are counted apart
+    assert 0 < srv.peak_used <= budget
+    assert srv.resident_bytes == sum(int(g.info().resident_bytes) for g in graphs.values()) > 0
 
 
 def test_budget_too_small_is_reported(env):
