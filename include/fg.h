@@ -388,8 +388,11 @@ void fg_msbfs_opts_default(fg_msbfs_opts* opts);
 
 /*
  * A batch of up to 64 independent BFS queries (lanes) that share one
- * traversal with one bit per lane in each vertex word.  Each lane's depths
- * equal fg_bfs's depths from its source.  Lanes are admitted at any step
+ * traversal with one bit per lane in each vertex word.  Each query is
+ * Alg. 1's BFS (push levels, and pull levels as in Sec. VI-A's backward
+ * step); the paper runs its sources one after another (Sec. VII), and
+ * batching them is this library's serving mode, not the paper's.  Each
+ * lane's depths equal fg_bfs's depths from its source.  Lanes are admitted at any step
  * boundary (continuous batching) and are done when their frontier empties.
  * ws: device workspace of fg_workspace_bytes(g, FG_PRIM_MSBFS, lanes) bytes,
  * owned by the caller, used exclusively by this batch until fg_msbfs_close.
@@ -462,8 +465,8 @@ void fg_mssp_opts_default(fg_mssp_opts* opts);
 
 /*
  * A batch of up to 64 independent SSSP queries (lanes) over the graph's
- * uint32 weights (Table I's SSSP, one query per source) sharing one
- * traversal: each iteration relaxes, for every vertex in some lane's near
+ * uint32 weights (Table I's SSSP, one query per source; batching them is
+ * this library's serving mode, not the paper's) sharing one traversal: each iteration relaxes, for every vertex in some lane's near
  * frontier, its edges for all of those lanes at once, and each lane orders
  * its work near-far with its own threshold (see fg_sssp).  Each lane's
  * distances equal fg_sssp's distances from its source (no parents).  Lanes
