@@ -1668,8 +1668,10 @@ struct AsLds {
   int32_t qe[2][AQ];
   int4 qh[2][AQ];
   int32_t cnt[2];
-  int32_t ovf;
-  int32_t big;
+  // by level parity: an append of the level did not fit; a vertex of degree
+  // > TPV is in the level's queue
+  int32_t ovf[2];
+  int32_t big[2];
   int32_t flag;
   int32_t tot;
   int32_t pre;
@@ -1690,9 +1692,10 @@ __device__ __forceinline__ bool as_relax(ull* key, int32_t v, int32_t u, int32_t
 }
 
 // Queues the winners of a relaxation round in the next LDS queue (room
-// permitting; an overflow stops the traversal).  Every lane must take part.
-__device__ __forceinline__ void as_put(AsLds& L, int nxt, bool won, int32_t v, int32_t vb,
-                                      int32_t ve, int4 vh) {
+// permitting; an overflow, flagged in L.ovf[par], stops the traversal).
+// Every lane must take part.
+__device__ __forceinline__ void as_put(AsLds& L, int nxt, int par, bool won, int32_t v,
+                                      int32_t vb, int32_t ve, int4 vh) {
   const int32_t pos = wave_reserve(won ? 1 : 0, &L.cnt[nxt]);
   if (won) {
     if (pos < AQ) {
@@ -1701,7 +1704,7 @@ __device__ __forceinline__ void as_put(AsLds& L, int nxt, bool won, int32_t v, i
       L.qe[nxt][pos] = ve;
       L.qh[nxt][pos] = vh;
     } else {
-      L.ovf = 1;
+      L.ovf[par] = 1;
     }
   }
 }
@@ -1721,7 +1724,8 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
   if (tid == 0) {
     L.cnt[0] = blockIdx.x == 0 ? 1 : 0;
     L.cnt[1] = 0;
-    L.ovf = 0;
+    L.ovf[0] = L.ovf[1] = 0;
+    L.big[0] = L.big[1] = 0;
     L.stop = 0;
     if (blockIdx.x == 0) {
       L.qv[0][0] = P.src;
@@ -1733,6 +1737,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
   __syncthreads();
   int cur = 0;
   int32_t base = 0;  // depth of the entries of queue `cur` at a super-step start
+  bool overflow = false;
   bool ok = true;
   // every super-step advances the queued depths by K, and no shortest
   // depth exceeds n - 1: past this many the team gives up (the
@@ -1748,12 +1753,10 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
       const int nxt = cur ^ 1;
       const int32_t cnt = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
       const int32_t d1 = base + t + 1;
-      __syncthreads();
-      if (tid == 0) {
-        L.cnt[nxt] = 0;
-        L.big = 0;
-      }
-      __syncthreads();
+      // the next queue's counter and this level's flags were cleared in the
+      // previous level, after every thread had read what they held (see
+      // below): no barriers at the start of a level
+      const int par = (base + t) & 1;
       // vertices of degree <= TPV: TPV lanes each, neighbours from the head
       // entry in LDS (the discoverer's slot blanked)
       bool big = false;
@@ -1781,11 +1784,18 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
           }
         }
         if (won) vh = blank_parent(vh, u);
-        as_put(L, nxt, won, v, vb, ve, vh);
+        as_put(L, nxt, par, won, v, vb, ve, vh);
       }
-      if (big) L.big = 1;
+      if (big) L.big[par] = 1;
       __syncthreads();
-      if (L.big) {
+      if (tid == 0) {
+        // every thread has read this level's input count (at the start) and
+        // the flags of the previous level (behind the last barrier)
+        L.cnt[cur] = 0;
+        L.ovf[par ^ 1] = 0;
+        L.big[par ^ 1] = 0;
+      }
+      if (L.big[par]) {
         // vertices of degree > TPV: block scan-gather over their rows
         for (int32_t c0 = 0; c0 < cnt; c0 += PB) {
           const int32_t i = c0 + tid;
@@ -1819,20 +1829,25 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
               insp++;
             }
             if (won) vh = blank_parent(vh, pu);
-            as_put(L, nxt, won, v, vb, ve, vh);
+            as_put(L, nxt, par, won, v, vb, ve, vh);
           }
           __syncthreads();
         }
       }
       __syncthreads();
       cur = nxt;
-      if (L.ovf) break;  // LDS flag: every thread sees the same value here
+      // every append of this level is behind that barrier, and the next
+      // level flags the other slot: every thread sees the same value
+      if (L.ovf[par]) {
+        overflow = true;
+        break;
+      }
     }
     base += K;
     // exchange: queue lengths (and an overflow) to the team
     if (tid == 0) {
       const int32_t c = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
-      fg_st_shared(&C->as_rec[blockIdx.x], ((ull)(L.ovf ? 1 : 0) << 63) | (ull)(uint32_t)c);
+      fg_st_shared(&C->as_rec[blockIdx.x], ((ull)(overflow ? 1 : 0) << 63) | (ull)(uint32_t)c);
     }
     if (!ts.sync_acquire(&L.flag)) {
       ok = false;
