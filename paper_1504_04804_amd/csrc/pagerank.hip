@@ -9,9 +9,10 @@
 //   contrib_{i+1}(v) = rank_{i+1}(v) / deg(v)   (0 for degree 0)
 // in one pass: the accumulation is a gather over v's own row (a pull, no
 // atomics), so each vertex's new rank is final when its row is done.  Rows
-// are summed by one lane (fewer than 64 entries, in CSR order), one wave
-// (up to PR_LONG entries) or one workgroup (longer rows, listed once per
-// call and taken first).  Convergence (the threshold ratio): the run stops
+// of fewer than 64 entries are laid end to end over a wave's lanes (64
+// entries per step, segmented sums), rows up to PR_LONG entries are summed
+// by one wave each and longer rows by one workgroup (listed once per call
+// and taken first); every row's sum is formed in a fixed order.  Convergence (the threshold ratio): the run stops
 // after an iteration in which every vertex changed by at most tol times its
 // previous rank; tol = 0 runs max_iter iterations.  Every iteration is a
 // launch that returns at once when the run has already stopped, so the
@@ -20,6 +21,7 @@
 #include <string.h>
 
 #include "fg_common.h"
+#include "frontier.h"
 
 namespace {
 
@@ -99,10 +101,52 @@ __global__ void pr_reset_kernel(PrCtl* c) {
   }
 }
 
+// Sum of x over the lanes of this lane's run of equal `key` up to this
+// lane (runs are adjacent lanes; `start` = the run's first lane), in a
+// fixed order.
+__device__ __forceinline__ double seg_incl_sum(double x, int lane, int start) {
+#pragma unroll
+  for (int dd = 1; dd < FG_WAVE; dd <<= 1) {
+    const double y = __shfl_up(x, dd, FG_WAVE);
+    if (lane - dd >= start) x += y;
+  }
+  return x;
+}
+
+// Sum of cur[col[i]] for i = first, first + stride, ... < end, with four
+// independent partial sums so that four gathers per thread are in flight
+// (a long row is otherwise a chain of dependent column-then-value loads,
+// and the longest row held its workgroup for most of an iteration; eight
+// partial sums measured no faster); the order of the additions is fixed.
+__device__ __forceinline__ double strided_gather_sum(const double* cur, const int32_t* col,
+                                                     int32_t first, int32_t end, int32_t stride) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int32_t i = first;
+  // every index of a round is below `end`: i < end - 3 * stride (no
+  // overflow: end >= 0 and 3 * stride is small)
+  for (; i < end - 3 * stride; i += 4 * stride) {
+    const int32_t c0 = col[i];
+    const int32_t c1 = col[i + stride];
+    const int32_t c2 = col[i + 2 * stride];
+    const int32_t c3 = col[i + 3 * stride];
+    a0 += cur[c0];
+    a1 += cur[c1];
+    a2 += cur[c2];
+    a3 += cur[c3];
+  }
+  for (; i < end; i += stride) a0 += cur[col[i]];
+  return (a0 + a1) + (a2 + a3);
+}
+
 __global__ __launch_bounds__(PR_BT) void pr_iter_kernel(PrArgs A, int32_t it) {
   __shared__ int32_t s_item;
   __shared__ int s_last;
   __shared__ double s_red[PR_BT / FG_WAVE];
+  // short rows of each wave's 64 vertices: exclusive prefix of their
+  // lengths, their first entries, their sums
+  __shared__ int32_t s_sc[PR_BT / FG_WAVE][FG_WAVE];
+  __shared__ int32_t s_sb[PR_BT / FG_WAVE][FG_WAVE];
+  __shared__ double s_acc[PR_BT / FG_WAVE][FG_WAVE];
   PrCtl* C = A.ctl;
   if (C->done) return;
   const int par = it & 1;
@@ -124,8 +168,7 @@ __global__ __launch_bounds__(PR_BT) void pr_iter_kernel(PrArgs A, int32_t it) {
       // one long row, the whole workgroup
       const int32_t v = A.longrows[item];
       const int32_t b = A.off[v], e = A.off[v + 1];
-      double acc = 0.0;
-      for (int32_t i = b + threadIdx.x; i < e; i += PR_BT) acc += cur[A.col[i]];
+      double acc = strided_gather_sum(cur, A.col, b + (int32_t)threadIdx.x, e, PR_BT);
       acc = wave_sum_f64(acc);
       if (lane == 0) s_red[wid] = acc;
       __syncthreads();
@@ -144,11 +187,46 @@ __global__ __launch_bounds__(PR_BT) void pr_iter_kernel(PrArgs A, int32_t it) {
       b = A.off[v];
       deg = A.off[v + 1] - b;
     }
-    if (deg < FG_WAVE) {
-      // short rows: one lane, in CSR order
-      double acc = 0.0;
-      for (int32_t i = 0; i < deg; ++i) acc += cur[A.col[b + i]];
-      if (v64 < A.n) nc += pr_update(A, nxt, v, deg, acc);
+    {
+      // short rows: the wave's rows laid end to end and taken 64 entries
+      // per step, one per lane (all the contribution loads of a step in
+      // flight together); a step's lanes of one row (adjacent) are summed
+      // by a segmented scan and its last lane adds the part to the row's
+      // sum, so every row is summed in a fixed order
+      const int32_t ds = (v64 < A.n && deg < FG_WAVE) ? deg : 0;
+      const int32_t incl = fg_wave_incl_scan(ds);
+      const int32_t T = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
+      int32_t* sc = s_sc[wid];
+      int32_t* sb = s_sb[wid];
+      double* sacc = s_acc[wid];
+      sc[lane] = incl - ds;
+      sb[lane] = b;
+      sacc[lane] = 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int32_t t0 = 0; t0 < T; t0 += FG_WAVE) {
+        const int32_t t = t0 + lane;
+        double x = 0.0;
+        int32_t key = -1 - lane;  // lanes past the end: runs of their own
+        if (t < T) {
+          const int32_t j = fgk::upper_idx(sc, FG_WAVE, t);
+          // t - sc[j] < the length of row j: the entry lies inside its row
+          x = cur[A.col[sb[j] + (t - sc[j])]];
+          key = j;
+        }
+        const int32_t kp = __shfl_up(key, 1, FG_WAVE);
+        const int32_t kn = __shfl_down(key, 1, FG_WAVE);
+        const bool head = lane == 0 || kp != key;
+        const bool tail = lane == FG_WAVE - 1 || kn != key;
+        const uint64_t H = __ballot(head);
+        const uint64_t upto = lane == FG_WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
+        const int start = 63 - __builtin_clzll(H & upto);
+        x = seg_incl_sum(x, lane, start);
+        if (tail && key >= 0) sacc[key] += x;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (v64 < A.n && deg < FG_WAVE) nc += pr_update(A, nxt, v, deg, sacc[lane]);
     }
     // medium rows: one at a time, the whole wave across the row
     uint64_t med = __ballot(deg >= FG_WAVE && deg < PR_LONG);
@@ -158,7 +236,7 @@ __global__ __launch_bounds__(PR_BT) void pr_iter_kernel(PrArgs A, int32_t it) {
       const int32_t ub = __shfl(b, l, FG_WAVE);
       const int32_t ud = __shfl(deg, l, FG_WAVE);
       double acc = 0.0;
-      for (int32_t i = lane; i < ud; i += FG_WAVE) acc += cur[A.col[ub + i]];
+      acc = strided_gather_sum(cur, A.col, ub + lane, ub + ud, FG_WAVE);
       acc = wave_sum_f64(acc);
       if (lane == l) nc += pr_update(A, nxt, v, ud, acc);
     }

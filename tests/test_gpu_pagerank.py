@@ -2,9 +2,9 @@
 iteration (O13), through the C ABI.
 
 Tolerance.  Both sides evaluate the same formula in IEEE double; they
-differ only in the order of the additions of a row's sum (a lane sums a
-short row in CSR order as the oracle does; a wave or a workgroup sums
-longer rows as a tree).  Summing k positive terms in any order is within
+differ only in the order of the additions of a row's sum (the kernel sums
+short rows in segments of a wave step, longer rows in strided partial sums
+combined as a tree; the oracle in CSR order).  Summing k positive terms in any order is within
 gamma_{k-1} = (k-1)u / (1 - (k-1)u) of the exact sum (u = 2^-53), and the
 contributions, the update and the division add a few roundings more, so
 after K iterations every rank agrees to the relative error
