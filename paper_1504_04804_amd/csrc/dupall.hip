@@ -287,14 +287,27 @@ __global__ __launch_bounds__(DUP_BT) void dup_step_kernel(DupArgs A) {
         bool found = false;
         int32_t pu = -1;
         if ((cand >> lane) & 1ull) {
+          // four entries per step, their column and visited-word loads in
+          // flight together (a row is otherwise a chain of dependent
+          // loads); the entries read still stop at the first hit
           const int32_t e = A.off[v + 1];
-          for (int32_t i = A.off[v]; i < e; ++i) {
-            const int32_t u = A.col[i];
-            insp++;
-            if ((A.visited[u >> 6] >> (u & 63)) & 1ull) {
+          for (int32_t i0 = A.off[v]; i0 < e && !found; i0 += 4) {
+            int32_t u[4];
+            uint64_t wv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k] = A.col[i0 + k < e ? i0 + k : e - 1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) wv[k] = A.visited[u[k] >> 6];
+            int32_t h = -1;
+#pragma unroll
+            for (int k = 3; k >= 0; --k)
+              if (i0 + k < e && ((wv[k] >> (u[k] & 63)) & 1ull)) h = k;
+            if (h >= 0) {
               found = true;
-              pu = u;
-              break;
+              pu = u[h];
+              insp += h + 1;
+            } else {
+              insp += e - i0 < 4 ? e - i0 : 4;
             }
           }
         }
