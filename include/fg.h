@@ -229,6 +229,32 @@ fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
                       int32_t* parent, int64_t out_stride, fg_run_stats* stats, void* stream);
 
 /*
+ * Two BFS workloads in one launch, side by side on disjoint workgroups, for
+ * callers that hold both at once (a step with a list of low-diameter
+ * queries and one high-diameter query): the list `srcs` on g exactly as
+ * fg_bfs_many (arguments, outputs, records and errors as there), and one
+ * push query from src2 on g2 exactly as fg_bfs with opts2, which must be
+ * FG_MODE_PUSH with async_levels > 1 (else FG_EINVAL).  The second query's
+ * asynchronous team (opts2->team_blocks workgroups) takes the launch's
+ * last workgroups and the list runs on the others; neither waits for the
+ * other.  If the team gives up (a member's frontier outgrows its LDS room),
+ * the second query runs level-synchronously after the launch, as in
+ * fg_bfs.  ws2: workspace of g2 as for fg_bfs; the two workspaces must not
+ * overlap (FG_EINVAL) and no other call may use either meanwhile; the two
+ * queries' outputs must not overlap.  A team that leaves the list no
+ * workgroup gives FG_EINVAL.  nsrc = 0 runs the second query alone.  Each
+ * traversal is the one its own entry point runs (Alg. 2 and Sec. VI-A for
+ * the list in FG_MODE_DO; the second query's depths as Alg. 1's); running
+ * them side by side is the library's scheduling, not the paper's.
+ */
+fg_status fg_bfs_corun(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
+                       const fg_bfs_opts* opts, void* ws, size_t ws_bytes, int32_t* depth,
+                       int32_t* parent, int64_t out_stride, fg_run_stats* stats,
+                       const fg_graph* g2, int32_t src2, const fg_bfs_opts* opts2, void* ws2,
+                       size_t ws2_bytes, int32_t* depth2, int32_t* parent2,
+                       fg_run_stats* stats2, void* stream);
+
+/*
  * fg_bfs without allocations, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same search, arguments, outputs and errors as fg_bfs

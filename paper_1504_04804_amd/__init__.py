@@ -179,6 +179,8 @@ SIGNATURES = {
     "fg_bfs_opts_default": (None, [ctypes.POINTER(BfsOpts)]),
     "fg_bfs": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_bfs_many": (_I32, [_P, _P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _I64, _P, _P]),
+    "fg_bfs_corun": (_I32, [_P, _P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _I64, _P,
+                             _P, _I32, ctypes.POINTER(BfsOpts), _P, _SZ, _P, _P, _P, _P]),
     "fg_bfs_noalloc": (_I32, [_P, _I32, ctypes.POINTER(BfsOpts), _P, _P, _P, _P]),
     "fg_sssp_opts_default": (None, [ctypes.POINTER(SsspOpts)]),
     "fg_sssp": (_I32, [_P, _I32, ctypes.POINTER(SsspOpts), _P, _SZ, _P, _P, _P, _P]),
@@ -374,6 +376,20 @@ def bfs_many_into(g, srcs, depth, parent=None, opts=None, ws=None, stats=None, o
                              ctypes.byref(opts) if opts is not None else None, _ptr(ws),
                              ws.numel(), _ptr(depth), _ptr(parent), int(out_stride), _ptr(stats),
                              _stream(stream)))
+
+
+def bfs_corun_into(g, srcs, depth, parent, opts, ws, stats, g2, src2, depth2, parent2, opts2,
+                   ws2=None, stats2=None, out_stride=0, stream=None):
+    """Enqueue fg_bfs_corun: the sources of `srcs` on g one after another (as
+    bfs_many_into) and, beside them in the same launch, the asynchronous
+    push query from src2 on g2 (opts2: push mode, async_levels > 1)."""
+    ws = ws if ws is not None else g.workspace(FG_PRIM_BFS)
+    ws2 = ws2 if ws2 is not None else g2.workspace(FG_PRIM_BFS)
+    _check(lib().fg_bfs_corun(g.handle, _ptr(srcs), int(srcs.numel()),
+                              ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                              ws.numel(), _ptr(depth), _ptr(parent), int(out_stride), _ptr(stats),
+                              g2.handle, int(src2), ctypes.byref(opts2), _ptr(ws2), ws2.numel(),
+                              _ptr(depth2), _ptr(parent2), _ptr(stats2), _stream(stream)))
 
 
 def new_stats_many(k, device="cuda"):

@@ -156,7 +156,19 @@ struct BfsParams {
   // the asynchronous traversal ran out of queue room
   int32_t async_k;
   int32_t async_fallback;
+  // the traversal's workgroups: [blk0, blk0 + nblk) of the launch (a launch
+  // may run two traversals side by side on disjoint ranges).  The
+  // level-synchronous kernel always starts at workgroup 0 (blk0 = 0: its
+  // code indexes workgroups by blockIdx.x, which costs no register); only an
+  // asynchronous team takes an offset.
+  uint32_t blk0;
+  uint32_t nblk;
 };
+
+// Workgroups of the traversal.
+__device__ __forceinline__ uint32_t fgb_n(const BfsParams& P) { return P.nblk; }
+// An asynchronous team member's index.
+__device__ __forceinline__ uint32_t as_member(const BfsParams& P) { return blockIdx.x - P.blk0; }
 
 // What changes from one traversal of a launch to the next: the source and
 // the traversal's index, from which its outputs and record follow (kept as
@@ -580,8 +592,8 @@ __device__ void push_tiny(const BfsParams& P, const BfsJob& J, const St& S, Lds&
   // work items are dealt wave-major over the workgroups (item i to
   // workgroup i mod G): a level with few items spreads them over as many
   // CUs instead of filling the first workgroups' waves
-  const int64_t gw = (int64_t)wid * gridDim.x + blockIdx.x;
-  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  const int64_t gw = (int64_t)wid * fgb_n(P) + blockIdx.x;
+  const int64_t W = (int64_t)fgb_n(P) * PWAVES;
   static_assert(CH == 4 * FG_WAVE, "one visit4 per chunk");
   for (int64_t c = gw; c < NC; c += W) {
     // the last vertex whose first chunk is at or before c (vertices without
@@ -752,7 +764,7 @@ __device__ void pull_phase(const BfsParams& P, const BfsJob& J, const St& S, Lds
   const int lane = fg_lane();
   const int wid = threadIdx.x / FG_WAVE;
   const int64_t gw = (int64_t)blockIdx.x * PWAVES + wid;
-  const int64_t W = (int64_t)gridDim.x * PWAVES;
+  const int64_t W = (int64_t)fgb_n(P) * PWAVES;
   const uint64_t* Vin = P.vis[S.cur];
   uint64_t* Vout = P.vis[S.cur ^ 1];
   const int32_t d_new = S.k + 1;
@@ -873,7 +885,7 @@ __device__ void bitmap_diff_to_queue(const BfsParams& P, const St& S, Lds& L) {
   const uint64_t* Vnew = P.vis[S.cur];
   const uint64_t* Vold = P.vis[S.cur ^ 1];
   int32_t* Q = P.q[S.qsel];
-  const int64_t per = ((P.nwords + gridDim.x - 1) / gridDim.x + FG_WAVE - 1) / FG_WAVE * FG_WAVE;
+  const int64_t per = ((P.nwords + fgb_n(P) - 1) / fgb_n(P) + FG_WAVE - 1) / FG_WAVE * FG_WAVE;
   const int64_t wb = (int64_t)blockIdx.x * per;
   const int64_t we = wb + per < P.nwords ? wb + per : P.nwords;
   for (int64_t c0 = wb; c0 < we; c0 += PWAVES * FG_WAVE) {
@@ -1331,9 +1343,8 @@ __device__ bool lds_mode(const BfsParams& P, const BfsJob& J, St& S, Lds& L, uin
 
 // MODE is FG_MODE_DO or FG_MODE_PUSH (one kernel per mode).
 template <int MODE, bool MULTI>
-__global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
-  __shared__ Lds L;
-  fg_grid_sync gs{P.ctl->bar, gridDim.x, 0u};
+__device__ __forceinline__ void bfs_persistent_run(const BfsParams& P, Lds& L) {
+  fg_grid_sync gs{P.ctl->bar, fgb_n(P), 0u};
   bool ok = true;
   // one traversal, or (MULTI, a build of its own: the loop around the
   // traversal raises the register pressure) P.nsrc traversals in turn
@@ -1363,7 +1374,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       {
         uint32_t* w = (uint32_t*)P.ctl;
         for (int i = FG_BAR_WORDS + (int)(blockIdx.x * PB + threadIdx.x); i < (int)(sizeof(BfsCtl) / 4);
-             i += (int)(gridDim.x * PB))
+             i += (int)(fgb_n(P) * PB))
           w[i] = 0u;
       }
     }
@@ -1394,7 +1405,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   // a1: depth = parent = -1 except at the source, visited = {src}, Q = {src}
   {
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * PB;
+    const int64_t nth = (int64_t)fgb_n(P) * PB;
     const int32_t src = J.src;
     if (blockIdx.x == 0 && J_stats(P, J)) {
       uint32_t* sw = (uint32_t*)J_stats(P, J);
@@ -1488,7 +1499,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
             c->pub_b[6] = S.b1insp;
             c->pub_b[7] = S.b1deg;
             __hip_atomic_fetch_add(&c->sm_signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            ack_need += gridDim.x - (small_ep ? 1u : (uint32_t)P.team);
+            ack_need += fgb_n(P) - (small_ep ? 1u : (uint32_t)P.team);
           }
         }
         __syncthreads();
@@ -1550,12 +1561,12 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       S.qsel ^= 1;
     } else if (MODE != FG_MODE_DO || S.dir == DIR_PUSH) {
-      push_phase_a(P, J, S, L, gridDim.x);
+      push_phase_a(P, J, S, L, fgb_n(P));
       if (!(ok = gs.sync_acquire(&L.flag))) break;
       const ull dt = fg_atomic_load_u64(&C.desc.v);
       const int64_t ndesc = (int64_t)(dt - B.desc);
       if (ndesc > 0) {
-        push_phase_b(P, J, S, ndesc, L, gridDim.x);
+        push_phase_b(P, J, S, ndesc, L, fgb_n(P));
         if (!(ok = gs.sync_acquire(&L.flag))) break;
       }
       B.desc = dt;
@@ -1594,7 +1605,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     __syncthreads();
     const uint64_t* fin = P.vis[S.cur];
     const int64_t tid = (int64_t)blockIdx.x * PB + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * PB;
+    const int64_t nth = (int64_t)fgb_n(P) * PB;
     for (int64_t w = tid; w < P.nwords; w += nth) {
       const uint64_t now = fin[w];
       if (incremental) {
@@ -1622,7 +1633,7 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
     st->reached = S.p;
     st->edges_inspected = S.insp_sum;
     st->direction_switches = S.switches;
-    st->grid_blocks = (int32_t)gridDim.x;
+    st->grid_blocks = (int32_t)fgb_n(P);
   }
   }  // jobs
   // the last workgroup out clears the control block for the next launch
@@ -1630,13 +1641,19 @@ __global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
   if (threadIdx.x == 0) {
     const uint32_t done = __hip_atomic_fetch_add(&P.ctl->exit_count, 1u, __ATOMIC_ACQ_REL,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    L.flag = done == gridDim.x - 1;
+    L.flag = done == fgb_n(P) - 1;
   }
   __syncthreads();
   if (L.flag) {
     uint32_t* w = (uint32_t*)P.ctl;
     for (int i = threadIdx.x; i < (int)(sizeof(BfsCtl) / 4); i += PB) w[i] = 0u;
   }
+}
+
+template <int MODE, bool MULTI>
+__global__ __launch_bounds__(PB) void bfs_persistent(BfsParams P) {
+  __shared__ Lds L;
+  bfs_persistent_run<MODE, MULTI>(P, L);
 }
 
 // ---- asynchronous push mode (high-diameter graphs) ----------------------
@@ -1709,11 +1726,10 @@ __device__ __forceinline__ void as_put(AsLds& L, int nxt, int par, bool won, int
   }
 }
 
-__global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
-  __shared__ AsLds L;
+__device__ __forceinline__ void bfs_async_run(const BfsParams& P, AsLds& L) {
   const int tid = threadIdx.x;
   const int lane = fg_lane();
-  const uint32_t T = gridDim.x;
+  const uint32_t T = fgb_n(P);
   BfsCtl* C = P.ctl;
   uint32_t* abort_flag = C->bar + FG_BAR_STRIDE;
   TeamSync ts{&C->as_arrive, abort_flag, T, 0u};
@@ -1722,12 +1738,12 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
   const int32_t K = P.async_k;
   int64_t insp = 0;
   if (tid == 0) {
-    L.cnt[0] = blockIdx.x == 0 ? 1 : 0;
+    L.cnt[0] = as_member(P) == 0 ? 1 : 0;
     L.cnt[1] = 0;
     L.ovf[0] = L.ovf[1] = 0;
     L.big[0] = L.big[1] = 0;
     L.stop = 0;
-    if (blockIdx.x == 0) {
+    if (as_member(P) == 0) {
       L.qv[0][0] = P.src;
       L.qb[0][0] = P.off[P.src];
       L.qe[0][0] = P.off[P.src + 1];
@@ -1745,7 +1761,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
   const uint32_t max_steps = (uint32_t)(P.n / K) + 2;
   for (uint32_t step = 0; ok; ++step) {
     if (step > max_steps) {
-      if (blockIdx.x == 0 && tid == 0)
+      if (as_member(P) == 0 && tid == 0)
         __hip_atomic_store(&C->as_state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
@@ -1847,7 +1863,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
     // exchange: queue lengths (and an overflow) to the team
     if (tid == 0) {
       const int32_t c = L.cnt[cur] < AQ ? L.cnt[cur] : AQ;
-      fg_st_shared(&C->as_rec[blockIdx.x], ((ull)(overflow ? 1 : 0) << 63) | (ull)(uint32_t)c);
+      fg_st_shared(&C->as_rec[as_member(P)], ((ull)(overflow ? 1 : 0) << 63) | (ull)(uint32_t)c);
     }
     if (!ts.sync_acquire(&L.flag)) {
       ok = false;
@@ -1861,7 +1877,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
       const int32_t o = (int32_t)(r >> 63);
       const int32_t incl = fg_wave_incl_scan(c);
       const int32_t tot = __builtin_amdgcn_readlane(incl, FG_WAVE - 1);
-      const int32_t pre = __builtin_amdgcn_readlane(incl - c, blockIdx.x);
+      const int32_t pre = __builtin_amdgcn_readlane(incl - c, as_member(P));
       const int32_t anyo = fg_wave_sum(o);
       if (tid == 0) {
         L.tot = tot;
@@ -1873,7 +1889,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
     }
     __syncthreads();
     if (L.stop) {
-      if (L.stop == 2 && blockIdx.x == 0 && tid == 0)
+      if (L.stop == 2 && as_member(P) == 0 && tid == 0)
         __hip_atomic_store(&C->as_state, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
@@ -1887,7 +1903,7 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
       break;
     }
     const int64_t tot = L.tot;
-    const int32_t lo = (int32_t)(tot * blockIdx.x / T), hi = (int32_t)(tot * (blockIdx.x + 1) / T);
+    const int32_t lo = (int32_t)(tot * as_member(P) / T), hi = (int32_t)(tot * (as_member(P) + 1) / T);
     for (int32_t i = tid; i < hi - lo; i += PB) {
       const int32_t v = G[lo + i];
       L.qv[cur][i] = v;
@@ -1912,6 +1928,29 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
       for (uint32_t i = 0; i < T; ++i) C->as_rec[i] = 0;
     }
   }
+}
+
+__global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
+  __shared__ AsLds L;
+  bfs_async_run(P, L);
+}
+
+// Two traversals side by side in one launch (fg_bfs_corun): workgroups
+// [0, A.nblk) run A's list of sources as bfs_persistent does, the rest run
+// B's asynchronous push traversal as bfs_async does.  Neither waits for the
+// other; each synchronises only its own range.
+union CorunLds {
+  Lds a;
+  AsLds b;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(PB) void bfs_corun(BfsParams A, BfsParams B) {
+  __shared__ CorunLds L;
+  if (blockIdx.x < A.nblk)
+    bfs_persistent_run<MODE, true>(A, L.a);
+  else
+    bfs_async_run(B, L.b);
 }
 
 // Start of an asynchronous traversal: every key "unreached" but the
@@ -2144,22 +2183,22 @@ static fg_status bfs_check(const char* fn, const fg_graph* g, int32_t src, const
   return FG_OK;
 }
 
-// One persistent launch of the fused BFS kernel over the workspace `lay`
-// (whose control block is zero).
-static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o,
-                            const BfsLayout& lay, int32_t* depth, int32_t* parent,
-                            fg_run_stats* stats, hipStream_t s, const int32_t* srcs = nullptr,
-                            int32_t nsrc = 0, int64_t out_stride = 0) {
-  int dev = 0;
-  FG_HIP_TRY(hipGetDevice(&dev));
-  fg_device_props pr = fg_props(dev);
-  if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_bfs: device lacks cooperative launch");
-  int bpc = o.mode == FG_MODE_DO ? persistent_blocks_per_cu<FG_MODE_DO>(dev)
-                                 : persistent_blocks_per_cu<FG_MODE_PUSH>(dev);
+// Width of the persistent launch: workgroups per CU as occupancy allows (at
+// most 2 by default; blocks_per_cu lowers it) times the CUs.
+static int persistent_grid(const fg_bfs_opts& o, const fg_device_props& pr, int occ) {
+  int bpc = occ;
   if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
   if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
-  const int grid = pr.cus * bpc;
+  return pr.cus * bpc;
+}
 
+// Kernel parameters of one traversal (src) or of a list (srcs, nsrc) over
+// the workspace `lay` (whose control block is zero), run by workgroups
+// [0, nblk) of their launch.
+static BfsParams bfs_params(const fg_graph* g, int32_t src, const fg_bfs_opts& o,
+                            const BfsLayout& lay, int32_t* depth, int32_t* parent,
+                            fg_run_stats* stats, const fg_device_props& pr, int nblk,
+                            const int32_t* srcs, int32_t nsrc, int64_t out_stride) {
   BfsParams P;
   memset(&P, 0, sizeof(P));
   P.off = g->off;
@@ -2191,34 +2230,79 @@ static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o
   P.big_deg = o.big_degree > 0 ? o.big_degree : DEF_BIG_DEG;
   P.clock_khz = pr.clock_khz;
   P.team = o.team_blocks > 0 ? o.team_blocks : (o.team_blocks < 0 ? 0 : DEF_TEAM);
-  if (P.team > grid) P.team = grid;
+  if (P.team > nblk) P.team = nblk;
   if (P.team > TEAM_MAX) P.team = TEAM_MAX;
   P.team_e = o.team_edges > 0 ? o.team_edges : DEF_TEAM_E;
   // team decisions are exact below the word's degree cap
   if (P.team_e > TW_CAP - 1) P.team_e = TW_CAP - 1;
   if (P.small_e > TW_CAP - 1) P.small_e = TW_CAP - 1;
-
   P.srcs = srcs;
   P.nsrc = nsrc;
   P.out_stride = out_stride;
+  P.async_k = o.async_levels > 1024 ? 1024 : o.async_levels;
+  P.blk0 = 0;
+  P.nblk = (uint32_t)nblk;
+  return P;
+}
+
+// Workgroups of an asynchronous team.
+static int async_team(const fg_bfs_opts& o, const fg_device_props& pr) {
+  int T = o.team_blocks > 0 ? o.team_blocks : DEF_TEAM;
+  if (T > pr.cus) T = pr.cus;
+  if (T > TEAM_MAX) T = TEAM_MAX;
+  if (T < 1) T = 1;
+  return T;
+}
+
+// Workgroups of the per-vertex kernels around an asynchronous traversal.
+static int async_fill_blocks(const fg_graph* g) {
+  int fb = (int)((g->n + 4095) / 4096);
+  if (fb > 2048) fb = 2048;
+  if (fb < 1) fb = 1;
+  return fb;
+}
+
+// The level-synchronous launch queued behind an asynchronous traversal: it
+// runs only if the team gave up.
+static fg_status async_fallback_launch(BfsParams P, int grid, hipStream_t s) {
+  P.async_fallback = 1;
+  P.blk0 = 0;
+  P.nblk = (uint32_t)grid;
+  if (P.team > grid) P.team = grid;
+  void* args[] = {&P};
+  FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_persistent<FG_MODE_PUSH, false>,
+                                        dim3(grid), dim3(PB), args, 0, s));
+  return FG_OK;
+}
+
+// One persistent launch of the fused BFS kernel over the workspace `lay`
+// (whose control block is zero).
+static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o,
+                            const BfsLayout& lay, int32_t* depth, int32_t* parent,
+                            fg_run_stats* stats, hipStream_t s, const int32_t* srcs = nullptr,
+                            int32_t nsrc = 0, int64_t out_stride = 0) {
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  fg_device_props pr = fg_props(dev);
+  if (!pr.coop) return fg_set_error(FG_EUNSUPPORTED, "fg_bfs: device lacks cooperative launch");
+  const int grid = persistent_grid(o, pr, o.mode == FG_MODE_DO
+                                              ? persistent_blocks_per_cu<FG_MODE_DO>(dev)
+                                              : persistent_blocks_per_cu<FG_MODE_PUSH>(dev));
+  BfsParams P = bfs_params(g, src, o, lay, depth, parent, stats, pr, grid, srcs, nsrc, out_stride);
 
   if (o.mode == FG_MODE_PUSH && o.async_levels > 1 && !srcs) {
     // asynchronous push: keys, the team's launch, outputs and record, and
     // the level-synchronous launch that runs only if the team gave up
-    P.async_k = o.async_levels > 1024 ? 1024 : o.async_levels;
-    int T = o.team_blocks > 0 ? o.team_blocks : DEF_TEAM;
-    if (T > pr.cus) T = pr.cus;
-    if (T > TEAM_MAX) T = TEAM_MAX;
-    if (T < 1) T = 1;
-    int fb = (int)((g->n + 4095) / 4096);
-    if (fb > 2048) fb = 2048;
-    if (fb < 1) fb = 1;
-    async_init_kernel<<<fb, 256, 0, s>>>(P);
-    void* aargs[] = {&P};
+    const int T = async_team(o, pr);
+    const int fb = async_fill_blocks(g);
+    BfsParams PA = P;
+    PA.nblk = (uint32_t)T;
+    async_init_kernel<<<fb, 256, 0, s>>>(PA);
+    void* aargs[] = {&PA};
     FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_async, dim3(T), dim3(PB), aargs, 0, s));
-    async_finalize_kernel<<<fb, 256, 0, s>>>(P);
-    async_stats_kernel<<<1, 64, 0, s>>>(P, T);
-    P.async_fallback = 1;
+    async_finalize_kernel<<<fb, 256, 0, s>>>(PA);
+    async_stats_kernel<<<1, 64, 0, s>>>(PA, T);
+    return async_fallback_launch(P, grid, s);
   }
 
   void* args[] = {&P};
@@ -2275,6 +2359,101 @@ extern "C" fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t
                         lay.bytes);
   return bfs_launch(g, 0, o, lay, depth, parent, stats, (hipStream_t)stream, srcs, nsrc,
                     out_stride);
+}
+
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+static int g_corun_occupancy[2][64];
+
+template <int MODE>
+int corun_blocks_per_cu(int device) {
+  if (device < 0 || device >= 64) return 1;
+  int& occ = g_corun_occupancy[MODE == FG_MODE_DO ? 0 : 1][device];
+  if (occ == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bfs_corun<MODE>, PB, 0) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    occ = nb;
+  }
+  return occ;
+}
+
+extern "C" fg_status fg_bfs_corun(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
+                                  const fg_bfs_opts* opts, void* ws, size_t ws_bytes,
+                                  int32_t* depth, int32_t* parent, int64_t out_stride,
+                                  fg_run_stats* stats, const fg_graph* g2, int32_t src2,
+                                  const fg_bfs_opts* opts2, void* ws2, size_t ws2_bytes,
+                                  int32_t* depth2, int32_t* parent2, fg_run_stats* stats2,
+                                  void* stream) {
+  const hipStream_t s = (hipStream_t)stream;
+  // the asynchronous query
+  fg_bfs_opts o2;
+  fg_status rc = bfs_check("fg_bfs_corun", g2, src2, opts2, depth2, &o2);
+  if (rc != FG_OK) return rc;
+  if (o2.mode != FG_MODE_PUSH || o2.async_levels <= 1)
+    return fg_set_error(FG_EINVAL,
+                        "fg_bfs_corun: the second query needs FG_MODE_PUSH with async_levels > 1");
+  if (!ws2) return fg_set_error(FG_EINVAL, "fg_bfs_corun: second workspace is NULL");
+  FG_CHECK_WS_ALIGN(ws2, "fg_bfs_corun");
+  const BfsLayout lay2 = bfs_layout(g2, ws2);
+  if (ws2_bytes < lay2.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_bfs_corun: second workspace of %zu bytes < required %zu",
+                        ws2_bytes, lay2.bytes);
+  // the list
+  if (!g) return fg_set_error(FG_EINVAL, "fg_bfs_corun: graph is NULL");
+  if (nsrc < 0) return fg_set_error(FG_EINVAL, "fg_bfs_corun: nsrc=%d < 0", nsrc);
+  if (nsrc > 0 && !srcs) return fg_set_error(FG_EINVAL, "fg_bfs_corun: srcs is NULL");
+  if (out_stride != 0 && out_stride < g->n)
+    return fg_set_error(FG_EINVAL, "fg_bfs_corun: out_stride=%lld is neither 0 nor >= n=%d",
+                        (long long)out_stride, g->n);
+  fg_bfs_opts o;
+  rc = bfs_check("fg_bfs_corun", g, 0, opts, depth, &o);
+  if (rc != FG_OK) return rc;
+  if (o.mode == FG_MODE_PUSH_UNFUSED)
+    return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_corun: the unfused mode runs one source per call");
+  if (!ws) return fg_set_error(FG_EINVAL, "fg_bfs_corun: workspace is NULL");
+  FG_CHECK_WS_ALIGN(ws, "fg_bfs_corun");
+  const BfsLayout lay = bfs_layout(g, ws);
+  if (ws_bytes < lay.bytes)
+    return fg_set_error(FG_ENOMEM, "fg_bfs_corun: workspace of %zu bytes < required %zu", ws_bytes,
+                        lay.bytes);
+  if (ranges_overlap(ws, lay.bytes, ws2, lay2.bytes))
+    return fg_set_error(FG_EINVAL, "fg_bfs_corun: the two workspaces overlap");
+  if (nsrc == 0) return bfs_launch(g2, src2, o2, lay2, depth2, parent2, stats2, s);
+
+  int dev = 0;
+  FG_HIP_TRY(hipGetDevice(&dev));
+  fg_device_props pr = fg_props(dev);
+  if (!pr.coop)
+    return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_corun: device lacks cooperative launch");
+  const int grid = persistent_grid(o, pr, o.mode == FG_MODE_DO ? corun_blocks_per_cu<FG_MODE_DO>(dev)
+                                                               : corun_blocks_per_cu<FG_MODE_PUSH>(dev));
+  const int T = async_team(o2, pr);
+  if (grid - T < 1)
+    return fg_set_error(FG_EINVAL,
+                        "fg_bfs_corun: a team of %d workgroups leaves none of %d for the list", T,
+                        grid);
+  // the list on workgroups [0, grid - T), the team on the last T
+  BfsParams PA = bfs_params(g, 0, o, lay, depth, parent, stats, pr, grid - T, srcs, nsrc,
+                            out_stride);
+  BfsParams PB2 = bfs_params(g2, src2, o2, lay2, depth2, parent2, stats2, pr, T, nullptr, 0, 0);
+  PB2.blk0 = (uint32_t)(grid - T);
+  const int fb = async_fill_blocks(g2);
+  async_init_kernel<<<fb, 256, 0, s>>>(PB2);
+  void* args[] = {&PA, &PB2};
+  const void* fn = o.mode == FG_MODE_DO ? (const void*)bfs_corun<FG_MODE_DO>
+                                        : (const void*)bfs_corun<FG_MODE_PUSH>;
+  FG_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PB), args, 0, s));
+  async_finalize_kernel<<<fb, 256, 0, s>>>(PB2);
+  async_stats_kernel<<<1, 64, 0, s>>>(PB2, T);
+  // if the team gave up, the second query runs level-synchronously
+  const int grid2 = persistent_grid(o2, pr, persistent_blocks_per_cu<FG_MODE_PUSH>(dev));
+  BfsParams PF = bfs_params(g2, src2, o2, lay2, depth2, parent2, stats2, pr, grid2, nullptr, 0, 0);
+  return async_fallback_launch(PF, grid2, s);
 }
 
 // ------------------------------------------------ BFS without allocations
