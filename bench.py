@@ -1033,25 +1033,54 @@ def main():
     m_grid = int(gdeg[gdepth >= 0].sum().item())
     edges_step = sum(m_comp) + m_grid
 
-    def events():
-        return [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(2)]
+    def pair():
+        return (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
 
-    def step(ev):
-        # the 64 sources one after another in one launch (fg_bfs_many), then
-        # the grid
+    def run_many(ev=None):
         if ev:
-            ev[0][0].record(stream)
+            ev[0].record(stream)
         fg.bfs_many_into(g, srcs_dev, depth, parent, o_do, ws=ws, stats=mstats, stream=stream)
         if ev:
-            ev[0][1].record(stream)
-            ev[1][0].record(stream)
+            ev[1].record(stream)
+
+    def run_grid(ev=None):
+        if ev:
+            ev[0].record(stream)
         fg.bfs_into(gg, 0, gdepth, gparent, o_push, ws=gws, stats=stats[NSRC], stream=stream)
         if ev:
-            ev[1][1].record(stream)
+            ev[1].record(stream)
+
+    def step(ev=None):
+        # the 64 sources one after another and, beside them in the same
+        # launch, the grid query on its own team of workgroups (fg_bfs_corun)
+        if ev:
+            ev[0].record(stream)
+        fg.bfs_corun_into(g, srcs_dev, depth, parent, o_do, ws, mstats, gg, 0, gdepth, gparent,
+                          o_push, ws2=gws, stats2=stats[NSRC], stream=stream)
+        if ev:
+            ev[1].record(stream)
+
+    # each part alone, and the two in sequence on one stream, outside the
+    # timed region (the per-workload figures and the sequential step)
+    alone = {"many": [], "grid": [], "seq": []}
+    for rep in range(4):
+        e_m, e_g, e_s = pair(), pair(), pair()
+        run_many(e_m)
+        run_grid(e_g)
+        e_s[0].record(stream)
+        run_many()
+        run_grid()
+        e_s[1].record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            for k, e in (("many", e_m), ("grid", e_g), ("seq", e_s)):
+                alone[k].append(e[0].elapsed_time(e[1]))
+    recs_alone = fg.read_stats_many(mstats, NSRC)
+    stg_alone = fg.read_stats(stats[NSRC])
 
     for _ in range(args.warmup):
-        step(None)
-    step_events = [events() for _ in range(args.steps)]
+        step()
+    step_events = [pair() for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -1062,25 +1091,27 @@ def main():
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / args.steps
-    lat_many = [ev[0][0].elapsed_time(ev[0][1]) for ev in step_events]
-    lat_grid = [ev[1][0].elapsed_time(ev[1][1]) for ev in step_events]
-    bytes_do, bytes_grid = [], []
+    lat_step = [e[0].elapsed_time(e[1]) for e in step_events]
     status_bad = 0
 
-    # statistics of the last step (same sources every step): per-source
-    # spans on the device clock, from one traversal's last level to the
-    # next one's (the next source's init included)
+    # records of the last timed step (same sources every step)
     recs = fg.read_stats_many(mstats, NSRC)
-    ends = []
-    for st in recs:
-        status_bad += st.status != 0
-        bytes_do.append(bfs_alg_bytes(st, n, (n + 63) // 64, nnz))
-        ends.append(st.t_end[min(st.iterations, 64) - 1])
-    khz = recs[0].clock_khz
-    lat_do = [(ends[j] - ends[j - 1]) / khz for j in range(1, NSRC)]
     stg = fg.read_stats(stats[NSRC])
-    status_bad += stg.status != 0
-    bytes_grid.append(bfs_alg_bytes(stg, ng, (ng + 63) // 64, gg.info().nonzero_degree))
+    status_bad += sum(st.status != 0 for st in recs) + (stg.status != 0)
+    bytes_do = [bfs_alg_bytes(st, n, (n + 63) // 64, nnz) for st in recs]
+    grid_bytes = float(bfs_alg_bytes(stg, ng, (ng + 63) // 64, gg.info().nonzero_degree))
+    khz = recs[0].clock_khz
+
+    def last_end(st):
+        return st.t_end[min(st.iterations, 64) - 1]
+
+    # per-source spans on the device clock, from one traversal's last level
+    # to the next one's (the next source's init included), DOBFS alone
+    ends = [last_end(st) for st in recs_alone]
+    lat_do = [(ends[j] - ends[j - 1]) / khz for j in range(1, NSRC)]
+    # spans of the two parts inside the timed step
+    co_list_ms = (last_end(recs[-1]) - recs[0].t_start) / khz
+    co_grid_ms = ((last_end(stg) - stg.t_start) / khz) if stg.iterations else None
 
     # the same 64 sources with one launch each (fg_bfs), outside the step,
     # for comparison
@@ -1094,26 +1125,32 @@ def main():
         torch.cuda.synchronize()
         if rep:
             sep = [a.elapsed_time(b) for a, b in evs]
-    fg.bfs_many_into(g, srcs_dev, depth, parent, o_do, ws=ws, stats=mstats, stream=stream)
+    # leave the step's outputs in place for the oracle check below
+    step()
     torch.cuda.synchronize()
 
+    lat_many = alone["many"]
+    lat_grid = alone["grid"]
     do_ms = float(np.mean(lat_many)) / NSRC
     grid_ms = float(np.mean(lat_grid))
+    seq_ms = float(np.mean(alone["seq"]))
     do_bytes = float(np.mean(bytes_do))
-    grid_bytes = float(np.mean(bytes_grid))
-    # dominant kernel: the one with the larger share of the step
-    # per launch: the multi-source kernel runs all 64 traversals in one
+    grid_name = "bfs_async" if push_kw.get("async_levels", 0) > 1 else "bfs_persistent<PUSH>"
+    # the step is one launch (plus the grid query's per-vertex kernels around
+    # it): the dominant kernel; the two parts alone for comparison
     kernels = {
-        "bfs_persistent<DO,many>": dict(ms=float(np.mean(lat_many)), bytes=do_bytes * NSRC,
-                                        launches=1, traversals=NSRC),
-        ("bfs_async" if push_kw.get("async_levels", 0) > 1 else "bfs_persistent<PUSH>"):
-            dict(ms=grid_ms, bytes=grid_bytes, launches=1),
+        "bfs_corun<DO>": dict(ms=float(np.mean(lat_step)), bytes=do_bytes * NSRC + grid_bytes,
+                              launches=1, traversals=NSRC + 1),
+        "bfs_persistent<DO,many> (alone)": dict(ms=float(np.mean(lat_many)),
+                                                bytes=do_bytes * NSRC, launches=1,
+                                                traversals=NSRC),
+        grid_name + " (alone)": dict(ms=grid_ms, bytes=grid_bytes, launches=1),
     }
     for k in kernels.values():
         k["share_ms"] = k["ms"] * k["launches"]
         k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9
         k["frac"] = k["gbs"] / HBM_PEAK_GBS
-    dom = max(kernels, key=lambda k: kernels[k]["share_ms"])
+    dom = "bfs_corun<DO>"
     dk = kernels[dom]
     traffic = TRAFFIC_BYTES.get(dom) if _sources_sha(TRAFFIC_SOURCES) == TRAFFIC_SHA256 else None
     step_ms = ms_per_step
@@ -1135,6 +1172,8 @@ def main():
         "config": {
             "workload": f"DOBFS rmat{SCALE} ef{EDGE_FACTOR} x{NSRC} sources one at a time + "
                         f"push BFS grid {GRID}x{GRID} from vertex 0",
+            "launch": "fg_bfs_corun: the sources one after another on all but the grid "
+                      "query's team of workgroups, the grid query on that team, in one launch",
             "rmat_n": n, "rmat_m": int(g.m), "grid_n": ng, "grid_m": int(gg.m),
             "do_a": "%d/%d" % do_kw["do_a"], "do_b": "%d/%d" % do_kw["do_b"],
             "dobfs_options": {k: v for k, v in do_kw.items() if k not in ("do_a", "do_b")},
@@ -1151,11 +1190,25 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": round(dk["ms"], 4),
             "alg_bytes_per_launch": round(dk["bytes"]),
+            "note": "one step = one fg_bfs_corun call (events around it: the co-run launch "
+                    "plus the grid query's per-vertex kernels before and after it); bytes = "
+                    "the 64 traversals' + the grid traversal's algorithmic bytes",
+        },
+        "step": {
+            "ms_corun": round(float(np.mean(lat_step)), 4),
+            "ms_sequential": round(seq_ms, 4),
+            "speedup_vs_sequential": round(seq_ms / float(np.mean(lat_step)), 3),
+            "list_span_ms": round(co_list_ms, 4),
+            "grid_span_ms": round(co_grid_ms, 4) if co_grid_ms is not None else None,
+            "list_workgroups": recs[0].grid_blocks,
+            "note": "sequential = fg_bfs_many then fg_bfs on one stream (measured outside the "
+                    "timed region); spans on the device clock inside the last timed step",
         },
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},
         "dobfs": {
-            "launch": "the 64 sources one after another in one launch (fg_bfs_many)",
+            "launch": "the 64 sources one after another in one launch (fg_bfs_many), alone "
+                      "on the GPU, outside the timed step",
             "ms_per_source": round(do_ms, 4),
             "ms_per_launch": round(float(np.mean(lat_many)), 4),
             "gteps_harmonic": round((NSRC - 1) / sum((l * 1e-3) / (mc / 1e9)
@@ -1163,10 +1216,10 @@ def main():
             "ms_p50": round(float(np.percentile(lat_do, 50)), 4),
             "ms_p99": round(float(np.percentile(lat_do, 99)), 4),
             "latency_note": "per source on the device clock, from one traversal's last level "
-                            "to the next one's (sources 2-64 of the last step)",
+                            "to the next one's (sources 2-64 of the launch)",
             "queries_per_s": round(1000.0 / do_ms, 1),
             "bytes_per_traversed_edge": round(do_bytes / (sum(m_comp) / len(m_comp)), 3),
-            "levels": level_table(recs),
+            "levels": level_table(recs_alone),
             "separate_launches": {
                 "ms_mean": round(float(np.mean(sep)), 4),
                 "ms_p50": round(float(np.percentile(sep, 50)), 4),
@@ -1176,8 +1229,9 @@ def main():
         "grid": {
             "ms": round(grid_ms, 3),
             "gteps": round(m_grid / (grid_ms * 1e-3) / 1e9, 3),
-            "levels": stg.iterations,
-            "us_per_level": round(grid_ms * 1e3 / max(stg.iterations, 1), 3),
+            "levels": stg_alone.iterations,
+            "us_per_level": round(grid_ms * 1e3 / max(stg_alone.iterations, 1), 3),
+            "note": "fg_bfs alone on the GPU (events around the call), outside the timed step",
         },
         "device_status_errors": status_bad,
         "timed_region_ms": round(total_ms, 3),
