@@ -115,9 +115,7 @@ struct alignas(256) BfsCtl {
   ull as_rec[TEAM_MAX];        // per member: its queue length (exchange)
   ull as_hist_cnt[FG_TRACE_MAX];  // vertices per depth (first depths)
   ull as_hist_deg[FG_TRACE_MAX];  // ... their degree sums
-  ull as_reached;              // vertices reached
   ull as_insp;                 // CSR entries read by the team
-  uint32_t as_maxd;            // largest depth
 };
 
 struct BfsParams {
@@ -1973,9 +1971,7 @@ __global__ void async_init_kernel(BfsParams P) {
       C->as_arrive = 0;
       C->as_state = 0;
       C->as_exit = 0;
-      C->as_reached = 0;
       C->as_insp = 0;
-      C->as_maxd = 0;
     }
     if (P.stats) {
       uint32_t* sw = (uint32_t*)P.stats;
@@ -1990,8 +1986,16 @@ __global__ void async_init_kernel(BfsParams P) {
 
 // Outputs from the keys: depth = key >> 32, parent = low word (-1 / -1 if
 // unreached), plus the level sizes and their degree sums for the record.
+// Per-workgroup totals of the finalize pass (vertices reached, largest
+// depth), two words per workgroup in the half of the descriptor region the
+// keys leave free (it holds 16 bytes per vertex, the keys 8), summed by the
+// record kernel: no atomics on one address from every wave.
+__device__ __forceinline__ ull* fin_partials(const BfsParams& P) { return (ull*)P.desc + P.n; }
+
 __global__ __launch_bounds__(256) void async_finalize_kernel(BfsParams P) {
   __shared__ ull s_cnt[FG_TRACE_MAX], s_deg[FG_TRACE_MAX];
+  __shared__ ull s_red[256 / FG_WAVE];
+  __shared__ uint32_t s_max[256 / FG_WAVE];
   BfsCtl* C = P.ctl;
   if (__hip_atomic_load(&C->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   for (int i = threadIdx.x; i < FG_TRACE_MAX; i += blockDim.x) {
@@ -2002,34 +2006,47 @@ __global__ __launch_bounds__(256) void async_finalize_kernel(BfsParams P) {
   const ull* key = (const ull*)P.desc;
   ull reached = 0;
   uint32_t maxd = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < P.n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const ull k = key[v];
-    if (k == ~0ull) {
-      P.depth[v] = -1;
-      if (P.parent) P.parent[v] = -1;
-    } else {
-      const uint32_t d = (uint32_t)(k >> 32);
-      P.depth[v] = (int32_t)d;
-      if (P.parent) P.parent[v] = (int32_t)(uint32_t)k;
-      reached++;
-      maxd = d > maxd ? d : maxd;
-      if (d < FG_TRACE_MAX) {
-        atomicAdd(&s_cnt[d], 1ull);
-        atomicAdd(&s_deg[d], (ull)(P.off[v + 1] - P.off[v]));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // four vertices per round, their keys loaded before any store
+  for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < P.n; v0 += 4 * stride) {
+    ull k[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t v = v0 + r * stride;
+      k[r] = v < P.n ? key[v] : ~0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t v = v0 + r * stride;
+      if (v >= P.n) continue;
+      if (k[r] == ~0ull) {
+        P.depth[v] = -1;
+        if (P.parent) P.parent[v] = -1;
+      } else {
+        const uint32_t d = (uint32_t)(k[r] >> 32);
+        P.depth[v] = (int32_t)d;
+        if (P.parent) P.parent[v] = (int32_t)(uint32_t)k[r];
+        reached++;
+        maxd = d > maxd ? d : maxd;
+        if (d < FG_TRACE_MAX) {
+          atomicAdd(&s_cnt[d], 1ull);
+          atomicAdd(&s_deg[d], (ull)(P.off[v + 1] - P.off[v]));
+        }
       }
     }
   }
-  reached = fg_wave_sum(reached);
+  reached = fg_block_sum<256>(reached, s_red);
   for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
     const uint32_t o = __shfl_xor(maxd, d, FG_WAVE);
     maxd = o > maxd ? o : maxd;
   }
-  if (fg_lane() == 0) {
-    if (reached) atomicAdd(&C->as_reached, reached);
-    atomicMax(&C->as_maxd, maxd);
-  }
+  if (fg_lane() == 0) s_max[threadIdx.x / FG_WAVE] = maxd;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 256 / FG_WAVE; ++i) maxd = s_max[i] > maxd ? s_max[i] : maxd;
+    fin_partials(P)[2 * blockIdx.x] = reached;
+    fin_partials(P)[2 * blockIdx.x + 1] = maxd;
+  }
   for (int i = threadIdx.x; i < FG_TRACE_MAX; i += blockDim.x) {
     if (s_cnt[i]) atomicAdd(&C->as_hist_cnt[i], s_cnt[i]);
     if (s_deg[i]) atomicAdd(&C->as_hist_deg[i], s_deg[i]);
@@ -2038,13 +2055,27 @@ __global__ __launch_bounds__(256) void async_finalize_kernel(BfsParams P) {
 
 // The record of an asynchronous traversal: levels = largest depth + 1, the
 // per-level trace from the level sizes (the entries a level-synchronous
-// push reads: the frontier's degree sum), the entries the team read.
-__global__ void async_stats_kernel(BfsParams P, int32_t team) {
+// push reads: the frontier's degree sum), the entries the team read.  One
+// wave; `parts` = workgroups of the finalize pass.
+__global__ void async_stats_kernel(BfsParams P, int32_t team, int32_t parts) {
   BfsCtl* C = P.ctl;
-  if (threadIdx.x != 0 || blockIdx.x != 0 || !P.stats) return;
+  if (blockIdx.x != 0 || !P.stats) return;
   if (__hip_atomic_load(&C->as_state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  ull reached = 0;
+  uint32_t maxd = 0;
+  for (int i = threadIdx.x; i < parts; i += FG_WAVE) {
+    reached += fin_partials(P)[2 * i];
+    const uint32_t d = (uint32_t)fin_partials(P)[2 * i + 1];
+    maxd = d > maxd ? d : maxd;
+  }
+  reached = fg_wave_sum(reached);
+  for (int d = FG_WAVE / 2; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_xor(maxd, d, FG_WAVE);
+    maxd = o > maxd ? o : maxd;
+  }
+  if (threadIdx.x != 0) return;
   fg_run_stats* st = P.stats;
-  const int32_t L = (int32_t)C->as_maxd + 1;
+  const int32_t L = (int32_t)maxd + 1;
   const int64_t now = (int64_t)wall_clock64();
   for (int32_t k = 0; k < L && k < FG_TRACE_MAX; ++k) {
     st->dir[k] = 0;
@@ -2054,7 +2085,7 @@ __global__ void async_stats_kernel(BfsParams P, int32_t team) {
   }
   st->status = FG_OK;
   st->iterations = L;
-  st->reached = (int64_t)C->as_reached;
+  st->reached = (int64_t)reached;
   st->edges_inspected = (int64_t)C->as_insp;
   st->direction_switches = 0;
   st->grid_blocks = team;
@@ -2301,7 +2332,7 @@ static fg_status bfs_launch(const fg_graph* g, int32_t src, const fg_bfs_opts& o
     void* aargs[] = {&PA};
     FG_HIP_TRY(hipLaunchCooperativeKernel((const void*)bfs_async, dim3(T), dim3(PB), aargs, 0, s));
     async_finalize_kernel<<<fb, 256, 0, s>>>(PA);
-    async_stats_kernel<<<1, 64, 0, s>>>(PA, T);
+    async_stats_kernel<<<1, FG_WAVE, 0, s>>>(PA, T, fb);
     return async_fallback_launch(P, grid, s);
   }
 
@@ -2449,7 +2480,7 @@ extern "C" fg_status fg_bfs_corun(const fg_graph* g, const int32_t* srcs, int32_
                                         : (const void*)bfs_corun<FG_MODE_PUSH>;
   FG_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(PB), args, 0, s));
   async_finalize_kernel<<<fb, 256, 0, s>>>(PB2);
-  async_stats_kernel<<<1, 64, 0, s>>>(PB2, T);
+  async_stats_kernel<<<1, FG_WAVE, 0, s>>>(PB2, T, fb);
   // if the team gave up, the second query runs level-synchronously
   const int grid2 = persistent_grid(o2, pr, persistent_blocks_per_cu<FG_MODE_PUSH>(dev));
   BfsParams PF = bfs_params(g2, src2, o2, lay2, depth2, parent2, stats2, pr, grid2, nullptr, 0, 0);
