@@ -31,26 +31,29 @@ SCALE = 22
 EDGE_FACTOR = 16
 NSRC = 64
 GRID = 4096
-# HBM bytes per launch of each BFS kernel from the two rocprofv3 counter
-# passes (read = 2 x FETCH_SIZE KiB, written = 1 x WRITE_SIZE KiB, factors
-# from a plain 512 MiB device copy; profiles/bfs_persistent_hbm_counters_
-# rmat22x64_grid4096.md).  They hold only for the kernel sources they were
-# taken with: `traffic` is null when these files hash differently.
+# HBM bytes per call of the step (the co-run launch with the grid query's
+# per-vertex kernels) and per launch of each part alone, from the two
+# rocprofv3 counter passes (read = 2 x FETCH_SIZE KiB, written = 1 x
+# WRITE_SIZE KiB, factors from a plain 512 MiB device copy;
+# profiles/bfs_corun_hbm_counters_rmat22x64_grid4096.md).  They hold only for
+# the kernel sources they were taken with: `traffic` is null when these files
+# hash differently.
 TRAFFIC_SOURCES = ('csrc/bfs.hip', 'csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
-TRAFFIC_SHA256 = "b5d1f591569c254ad53f7fd3a72625ebca9b860e1ff84d4d95412ef0918e25a1"
-TRAFFIC_BYTES = {"bfs_persistent<DO,many>": 15690868208, "bfs_async": 2284683456}
+TRAFFIC_SHA256 = "e7539a753726c8788fa18e99d3e57a78f53492cd5e1665448b0cd815f672cae1"
+TRAFFIC_BYTES = {"bfs_corun<DO>": 17631632504, "bfs_persistent<DO,many> (alone)": 15688136232,
+                 "bfs_async (alone)": 2285312303}
 # The same for the side workloads' kernels (per launch; PageRank per
 # iteration), from the same two passes
 # (profiles/side_kernels_hbm_counters.md), each guarded by a hash of the
 # sources its kernel is built from.
 _COMMON = ('csrc/fg_common.h', 'csrc/frontier.h', 'csrc/graph.hip')
 SIDE_TRAFFIC = {
-    "sssp": (('csrc/sssp.hip',) + _COMMON, 12563204255),
-    "c4_rmat23": (('csrc/msbfs.hip',) + _COMMON, 21656966528),
-    "c4_grid2048": (('csrc/msbfs.hip',) + _COMMON, 519138402208),
-    "mssp_rmat22": (('csrc/mssp.hip',) + _COMMON, 144325570432),
-    "mssp_grid2048": (('csrc/mssp.hip',) + _COMMON, 515514752480),
-    "pagerank_iter": (('csrc/pagerank.hip',) + _COMMON, 4348971768),
+    "sssp": (('csrc/sssp.hip',) + _COMMON, 12526998689),
+    "c4_rmat23": (('csrc/msbfs.hip',) + _COMMON, 21703544704),
+    "c4_grid2048": (('csrc/msbfs.hip',) + _COMMON, 519162442858),
+    "mssp_rmat22": (('csrc/mssp.hip',) + _COMMON, 145361529136),
+    "mssp_grid2048": (('csrc/mssp.hip',) + _COMMON, 515993769344),
+    "pagerank_iter": (('csrc/pagerank.hip',) + _COMMON, 4345334762),
 }
 SIDE_TRAFFIC_SHA256 = {
     "sssp": "0c737dc3597a498653df2bc2c3f9d03779fecc203dcf69743c2fda4c247c17f9",
@@ -1146,13 +1149,15 @@ def main():
                                                 traversals=NSRC),
         grid_name + " (alone)": dict(ms=grid_ms, bytes=grid_bytes, launches=1),
     }
-    for k in kernels.values():
+    traffic_ok = _sources_sha(TRAFFIC_SOURCES) == TRAFFIC_SHA256
+    for name, k in kernels.items():
         k["share_ms"] = k["ms"] * k["launches"]
         k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9
         k["frac"] = k["gbs"] / HBM_PEAK_GBS
+        k["traffic"] = TRAFFIC_BYTES.get(name) if traffic_ok else None
     dom = "bfs_corun<DO>"
     dk = kernels[dom]
-    traffic = TRAFFIC_BYTES.get(dom) if _sources_sha(TRAFFIC_SOURCES) == TRAFFIC_SHA256 else None
+    traffic = kernels[dom]["traffic"]
     step_ms = ms_per_step
     value = edges_step / (step_ms * 1e-3) / 1e9
 
