@@ -9,6 +9,9 @@ benchmark times, against the serial oracle on every query.
   read per iteration equal to the oracle's early-exit count.
 * Push BFS on the 4096 x 4096 grid from the centre (the corner is covered
   by the closed-form test of test_gpu_bfs.py).
+* The benchmark step as timed: the 64 R-MAT 22 sources beside the grid
+  query from vertex 0 in one co-run launch, with per-source and with shared
+  outputs.
 * SSSP on R-MAT 22 with weights in [1, 64] from the first 16 sources:
   distances and canonical parents bit-exact against Dijkstra.
 * 64-lane batched BFS on R-MAT 23 and on the 2048 x 2048 grid with the
@@ -138,6 +141,61 @@ def test_c2_grid4096_push_centre_tuned(fg, orc):
         assert st.status == 0 and st.iterations == int(d.max()) + 1
         assert orc.check_bfs(off, col, src, d, to_np(parent)) is None
     g.close()
+
+
+def test_c2_step_corun_as_benchmarked(fg, orc, rmat22):
+    """The benchmark step itself: fg_bfs_corun with the 64 sources and the
+    grid query from vertex 0, the tuned options of both.  Per-source outputs:
+    every traversal's depths, parents and record against the oracle; shared
+    outputs (the benchmark's launch): the last source's outputs; the grid's
+    depths in closed form with a valid parent tree both times."""
+    from paper_1504_04804_amd import autotune
+    off, col, _, g = rmat22
+    opts, kw = autotune.workload_opts("rmat22_dobfs", g)
+    goff, gcol, _ = workloads.graph("grid4096")
+    gg = fg.Graph(goff, gcol, symmetric=True, validate=False)
+    gopts, _ = autotune.workload_opts("grid4096_push", gg)
+    R = 4096
+    want_grid = (np.arange(R, dtype=np.int32)[:, None] + np.arange(R, dtype=np.int32)[None, :])
+    srcs = [int(x) for x in synth.sources(off, 64)]
+    n = g.n
+    srcs_dev = torch.tensor(srcs, dtype=torch.int32, device="cuda")
+    stats = fg.new_stats_many(64)
+    gdepth = torch.empty(gg.n, dtype=torch.int32, device="cuda")
+    gparent = torch.empty(gg.n, dtype=torch.int32, device="cuda")
+    gst = fg.new_stats()
+    for stride in (n, 0):
+        rows = 64 if stride else 1
+        depth = torch.full((rows * n,), -7, dtype=torch.int32, device="cuda")
+        parent = torch.full((rows * n,), -7, dtype=torch.int32, device="cuda")
+        announce(f"config step co-run rmat22 x64 beside grid4096, out_stride={stride}")
+        fg.bfs_corun_into(g, srcs_dev, depth, parent, opts, None, stats, gg, 0, gdepth,
+                          gparent, gopts, stats2=gst, out_stride=stride)
+        torch.cuda.synchronize()
+        sts = fg.read_stats_many(stats, 64)
+        assert all(st.status == 0 for st in sts), [st.status for st in sts]
+        sg = fg.read_stats(gst)
+        assert sg.status == 0 and sg.iterations == 2 * R - 1
+        d2 = to_np(gdepth)
+        assert np.array_equal(d2.reshape(R, R), want_grid)
+        assert orc.check_bfs(goff, gcol, 0, d2, to_np(gparent)) is None
+        d = to_np(depth).reshape(rows, n)
+        p = to_np(parent).reshape(rows, n)
+        if stride:
+            with workloads.pool() as ex:
+                futs = []
+                for j, s in enumerate(srcs):
+                    dirs, front, insp = sts[j].trace()
+                    futs.append(ex.submit(_bfs_oracle_checks, orc, off, col, s, d[j], p[j], dirs,
+                                          front, insp, sts[j].iterations, kw["do_a"], kw["do_b"],
+                                          "do"))
+                bad = [e for e in (f.result() for f in futs) if e is not None]
+            assert not bad, bad[:4]
+        else:
+            assert _bfs_oracle_checks(orc, off, col, srcs[-1], d[0], p[0], *sts[-1].trace(),
+                                      sts[-1].iterations, kw["do_a"], kw["do_b"], "do") is None
+        del depth, parent
+    gg.close()
 
 
 def test_c3a_sssp_rmat22_16_sources(fg, orc, rmat22):
