@@ -1023,6 +1023,9 @@ def main():
     mstats = fg.new_stats_many(NSRC, dev)
     o_do, do_kw = autotune.workload_opts("rmat22_dobfs", g)
     o_push, push_kw = autotune.workload_opts("grid4096_push", gg)
+    # the list's options in the step: the same, with the tuned share of the
+    # workgroups beside the grid query's team
+    o_step, step_kw = autotune.workload_opts("rmat22_dobfs_corun", g)
     stream = torch.cuda.current_stream()
 
     # traversed edges per query (graph + source only), outside the timed region
@@ -1058,7 +1061,7 @@ def main():
         # launch, the grid query on its own team of workgroups (fg_bfs_corun)
         if ev:
             ev[0].record(stream)
-        fg.bfs_corun_into(g, srcs_dev, depth, parent, o_do, ws, mstats, gg, 0, gdepth, gparent,
+        fg.bfs_corun_into(g, srcs_dev, depth, parent, o_step, ws, mstats, gg, 0, gdepth, gparent,
                           o_push, ws2=gws, stats2=stats[NSRC], stream=stream)
         if ev:
             ev[1].record(stream)
@@ -1182,6 +1185,7 @@ def main():
             "rmat_n": n, "rmat_m": int(g.m), "grid_n": ng, "grid_m": int(gg.m),
             "do_a": "%d/%d" % do_kw["do_a"], "do_b": "%d/%d" % do_kw["do_b"],
             "dobfs_options": {k: v for k, v in do_kw.items() if k not in ("do_a", "do_b")},
+            "step_list_workgroups": step_kw.get("grid_blocks", 0) or None,
             "grid_options": {k: v for k, v in push_kw.items() if k not in ("do_a", "do_b")},
             "options_from": "paper_1504_04804_amd/tuned.json (autotuner)", "parents": True,
         },

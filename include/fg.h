@@ -185,6 +185,9 @@ typedef struct {
                              level-synchronous kernel takes over if a
                              member's frontier outgrows its LDS room
                              (0 = level-synchronous; at most 1024)            */
+  int32_t grid_blocks;    /* workgroups of the persistent launch (0 = every CU x
+                             blocks_per_cu); in fg_bfs_corun, of the list's
+                             share (0 = every workgroup the team leaves)     */
 } fg_bfs_opts;
 
 /* Fill *opts with the defaults (DO mode, do_a = 1/100, do_b = 1/10). */

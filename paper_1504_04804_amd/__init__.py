@@ -72,6 +72,7 @@ class BfsOpts(ctypes.Structure):
         ("team_blocks", ctypes.c_int32),
         ("team_edges", ctypes.c_int32),
         ("async_levels", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -273,7 +274,8 @@ def last_error():
 
 
 def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, small_edges=0,
-             big_degree=0, blocks_per_cu=0, team_blocks=0, team_edges=0, async_levels=0):
+             big_degree=0, blocks_per_cu=0, team_blocks=0, team_edges=0, async_levels=0,
+             grid_blocks=0):
     o = BfsOpts()
     lib().fg_bfs_opts_default(ctypes.byref(o))
     o.mode = mode
@@ -286,6 +288,7 @@ def bfs_opts(mode=FG_MODE_DO, do_a=(1, 100), do_b=(1, 10), small_frontier=0, sma
     o.team_blocks = team_blocks
     o.team_edges = team_edges
     o.async_levels = async_levels
+    o.grid_blocks = grid_blocks
     return o
 
 

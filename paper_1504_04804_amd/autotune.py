@@ -4,8 +4,9 @@ Sweeps the direction-optimizing thresholds do_a / do_b (Sec. VI-A: good
 values are consistent within a graph type, e.g. 0.01 / 0.1 for social
 graphs on the paper's GPUs), the high-degree cut of the push load balance,
 the team-mode width, for push BFS the asynchronous team (levels between
-synchronisations, team width), and for batched BFS the push/pull switch
-points.  Every
+synchronisations, team width), for batched BFS the push/pull switch
+points, and for a list of sources run beside an asynchronous query in one
+launch (fg_bfs_corun) the list's share of the workgroups.  Every
 candidate runs on the device on a sample of sources; the fastest mean time
 wins.  Results never change depths (the schedule only affects speed), which
 the test suite checks separately.
@@ -36,6 +37,7 @@ ASYNC = [16, 32, 64, 128, 256]
 ASYNC_TEAM = [32, 48, 64]
 PULL_DIV = [4, 8, 16, 64, 256]
 PUSH_DIV = [64, 512, 4096]
+CORUN_WIDTH = [0, 184, 176, 168, 160, 152, 144, 128]
 
 TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
@@ -144,6 +146,45 @@ def tune_msbfs(g, srcs, log=None, pull_div=None, push_div=None, reps=2):
     return best
 
 
+def tune_corun(g, srcs, list_kw, g2, src2, opts2, log=None, widths=None, reps=2):
+    """The list's workgroups in fg_bfs_corun (grid_blocks; 0 = every one the
+    second query's team leaves): the list of `srcs` on g with the options
+    `list_kw` beside the asynchronous push query from src2 on g2 (opts2).
+    Returns (list_kw with the best grid_blocks, ms per call); each
+    candidate's time is the mean of `reps` calls after one untimed one."""
+    dev = g.off.device
+    depth = torch.empty(g.n, dtype=torch.int32, device=dev)
+    parent = torch.empty(g.n, dtype=torch.int32, device=dev)
+    depth2 = torch.empty(g2.n, dtype=torch.int32, device=dev)
+    parent2 = torch.empty(g2.n, dtype=torch.int32, device=dev)
+    ws = g.workspace(fg.FG_PRIM_BFS)
+    ws2 = g2.workspace(fg.FG_PRIM_BFS)
+    sd = torch.tensor([int(s) for s in srcs], dtype=torch.int32, device=dev)
+    best = None
+    for w in CORUN_WIDTH if widths is None else widths:
+        kw = dict(list_kw, grid_blocks=w)
+        o = fg.bfs_opts(**kw)
+
+        def run():
+            fg.bfs_corun_into(g, sd, depth, parent, o, ws, None, g2, src2, depth2, parent2, opts2,
+                              ws2=ws2)
+        run()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        if log:
+            log(f"corun {kw}: {ms:.3f} ms")
+        if best is None or ms < best[1]:
+            best = (kw, ms)
+    return best
+
+
 def load(path):
     if path and os.path.exists(path):
         with open(path) as f:
@@ -199,7 +240,10 @@ def main():
     grid4096_push (push BFS, 4096 x 4096 grid, vertex 0),
     rmat23_msbfs and grid2048_msbfs (64-lane batches, their 64 sources),
     rmat23_dobfs and grid2048_push (the one-at-a-time paths the batches are
-    compared with: R-MAT 23's 64 sources, the grid's first 4)."""
+    compared with: R-MAT 23's 64 sources, the grid's first 4),
+    rmat22_dobfs_corun (rmat22_dobfs's options and the list's share of the
+    workgroups when the 64 sources run beside the grid4096_push query in
+    one launch; needs those two entries)."""
     ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
@@ -216,6 +260,7 @@ def main():
             ("rmat23_dobfs", lambda: synth.rmat_csr(23, 16), "bfs", fg.FG_MODE_DO, every),
             ("grid2048_push", lambda: synth.grid_csr(2048, 2048), "bfs", fg.FG_MODE_PUSH,
              lambda off: every(off)[:4])]
+    jobs.append(("rmat22_dobfs_corun", lambda: synth.rmat_csr(22, 16), "corun", None, every))
     only = set(sys.argv[1:])
     for name, make, kind, mode, pick in jobs:
         if only and name not in only:
@@ -226,6 +271,14 @@ def main():
         srcs = pick(off)
         if kind == "bfs":
             kw, ms = tune_bfs(g, srcs, mode, log)
+        elif kind == "corun":
+            goff, gcol = synth.grid_csr(4096, 4096)
+            g2 = fg.Graph(goff, gcol, symmetric=True, validate=False)
+            _, list_kw = workload_opts("rmat22_dobfs", g)
+            opts2, _ = workload_opts("grid4096_push", g2)
+            kw, ms = tune_corun(g, srcs, list_kw, g2, 0, opts2, log)
+            g2.close()
+            kind = "bfs"
         else:
             kw, ms = tune_msbfs(g, srcs, log)
         cache[name] = dict(kind=kind, signature=signature(g), kwargs=_to_json(kw),

@@ -1934,9 +1934,10 @@ __global__ __launch_bounds__(PB) void bfs_async(BfsParams P) {
 }
 
 // Two traversals side by side in one launch (fg_bfs_corun): workgroups
-// [0, A.nblk) run A's list of sources as bfs_persistent does, the rest run
-// B's asynchronous push traversal as bfs_async does.  Neither waits for the
-// other; each synchronises only its own range.
+// [0, A.nblk) run A's list of sources as bfs_persistent does, workgroups
+// [B.blk0, B.blk0 + B.nblk) run B's asynchronous push traversal as bfs_async
+// does, any in between leave at once.  Neither range waits for the other;
+// each synchronises only its own workgroups.
 union CorunLds {
   Lds a;
   AsLds b;
@@ -1947,7 +1948,7 @@ __global__ __launch_bounds__(PB) void bfs_corun(BfsParams A, BfsParams B) {
   __shared__ CorunLds L;
   if (blockIdx.x < A.nblk)
     bfs_persistent_run<MODE, true>(A, L.a);
-  else
+  else if (blockIdx.x >= B.blk0)
     bfs_async_run(B, L.b);
 }
 
@@ -2215,12 +2216,14 @@ static fg_status bfs_check(const char* fn, const fg_graph* g, int32_t src, const
 }
 
 // Width of the persistent launch: workgroups per CU as occupancy allows (at
-// most 2 by default; blocks_per_cu lowers it) times the CUs.
+// most 2 by default; blocks_per_cu lowers it) times the CUs, at most
+// grid_blocks when that is set.
 static int persistent_grid(const fg_bfs_opts& o, const fg_device_props& pr, int occ) {
   int bpc = occ;
   if (o.blocks_per_cu > 0 && o.blocks_per_cu < bpc) bpc = o.blocks_per_cu;
   if (o.blocks_per_cu == 0 && bpc > 2) bpc = 2;
-  return pr.cus * bpc;
+  const int grid = pr.cus * bpc;
+  return o.grid_blocks > 0 && o.grid_blocks < grid ? o.grid_blocks : grid;
 }
 
 // Kernel parameters of one traversal (src) or of a list (srcs, nsrc) over
@@ -2461,16 +2464,20 @@ extern "C" fg_status fg_bfs_corun(const fg_graph* g, const int32_t* srcs, int32_
   fg_device_props pr = fg_props(dev);
   if (!pr.coop)
     return fg_set_error(FG_EUNSUPPORTED, "fg_bfs_corun: device lacks cooperative launch");
-  const int grid = persistent_grid(o, pr, o.mode == FG_MODE_DO ? corun_blocks_per_cu<FG_MODE_DO>(dev)
-                                                               : corun_blocks_per_cu<FG_MODE_PUSH>(dev));
+  fg_bfs_opts ow = o;
+  ow.grid_blocks = 0;
+  const int grid = persistent_grid(ow, pr, o.mode == FG_MODE_DO ? corun_blocks_per_cu<FG_MODE_DO>(dev)
+                                                                : corun_blocks_per_cu<FG_MODE_PUSH>(dev));
   const int T = async_team(o2, pr);
   if (grid - T < 1)
     return fg_set_error(FG_EINVAL,
                         "fg_bfs_corun: a team of %d workgroups leaves none of %d for the list", T,
                         grid);
-  // the list on workgroups [0, grid - T), the team on the last T
-  BfsParams PA = bfs_params(g, 0, o, lay, depth, parent, stats, pr, grid - T, srcs, nsrc,
-                            out_stride);
+  // the list on workgroups [0, nA), the team on the last T; workgroups in
+  // between (a list narrowed by grid_blocks, so that it loads the memory
+  // system less while the latency-bound team runs) leave at once
+  const int nA = o.grid_blocks > 0 && o.grid_blocks < grid - T ? o.grid_blocks : grid - T;
+  BfsParams PA = bfs_params(g, 0, o, lay, depth, parent, stats, pr, nA, srcs, nsrc, out_stride);
   BfsParams PB2 = bfs_params(g2, src2, o2, lay2, depth2, parent2, stats2, pr, T, nullptr, 0, 0);
   PB2.blk0 = (uint32_t)(grid - T);
   const int fb = async_fill_blocks(g2);

@@ -6,6 +6,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import synth
 from gpu_util import announce, gpu, need_gpu, to_np
@@ -64,6 +65,42 @@ def test_tune_push_async_small(env, orc):
     g.close()
 
 
+def test_tune_corun_small(env, orc):
+    """The list's share of the workgroups beside an asynchronous query: the
+    winner is one of the candidates, and a co-run with it gives the
+    oracle's depths for every list source and the grid's closed form."""
+    fg, at = env
+    off, col = synth.rmat_csr(14)
+    g = fg.Graph(off, col)
+    goff, gcol = synth.grid_csr(300, 200)
+    g2 = fg.Graph(goff, gcol)
+    srcs = [int(s) for s in synth.sources(off, 8, seed=12)]
+    opts2 = fg.bfs_opts(mode=fg.FG_MODE_PUSH, async_levels=8, team_blocks=16)
+    announce("autotune corun rmat14 x8 beside grid300x200")
+    kw, ms = at.tune_corun(g, srcs, dict(mode=fg.FG_MODE_DO), g2, 0, opts2, print,
+                           widths=[0, 96, 24])
+    assert kw["grid_blocks"] in (0, 96, 24) and ms > 0
+    n = g.n
+    depth = torch.empty(len(srcs) * n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(len(srcs) * n, dtype=torch.int32, device="cuda")
+    d2 = torch.empty(g2.n, dtype=torch.int32, device="cuda")
+    stats = fg.new_stats_many(len(srcs))
+    fg.bfs_corun_into(g, torch.tensor(srcs, dtype=torch.int32, device="cuda"), depth, parent,
+                      fg.bfs_opts(**kw), None, stats, g2, 0, d2, None, opts2, out_stride=n)
+    torch.cuda.synchronize()
+    d = to_np(depth).reshape(len(srcs), n)
+    p = to_np(parent).reshape(len(srcs), n)
+    for j, s in enumerate(srcs):
+        assert np.array_equal(d[j], orc.bfs(off, col, s)[0])
+        assert orc.check_bfs(off, col, s, d[j], p[j]) is None
+    sts = fg.read_stats_many(stats, len(srcs))
+    if kw["grid_blocks"]:
+        assert all(st.grid_blocks == kw["grid_blocks"] for st in sts)
+    assert to_np(d2).tolist() == [r + c for r in range(300) for c in range(200)]
+    g.close()
+    g2.close()
+
+
 def test_tune_msbfs_small(env, orc):
     fg, at = env
     off, col = synth.rmat_csr(13)
@@ -86,7 +123,7 @@ def test_workload_cache_entries(env):
     fg, at = env
     cache = at.load(at.TUNED_PATH)
     for name in ("rmat22_dobfs", "grid4096_push", "rmat23_msbfs", "grid2048_msbfs",
-                 "rmat23_dobfs", "grid2048_push"):
+                 "rmat23_dobfs", "grid2048_push", "rmat22_dobfs_corun"):
         assert name in cache, name
         ent = cache[name]
         assert ent["kind"] in ("bfs", "msbfs") and "signature" in ent and "kwargs" in ent

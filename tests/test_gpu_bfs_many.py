@@ -190,3 +190,28 @@ def test_many_rmat22_benchmark_sources(fg, orc):
     with workloads.pool() as ex:
         list(ex.map(full, range(8)))
     g.close()
+
+
+@pytest.mark.parametrize("blocks", [1, 37, 100])
+def test_many_narrowed_launch(fg, orc, blocks):
+    """grid_blocks narrows the persistent launch (a team wider than it is
+    narrowed too): every traversal's outputs and record as on the full
+    device, and the record names the width."""
+    off, col = synth.rmat_csr(13)
+    g = fg.Graph(off, col)
+    srcs = [int(x) for x in synth.sources(off, 6, seed=14)]
+    for mode in (0, 1):
+        opts = fg.bfs_opts(mode=mode, grid_blocks=blocks)
+        announce(f"bfs_many rmat13 grid_blocks={blocks} mode={mode}")
+        depth, parent, sts = run_many(fg, g, srcs, opts, stride=True)
+        d = to_np(depth).reshape(len(srcs), g.n)
+        p = to_np(parent).reshape(len(srcs), g.n)
+        for j, s in enumerate(srcs):
+            want = check_record(orc, off, col, s, sts[j], mode, (1, 100), (1, 10))
+            assert np.array_equal(d[j], want), (mode, j)
+            assert orc.check_bfs(off, col, s, d[j], p[j]) is None
+            assert sts[j].grid_blocks == blocks
+        dd, pp, st = fg.bfs(g, srcs[0], opts=opts)
+        assert st.status == 0 and st.grid_blocks == blocks
+        assert np.array_equal(to_np(dd), orc.bfs(off, col, srcs[0])[0])
+    g.close()

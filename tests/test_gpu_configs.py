@@ -151,7 +151,7 @@ def test_c2_step_corun_as_benchmarked(fg, orc, rmat22):
     depths in closed form with a valid parent tree both times."""
     from paper_1504_04804_amd import autotune
     off, col, _, g = rmat22
-    opts, kw = autotune.workload_opts("rmat22_dobfs", g)
+    opts, kw = autotune.workload_opts("rmat22_dobfs_corun", g)
     goff, gcol, _ = workloads.graph("grid4096")
     gg = fg.Graph(goff, gcol, symmetric=True, validate=False)
     gopts, _ = autotune.workload_opts("grid4096_push", gg)
