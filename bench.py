@@ -1211,7 +1211,9 @@ def main():
             "grid_span_ms": round(co_grid_ms, 4) if co_grid_ms is not None else None,
             "list_workgroups": recs[0].grid_blocks,
             "note": "sequential = fg_bfs_many then fg_bfs on one stream (measured outside the "
-                    "timed region); spans on the device clock inside the last timed step",
+                    "timed region); spans on the device clock inside the last timed step: the "
+                    "list's from its first start to its last level, the grid query's from its "
+                    "start to its record (written after the launch ends)",
         },
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},

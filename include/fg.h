@@ -239,8 +239,9 @@ fg_status fg_bfs_many(const fg_graph* g, const int32_t* srcs, int32_t nsrc,
  * push query from src2 on g2 exactly as fg_bfs with opts2, which must be
  * FG_MODE_PUSH with async_levels > 1 (else FG_EINVAL).  The second query's
  * asynchronous team (opts2->team_blocks workgroups) takes the launch's
- * last workgroups and the list runs on the others; neither waits for the
- * other.  If the team gives up (a member's frontier outgrows its LDS room),
+ * last workgroups and the list runs on the others (on the first
+ * opts->grid_blocks of them when that is set and smaller; the rest stay
+ * idle); neither waits for the other.  If the team gives up (a member's frontier outgrows its LDS room),
  * the second query runs level-synchronously after the launch, as in
  * fg_bfs.  ws2: workspace of g2 as for fg_bfs; the two workspaces must not
  * overlap (FG_EINVAL) and no other call may use either meanwhile; the two
