@@ -56,25 +56,33 @@ def grid_want(r, c):
     return np.add.outer(np.arange(r), np.arange(c)).astype(np.int32).ravel()
 
 
-@pytest.mark.parametrize("team2", [8, 64])
-def test_list_beside_grid_query(fg, orc, team2):
+@pytest.mark.parametrize("mode,team2,blocks", [(0, 8, 0), (0, 64, 0), (0, 64, 50), (1, 32, 0)])
+def test_list_beside_grid_query(fg, orc, mode, team2, blocks):
+    """The list in either mode, on every workgroup the team leaves or on a
+    narrower share (grid_blocks)."""
     off, col = synth.rmat_csr(14)
     g = fg.Graph(off, col)
     goff, gcol = synth.grid_csr(300, 200)
     g2 = fg.Graph(goff, gcol)
     srcs = [int(x) for x in synth.sources(off, 12, seed=21)]
     da, db = (1, 100), (1, 10)
-    opts = fg.bfs_opts(mode=0, do_a=da, do_b=db)
+    opts = fg.bfs_opts(mode=mode, do_a=da, do_b=db, grid_blocks=blocks)
     opts2 = fg.bfs_opts(mode=fg.FG_MODE_PUSH, async_levels=8, team_blocks=team2)
-    announce(f"bfs_corun rmat14 x{len(srcs)} beside grid300x200 team {team2}")
+    announce(f"bfs_corun rmat14 x{len(srcs)} mode {mode} on {blocks or 'all'} workgroups "
+             f"beside grid300x200 team {team2}")
     depth, parent, sts, d2, p2, st2 = corun(fg, g, srcs, opts, True, g2, 0, opts2)
     d = to_np(depth).reshape(len(srcs), g.n)
     p = to_np(parent).reshape(len(srcs), g.n)
     for j, s in enumerate(srcs):
-        want = check_list_record(orc, off, col, s, sts[j], da, db)
+        if mode == 0:
+            want = check_list_record(orc, off, col, s, sts[j], da, db)
+        else:
+            want, _, cnt, _ = orc.bfs(off, col, s)
+            assert sts[j].status == 0 and sts[j].iterations == len(cnt)
+            assert sts[j].trace()[0] == [0] * min(len(cnt), 64)
         assert np.array_equal(d[j], want), j
         assert orc.check_bfs(off, col, s, d[j], p[j]) is None
-        assert sts[j].grid_blocks <= 256 - team2
+        assert sts[j].grid_blocks == (blocks or 256 - team2)
     assert st2.status == 0 and st2.reached == g2.n
     assert np.array_equal(to_np(d2), grid_want(300, 200))
     assert orc.check_bfs(goff, gcol, 0, to_np(d2), to_np(p2)) is None
