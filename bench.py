@@ -809,12 +809,12 @@ def side_pagerank(fg, torch, stream, off, col, cpu):
     return out
 
 
-SERVE_QPS = (25, 50, 100, 150, 200, 300)
+SERVE_QPS = (25, 50, 100, 150, 200, 250, 300)
 SERVE_SECONDS = 8.0          # arrivals span about this long per load ...
 SERVE_NREQ = (300, 1600)     # ... with at least / at most this many requests
 SERVE_BUDGET = 16 << 30
 SERVE_P99_TARGETS_MS = (250, 500, 1000)
-SERVE_SUSTAIN = 0.95         # a load counts as sustained when achieved >= this x offered
+SERVE_SUSTAIN = 0.95         # a load counts as sustained when achieved >= this x arrived
 
 
 def serving_graphs(fg, cpu_graphs):
@@ -839,10 +839,11 @@ def serving_graphs(fg, cpu_graphs):
 
 def max_sustained_at(sweep, path, target):
     """The highest swept load that `path` sustained (achieved q/s at least
-    SERVE_SUSTAIN x offered) with p99 latency within `target` ms; returns
-    (offered, achieved) or (None, None)."""
+    SERVE_SUSTAIN x the rate at which that replay's requests arrived: a
+    Poisson sample's own rate, not the nominal one) with p99 latency within
+    `target` ms; returns (offered, achieved) or (None, None)."""
     ok = [(row["qps_offered"], row[path]["qps"]) for row in sweep
-          if row[path]["p99_ms"] <= target and row[path]["qps"] >= SERVE_SUSTAIN * row["qps_offered"]]
+          if row[path]["p99_ms"] <= target and row[path]["qps"] >= SERVE_SUSTAIN * row["qps_arrived"]]
     return max(ok) if ok else (None, None)
 
 
@@ -941,7 +942,8 @@ def side_serving(fg, torch, cpu_graphs):
         done2 = serve.serve_fifo(graphs, reqs2, sssp_ws, bfs_ws=bfs_ws, time_limit=300,
                                  keep_results=False)
         fifo = serve.latency_stats(done2)
-        row = {"qps_offered": qps, "requests": nreq,
+        arrived = (nreq - 1) / (reqs[-1].arrival - reqs[0].arrival)
+        row = {"qps_offered": qps, "qps_arrived": round(arrived, 3), "requests": nreq,
                "served": {k: round(v, 3) for k, v in served.items()},
                "fifo": {k: round(v, 3) for k, v in fifo.items()},
                "served_batched_frac": round(nb / len(done), 3),
@@ -978,7 +980,11 @@ def side_serving(fg, torch, cpu_graphs):
                           for (n, k), c in costs.items()},
         "sweep": sweep,
         "max_sustained_qps_at_p99": at,
-        "sustained_rule": f"achieved q/s >= {SERVE_SUSTAIN} x offered and p99 within the target",
+        "sustained_rule": f"achieved q/s >= {SERVE_SUSTAIN} x the replay's arrival rate "
+                          "(qps_arrived) and p99 within the target",
+        "single_query_options": "the same for both paths: direction-optimizing BFS on the R-MAT "
+                                "graphs, the asynchronous push team (64 levels, 64 workgroups) "
+                                "on the grids, SSSP with defaults",
     }
 
 
