@@ -948,6 +948,8 @@ def side_serving(fg, torch, cpu_graphs):
                "fifo": {k: round(v, 3) for k, v in fifo.items()},
                "served_batched_frac": round(nb / len(done), 3),
                "served_steps": srv.counts["steps"], "served_singles": srv.counts["singles"],
+               "served_coruns": srv.counts["coruns"],
+               "served_corun_list_queries": srv.counts["corun_list"],
                "served_evictions": srv.counts["evictions"],
                "hbm_resident_graphs_bytes": srv.resident_bytes,
                "hbm_workspace_peak_bytes": srv.peak_used,

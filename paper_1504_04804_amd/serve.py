@@ -12,11 +12,15 @@ batch or the oldest one runs alone.  Batch and single-run workspaces are
 admitted against an explicit HBM budget: idle batches are closed, least
 recently used first, to make room, and requests wait while nothing fits.
 
-The device runs one traversal at a time (each is a cooperative persistent
-launch over the whole device).  The next unit of work -- a step of a running
-batch, the start of a batch, or a single run -- is the one holding the
-oldest request, and steps are sized from the measured time per iteration so
-the device changes hands every few milliseconds.
+The device runs one unit of work at a time (each is a cooperative
+persistent launch).  The next unit -- a step of a running batch, the start
+of a batch, or a single run -- is the one holding the oldest request, and
+steps are sized from the measured time per iteration so the device changes
+hands every few milliseconds.  A single BFS on a graph of mean degree <= 8
+runs as an asynchronous push team on 64 workgroups; when BFS queries on a
+direction-optimizing graph are waiting outside a batch, the oldest of those
+kinds runs a list of them one after another on the other workgroups of the
+same launch (fg_bfs_corun), as many as take about as long as the team.
 """
 import collections
 import time
@@ -85,6 +89,8 @@ class _Kind:
         self.single_ws = None
         self.single_bytes = 0
         self.single_out = None
+        # a single BFS here runs as an asynchronous push team
+        self.async_single = kind == BFS and single_bfs_opts(g).async_levels > 1
         self.cost = None
         self.it_ms = None  # running estimate of the batch's time per iteration
         self.it_seen = 0   # the batch's iteration count after its last step
@@ -138,6 +144,7 @@ class Server:
         self.finished = []
         self.counts = collections.Counter()
         self.stats = None
+        self.list_stats = None
 
     def close(self):
         """Close every batch and drop the workspaces (waits for the device)."""
@@ -275,6 +282,78 @@ class Server:
             r.result = out
         self.finished.append(r)
 
+    def _corun_partner(self, k):
+        """Among the BFS kinds on direction-optimizing graphs with waiting
+        requests and no running batch, the one holding the oldest request."""
+        best = None
+        for k2 in self.kinds.values():
+            if k2 is k or k2.kind != BFS or k2.async_single or not k2.g.symmetric:
+                continue
+            if not k2.waiting or k2.lane_req:
+                continue
+            if best is None or k2.waiting[0].arrival < best.waiting[0].arrival:
+                best = k2
+        return best
+
+    def _corun(self, k, now_fn):
+        """The oldest request of k (an asynchronous single BFS) with a list of
+        a partner kind's waiting requests beside it in one launch; False if
+        there is no partner."""
+        k2 = self._corun_partner(k)
+        if k2 is None or not self._ensure_single(k2):
+            return False
+        # as many list queries as take about as long as the team
+        nl = int(k.cost.single / max(k2.cost.single, 1e-3)) if k.cost and k2.cost else 8
+        nl = max(1, min(nl, len(k2.waiting), LANES))
+        r = k.waiting.popleft()
+        lst = [k2.waiting.popleft() for _ in range(nl)]
+        t = now_fn()
+        r.start, r.path = t, "single"
+        for q in lst:
+            q.start, q.path = t, "corun"
+        g, g2 = k.g, k2.g
+        dev = g.off.device
+        if self.keep or k.single_out is None:
+            out = torch.empty(g.n, dtype=torch.int32, device=dev)
+            if not self.keep:
+                k.single_out = out
+        else:
+            out = k.single_out
+        if self.keep:
+            lout = torch.empty(nl * g2.n, dtype=torch.int32, device=dev)
+            stride = g2.n
+        else:
+            if k2.single_out is None:
+                k2.single_out = torch.empty(g2.n, dtype=torch.int32, device=dev)
+            lout, stride = k2.single_out, 0
+        if self.stats is None:
+            self.stats = fg.new_stats(dev)
+        if self.list_stats is None:
+            self.list_stats = fg.new_stats_many(LANES, dev)
+        srcs = torch.tensor([q.src for q in lst], dtype=torch.int32, device=dev)
+        fg.bfs_corun_into(g2, srcs, lout, None, single_bfs_opts(g2), k2.single_ws,
+                          self.list_stats, g, r.src, out, None, single_bfs_opts(g),
+                          ws2=k.single_ws, stats2=self.stats, stream=self.stream, out_stride=stride)
+        sts = fg.read_stats_many(self.list_stats, nl, stream=self.stream)
+        st = fg.read_stats(self.stats, stream=self.stream)
+        bad = [(q.src, s_.status) for q, s_ in zip(lst, sts) if s_.status != 0]
+        if st.status != 0 or bad:
+            raise RuntimeError(f"co-run of BFS on {k.name} from {r.src} (status {st.status}) and "
+                               f"{nl} BFS on {k2.name} (failed: {bad})")
+        t = now_fn()
+        r.done = t
+        r.result = out if self.keep else None
+        self.finished.append(r)
+        for j, q in enumerate(lst):
+            q.done = t
+            q.result = lout[j * g2.n:(j + 1) * g2.n] if self.keep else None
+            self.finished.append(q)
+        k2.last_used = time.perf_counter()
+        self.counts["singles"] += 1
+        self.counts["coruns"] += 1
+        self.counts["corun_list"] += nl
+        return True
+
     def tick(self, now_fn):
         """Run the unit of work that holds the oldest request; False when
         there is nothing to run."""
@@ -294,7 +373,8 @@ class Server:
                 self._step(k, now_fn)
                 return True
             if self._ensure_single(k):
-                self._single(k, now_fn)
+                if not (k.async_single and self._corun(k, now_fn)):
+                    self._single(k, now_fn)
                 return True
             # nothing of this kind fits the budget now; try the next one
         raise RuntimeError("no waiting request fits the HBM budget")

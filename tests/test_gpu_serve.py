@@ -66,7 +66,9 @@ def test_served_mix_equals_alone(env, orc, budget, policy, step_ms):
         else:
             assert all(r.path == "batch" for r in done)
     if policy == "single":
-        assert srv.counts["steps"] == 0 and srv.counts["singles"] == len(reqs)
+        # single runs, some of them lists run beside a grid query
+        assert srv.counts["steps"] == 0
+        assert srv.counts["singles"] + srv.counts["corun_list"] == len(reqs)
     st = serve.latency_stats(done)
     assert st["n"] == len(reqs)
     # workspaces stayed within the budget; the graphs' own bytes are counted apart
@@ -137,3 +139,21 @@ def test_served_config_graphs_equal_alone(orc):
     assert not bad, bad[:4]
     for g in graphs.values():
         g.close()
+
+
+def test_grid_singles_co_run_lists(env, orc):
+    """Single runs only, a burst of BFS queries on grids (asynchronous
+    singles) and on R-MAT graphs: the server runs lists of R-MAT queries
+    beside grid queries in one launch, and every result equals the oracle's
+    answer for that query alone."""
+    fg, serve, specs, graphs, csr = env
+    reqs = [r for r in serve.make_requests(specs, 240, qps=50000.0, bfs_frac=1.0, seed=77)]
+    announce("serve 240 BFS requests, single runs, co-run lists beside grid queries")
+    srv = serve.Server(graphs, hbm_budget=32 << 30, policy="single")
+    done = serve.serve_stream(srv, reqs, time_limit=120)
+    assert len(done) == len(reqs)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    assert srv.counts["coruns"] > 0 and srv.counts["corun_list"] >= srv.counts["coruns"]
+    assert sum(1 for r in done if r.path == "corun") == srv.counts["corun_list"]
+    check_results(orc, csr, done, serve)
+    srv.close()
