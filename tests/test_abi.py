@@ -115,3 +115,34 @@ def test_dup_argument_errors_without_gpu(fg):
     assert L.fg_dup_info(None, None) == fg.FG_EINVAL
     assert L.fg_dup_run(None, 0, 0, None, None, None, 0, None) == fg.FG_EINVAL
     assert L.fg_dup_destroy(None) == fg.FG_OK
+
+
+def test_corun_argument_errors_without_gpu(fg):
+    """fg_bfs_corun checks its second query first, then the list, before any
+    device work."""
+    L = fg.lib()
+    o2 = fg.bfs_opts(mode=fg.FG_MODE_PUSH, async_levels=8)
+    rc = L.fg_bfs_corun(None, None, 0, None, None, 0, None, None, 0, None,
+                        None, 0, ctypes.byref(o2), None, 0, None, None, None, None)
+    assert rc == fg.FG_EINVAL
+    assert "fg_bfs_corun" in fg.last_error() and "graph is NULL" in fg.last_error()
+
+
+def test_serving_single_query_options(fg):
+    """Both serving paths run a single BFS with the same options: the
+    asynchronous push team on graphs of mean degree <= 8, direction-optimizing
+    on other undirected graphs, push on directed ones."""
+    from paper_1504_04804_amd import serve
+
+    class G:
+        def __init__(self, n, m, symmetric):
+            self.n, self.m, self.symmetric = n, m, symmetric
+
+    o = serve.single_bfs_opts(G(100, 360, True))
+    assert o.mode == fg.FG_MODE_PUSH and o.async_levels == 64 and o.team_blocks == 64
+    o = serve.single_bfs_opts(G(100, 800, True))
+    assert o.mode == fg.FG_MODE_PUSH and o.async_levels == 64
+    o = serve.single_bfs_opts(G(100, 3000, True))
+    assert o.mode == fg.FG_MODE_DO and o.async_levels == 0
+    o = serve.single_bfs_opts(G(100, 3000, False))
+    assert o.mode == fg.FG_MODE_PUSH and o.async_levels == 0
